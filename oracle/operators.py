@@ -1,0 +1,128 @@
+"""Forward operator A (the paper's H) and its adjoint A^T (the paper's H*).
+
+Test infrastructure only (see ``oracle/__init__``).
+
+Array layouts (C order, x fastest): object x[l, j, i] of shape [Nz, Ny, Nx],
+data d[n, j, i] of shape [Nt, Ny, Nx].  All arithmetic is float64.
+
+Three independent realisations of the same discrete operator:
+
+* ``A_direct`` / ``AT_direct``: eq. 7 written out as a sum over depths of 2D
+  circular convolutions with the real-space kernels h_l, and eq. 11 as the
+  matching sum over time of 2D circular correlations (periodic transverse
+  boundary, so shifts wrap).  Tiny grids only.
+* ``A_dft`` / ``AT_dft``: the three steps of the FFT realisation of
+  Sec. 3.2 (transverse DFT of every depth slice, per-frequency
+  multiply-accumulate over depth, inverse transverse DFT of every time
+  sample) with dense DFT matrices on the full spectrum; the adjoint runs the
+  same steps with conj(H^) and the sum over time.
+* ``A_fft`` / ``AT_fft``: the same with numpy's r2c/c2r FFTs (pocketfft) on
+  the half spectrum, the only form fast enough for long iterations on large
+  grids.
+
+The inner products are the unweighted Euclidean ones of eq. 10, so A^T is the
+plain matrix transpose.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .hlib import dft_matrix
+
+
+# ---------------------------------------------------------------- direct sums
+def A_direct(h: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """d[n, j, i] = sum_l sum_{i',j'} h[l, j-j', i-i', n] x[l, j', i'] (eq. 7)."""
+    nz, ny, nx, nt = h.shape
+    assert x.shape == (nz, ny, nx)
+    d = np.zeros((nt, ny, nx))
+    for b in range(ny):
+        for a in range(nx):
+            xs = np.roll(x, shift=(b, a), axis=(1, 2))        # x[l, j-b, i-a]
+            d += np.tensordot(h[:, b, a, :], xs, axes=([0], [0]))
+    return d
+
+
+def AT_direct(h: np.ndarray, d: np.ndarray) -> np.ndarray:
+    """g[l, j', i'] = sum_n sum_{i,j} h[l, j-j', i-i', n] d[n, j, i] (eq. 11)."""
+    nz, ny, nx, nt = h.shape
+    assert d.shape == (nt, ny, nx)
+    g = np.zeros((nz, ny, nx))
+    for b in range(ny):
+        for a in range(nx):
+            ds = np.roll(d, shift=(-b, -a), axis=(1, 2))      # d[n, j'+b, i'+a]
+            g += np.tensordot(h[:, b, a, :], ds, axes=([1], [0]))
+    return g
+
+
+# ------------------------------------------------------ dense DFT (full grid)
+def A_dft(Hf: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """A by dense DFT matrices.  Hf: H^ on the full grid [Ny, Nx, Nz, Nt]."""
+    ny, nx, nz, nt = Hf.shape
+    Fy, Fx = dft_matrix(ny, -1.0), dft_matrix(nx, -1.0)
+    X = np.einsum("pj,lji,mi->pml", Fy, x, Fx, optimize=True)      # step (i)
+    D = np.einsum("pmln,pml->pmn", Hf, X, optimize=True)            # step (ii)
+    d = np.einsum("jp,pmn,im->nji", Fy.conj(), D, Fx.conj(), optimize=True)  # (iii)
+    d /= nx * ny
+    if np.abs(d.imag).max() > 1e-12 * max(1e-300, np.abs(d.real).max()):
+        raise AssertionError("A_dft output is not real")
+    return d.real
+
+
+def AT_dft(Hf: np.ndarray, d: np.ndarray) -> np.ndarray:
+    """A^T by dense DFT matrices: same steps, conj(H^), sum over time."""
+    ny, nx, nz, nt = Hf.shape
+    Fy, Fx = dft_matrix(ny, -1.0), dft_matrix(nx, -1.0)
+    R = np.einsum("pj,nji,mi->pmn", Fy, d, Fx, optimize=True)
+    G = np.einsum("pmln,pmn->pml", Hf.conj(), R, optimize=True)
+    g = np.einsum("jp,pml,im->lji", Fy.conj(), G, Fx.conj(), optimize=True)
+    g /= nx * ny
+    if np.abs(g.imag).max() > 1e-12 * max(1e-300, np.abs(g.real).max()):
+        raise AssertionError("AT_dft output is not real")
+    return g.real
+
+
+# --------------------------------------------------- pocketfft, half spectrum
+def A_fft(Hh: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """A with r2c/c2r FFTs.  Hh: H^ on the half spectrum [Ny, Nx/2+1, Nz, Nt]."""
+    ny, nh, nz, nt = Hh.shape
+    nx = x.shape[-1]
+    X = np.fft.rfft2(x, axes=(1, 2))                       # [nz, ny, nh]
+    D = np.einsum("pmln,lpm->npm", Hh, X, optimize=True)    # [nt, ny, nh]
+    return np.fft.irfft2(D, s=(ny, nx), axes=(1, 2))
+
+
+def AT_fft(Hh: np.ndarray, d: np.ndarray) -> np.ndarray:
+    """A^T with r2c/c2r FFTs (conj(H^) = H^ up to rounding, kept explicit)."""
+    ny, nh, nz, nt = Hh.shape
+    nx = d.shape[-1]
+    R = np.fft.rfft2(d, axes=(1, 2))                       # [nt, ny, nh]
+    G = np.einsum("pmln,npm->lpm", np.conj(Hh), R, optimize=True)
+    return np.fft.irfft2(G, s=(ny, nx), axes=(1, 2))
+
+
+# ----------------------------------------- single frequencies of large grids
+def dft_at(f: np.ndarray, m_idx, p_idx) -> np.ndarray:
+    """Forward 2D DFT of every slice of f[s, j, i] at the frequencies
+    (m_idx[k], p_idx[k]) by direct sums: returns complex [K, S]."""
+    s, ny, nx = f.shape
+    m_idx = np.asarray(m_idx).ravel()
+    p_idx = np.asarray(p_idx).ravel()
+    ey = np.exp(-2j * np.pi * np.outer(p_idx, np.arange(ny)) / ny)   # [K, ny]
+    ex = np.exp(-2j * np.pi * np.outer(m_idx, np.arange(nx)) / nx)   # [K, nx]
+    out = np.empty((m_idx.size, s), dtype=np.complex128)
+    for k in range(m_idx.size):
+        out[k] = np.einsum("j,sji,i->s", ey[k], f, ex[k], optimize=True)
+    return out
+
+
+def A_at_freqs(Hk: np.ndarray, x: np.ndarray, m_idx, p_idx) -> np.ndarray:
+    """Spectrum of A x at the given frequencies: D^[k, n] = sum_l H^[k,l,n] X^[k,l]."""
+    X = dft_at(x, m_idx, p_idx)                            # [K, nz]
+    return np.einsum("kln,kl->kn", Hk, X)
+
+
+def AT_at_freqs(Hk: np.ndarray, d: np.ndarray, m_idx, p_idx) -> np.ndarray:
+    """Spectrum of A^T d at the given frequencies: G^[k, l] = sum_n H^[k,l,n] R^[k,n]."""
+    R = dft_at(d, m_idx, p_idx)                            # [K, nt]
+    return np.einsum("kln,kn->kl", np.conj(Hk), R)
