@@ -1,0 +1,245 @@
+#!/usr/bin/env python3
+"""Benchmark of the planar photoacoustic operator on one MI355X.
+
+Step = one forward A and one adjoint A^T (the pair every gradient of the
+reconstruction needs, eq. 15) at 256 x 256 x 128 depths x 512 time samples,
+float32, on a seeded synthetic vascular phantom (40 polyline tubes) resident
+in HBM.  Each apply is issued as its three steps through the C ABI
+(spectrum -> contraction -> inverse spectrum; the same kernels pat_apply_A
+launches) so that HIP events around the contraction, the dominant kernel,
+give its duration inside the timed region.
+
+Prints ONE JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "A+Aᵀ applies/s at 256²×128×512, % HBM roofline; served recon p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+BIG = dict(nx=256, ny=256, nz=128, nt=512)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def contraction_bytes(info: dict, nk: int, nz: int, nt: int, adjoint: bool, B: int = 1) -> int:
+    """Algorithmic bytes of one contraction launch: every stored slab once,
+    the input spectrum read once and the output spectrum written once."""
+    slab = info["slab_bytes_AT"] if adjoint else info["slab_bytes_A"]
+    return slab + B * nk * (nz + nt) * 8
+
+
+def time_pairs(op, x, steps, warmup, B=1):
+    """Times `steps` A+A^T pairs built from stage calls; returns
+    (seconds total, mean contraction ms for A, for A^T)."""
+    import torch
+    g = op.geom
+    Sz, St = B * g.nz, B * g.nt
+    Xs = op.spectrum_buffer(Sz)
+    Ds = op.spectrum_buffer(St)
+    y = torch.empty((B,) + op.d_shape if B > 1 else op.d_shape, dtype=torch.float32, device=op.device)
+    gx = torch.empty_like(x)
+
+    def pair(ev=None):
+        op.spectrum(x, Sz, Xs, B_ws=B)
+        if ev: ev[0].record()
+        op.contract(Xs, Ds, adjoint=False, B=B)
+        if ev: ev[1].record()
+        op.inverse_spectrum(Ds, St, y, B_ws=B)
+        op.spectrum(y, St, Ds, B_ws=B)
+        if ev: ev[2].record()
+        op.contract(Ds, Xs, adjoint=True, B=B)
+        if ev: ev[3].record()
+        op.inverse_spectrum(Xs, Sz, gx, B_ws=B)
+
+    for _ in range(warmup):
+        pair()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        pair(evs[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tA = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    tAT = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
+    return t1 - t0, tA, tAT
+
+
+def cpu_baseline(x64: np.ndarray, budget_s: float = 12.0) -> dict:
+    """The FP64 oracle timed on the host on a bounded sample of the workload:
+    the forward and adjoint applies restricted to a subset of transverse
+    frequencies (spectra by direct DFT sums, then the per-frequency
+    contraction), scaled to all nk frequencies."""
+    from oracle import hlib, operators as ops
+    from oracle.geometry import paper_like
+    from paper_2603_28150_amd import inputs
+    g = paper_like(**BIG)
+    nh = g.nx // 2 + 1
+    nk = g.ny * nh
+    rng = np.random.default_rng(7)
+    ks = rng.permutation(nk)
+    r64 = inputs.gaussian_random((g.nt, g.ny, g.nx), seed=8)
+    done, spent = 0, 0.0
+    chunk = 4
+    while spent < budget_s and done < nk:
+        kk = ks[done:done + chunk]
+        m, p = kk % nh, kk // nh
+        Hk = hlib.H_hat(g, m, p)            # library for the sample, outside the timing
+        t0 = time.perf_counter()
+        ops.A_at_freqs(Hk, x64, m, p)
+        ops.AT_at_freqs(Hk, r64, m, p)
+        spent += time.perf_counter() - t0
+        done += len(kk)
+    sec_per_pair = spent / done * nk
+    return {"value": 1.0 / sec_per_pair, "unit": "A+Aᵀ pairs/s", "cores": len(os.sched_getaffinity(0)),
+            "kind": "oracle",
+            "sample": f"oracle forward+adjoint (direct DFT sums + per-frequency contraction, FP64) "
+                      f"on {done} of {nk} transverse frequencies of the 256x256x128x512 operator, "
+                      f"{spent:.1f} s, scaled by {nk}/{done}; library build and inverse DFT not timed",
+            "cpu": platform.processor() or platform.machine()}
+
+
+def profile_traffic(kernel_bytes: int):
+    """HBM traffic of the contraction from committed rocprofv3 PMC summaries, if present."""
+    p = os.path.join(ROOT, "profiles", "contract_fp32_256x256x128x512_traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        with open(p) as f:
+            return json.load(f).get("traffic_bytes_per_launch")
+    except (OSError, ValueError):
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-forms", action="store_true", help="skip the BF16/FP16/batch/FISTA forms")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU; --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2603_28150_amd import inputs
+    from paper_2603_28150_amd.op import Geometry, Operator
+
+    torch.cuda.set_device(0)
+    geom = Geometry.paper_like(**BIG)
+    t0 = time.perf_counter()
+    op = Operator(geom, "f32")
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    info = op.info()
+    log(f"library built in {t_build:.3f} s: {info}")
+    x64 = inputs.vascular_phantom(op.x_shape, seed=1001)
+    x = torch.from_numpy(x64.astype(np.float32)).cuda()
+
+    secs, tA, tAT = time_pairs(op, x, args.steps, args.warmup)
+    ms_step = secs / args.steps * 1e3
+    value = args.steps / secs
+    bA = contraction_bytes(info, op.nk, geom.nz, geom.nt, False)
+    bAT = contraction_bytes(info, op.nk, geom.nz, geom.nt, True)
+    achieved = (bA + bAT) / ((tA + tAT) * 1e-3) / 1e9
+    log(f"A+AT: {ms_step:.3f} ms/pair, contraction A {tA:.3f} ms, AT {tAT:.3f} ms, {achieved:.0f} GB/s")
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "A+Aᵀ pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded vascular phantom, 40 tubes)",
+        "config": {"workload": "planar PAT operator: one A + one A^T, 256x256 transverse, "
+                               "128 depths, 512 time samples, FP32 kernel library, batch 1",
+                   "nx": 256, "ny": 256, "nz": 128, "nt": 512, "batch": 1,
+                   "library_classes": info["nclass"], "library_build_s": t_build},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": profile_traffic(bA),
+                     "kernel": "k_contract (A and A^T, mean of both)",
+                     "algorithmic_bytes_per_launch": (bA + bAT) / 2,
+                     "ms_per_launch": (tA + tAT) / 2},
+    }
+
+    if not args.no_forms:
+        out["forms"] = forms(op, x, x64, args)
+    if not args.no_cpu:
+        log("cpu baseline (oracle sample) ...")
+        out["cpu_baseline"] = cpu_baseline(x64)
+    print(json.dumps(out), flush=True)
+
+
+def forms(op, x, x64, args) -> dict:
+    """Secondary numbers on the same GPU: FISTA, 16-bit library, batch 16."""
+    import torch
+    from paper_2603_28150_amd import inputs
+    from paper_2603_28150_amd.op import Operator
+    res = {}
+    g = op.geom
+    # 100-iteration FISTA with the step from 30 power iterations, 20 dB noise
+    clean = op.apply_A(x)
+    sig = float(torch.sqrt(torch.mean(clean * clean)))
+    noise = torch.from_numpy(inputs.noise_like(op.d_shape, seed=1501).astype(np.float32)).cuda()
+    d = clean + inputs.NOISE_20DB * sig * noise
+    v0 = torch.from_numpy(inputs.gaussian_random(op.x_shape, seed=1002).astype(np.float32)).cuda()
+    t0 = time.perf_counter()
+    L, _ = op.power_norm(v0, 30)
+    t_pow = time.perf_counter() - t0
+    op.recon_fista(d, 2, 1.0 / L)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    op.recon_fista(d, 100, 1.0 / L, 0.0, nonneg=True)
+    torch.cuda.synchronize()
+    t_f = time.perf_counter() - t0
+    res["fista100_fp32_s"] = t_f
+    res["power30_s"] = t_pow
+    log(f"FISTA 100 it: {t_f:.3f} s; power 30 it {t_pow:.3f} s")
+    # 16-bit libraries, batch 1
+    for kind in ("bf16", "f16"):
+        o = Operator(g, kind)
+        inf = o.info()
+        secs, tA, tAT = time_pairs(o, x, max(5, args.steps // 2), 2)
+        b = contraction_bytes(inf, o.nk, g.nz, g.nt, False) + contraction_bytes(inf, o.nk, g.nz, g.nt, True)
+        res[f"{kind}_pairs_per_s"] = max(5, args.steps // 2) / secs
+        res[f"{kind}_contract_GBs"] = b / ((tA + tAT) * 1e-3) / 1e9
+        log(f"{kind}: {res[f'{kind}_pairs_per_s']:.1f} pairs/s, contraction {res[f'{kind}_contract_GBs']:.0f} GB/s")
+        del o
+        torch.cuda.empty_cache()
+    # batch of 16 objects, FP32 and BF16 libraries
+    xb = torch.from_numpy(np.stack([inputs.vascular_phantom(op.x_shape, seed=2001 + b)
+                                    for b in range(16)]).astype(np.float32)).cuda()
+    for kind in ("f32", "bf16"):
+        o = op if kind == "f32" else Operator(g, kind)
+        secs, tA, tAT = time_pairs(o, xb, 3, 1, B=16)
+        res[f"batch16_{kind}_object_pairs_per_s"] = 16 * 3 / secs
+        log(f"batch16 {kind}: {res[f'batch16_{kind}_object_pairs_per_s']:.1f} object-pairs/s")
+        if o is not op:
+            del o
+        torch.cuda.empty_cache()
+    return res
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,216 @@
+// Per-frequency multiply-accumulate of the operator (step (ii) of Sec. 3.2).
+//
+// For every transverse frequency k:
+//   A   :  D^[k, n] = sum_l H^[k, l, n] X^[k, l]          (sum over depth)
+//   A^T :  G^[k, l] = sum_n conj(H^[k, l, n]) R^[k, n]    (sum over time)
+// H^ is real and identical for all frequencies of one symmetry class, so the
+// library keeps one slab per class in two layouts, [l][n] for A and [n][l] for
+// A^T.  Both products then have the same shape: the summed index i runs over
+// slab rows, the kept index j runs along a row, and one workgroup streams one
+// slab exactly once while applying it to every member frequency of the class
+// (up to four).  Streaming the slab is the whole cost (it is >95 % of the bytes
+// an apply moves), so the kernel is built around 16-byte non-temporal loads
+// of whole rows: lanes of a row group cover one row, row groups take
+// interleaved rows, and a short LDS tree adds the row-group partial sums at
+// the end.  Accumulation is float32 for every storage type.
+#include "dft.hpp"
+#include "pat_internal.hpp"
+
+namespace pat {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+
+template <typename HT> struct Slab;
+
+template <> struct Slab<float> {
+  static constexpr int VEC = 4;
+  typedef v4f raw_t;
+  __device__ static __forceinline__ float get(const raw_t& r, int v) { return r[v]; }
+};
+
+struct bf16_t { unsigned short bits; };
+struct f16_t { unsigned short bits; };
+
+template <> struct Slab<bf16_t> {
+  static constexpr int VEC = 8;
+  typedef v4u raw_t;
+  __device__ static __forceinline__ float get(const raw_t& r, int v) {
+    const unsigned w = r[v >> 1];
+    const unsigned b = (v & 1) ? (w & 0xFFFF0000u) : (w << 16);
+    return __uint_as_float(b);
+  }
+};
+
+template <> struct Slab<f16_t> {
+  static constexpr int VEC = 8;
+  typedef v4u raw_t;
+  __device__ static __forceinline__ float get(const raw_t& r, int v) {
+    const unsigned w = r[v >> 1];
+    const unsigned short h = (v & 1) ? (unsigned short)(w >> 16) : (unsigned short)(w & 0xFFFFu);
+    _Float16 x;
+    __builtin_memcpy(&x, &h, 2);
+    return (float)x;
+  }
+};
+
+template <typename HT, int G, int JPT>
+__global__ __launch_bounds__(256) void k_contract(ContractArgs a, int lr_log2) {
+  typedef Slab<HT> SL;
+  typedef typename SL::raw_t raw_t;
+  constexpr int VEC = SL::VEC;
+  constexpr int U = 8 / JPT;               // rows in flight per thread
+  constexpr int NS = JPT * VEC * G * 2;    // accumulators per thread
+  extern __shared__ float4 smem_raw[];
+  float2* xin = reinterpret_cast<float2*>(smem_raw);
+  float* red = reinterpret_cast<float*>(smem_raw);
+
+  const int tid = threadIdx.x;
+  const int c = blockIdx.x, b = blockIdx.y;
+  const int Lr = 1 << lr_log2, R = 256 >> lr_log2;
+  const int lr = tid & (Lr - 1), rg = tid >> lr_log2;
+
+  int kg[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) kg[g] = a.members[c * G + g];
+
+  // member input vectors, [i][g], with the optional per-row scale applied
+  for (int idx = tid; idx < a.ni * G; idx += 256) {
+    const int i = idx / G, g = idx % G;
+    int k = -1;
+#pragma unroll
+    for (int gg = 0; gg < G; ++gg) k = (gg == g) ? kg[gg] : k;
+    float2 v = make_float2(0.f, 0.f);
+    if (k >= 0) {
+      v = a.in[(size_t)k * a.in_rs + (size_t)b * a.ni + i];
+      if (a.in_scale) v = cscale(v, a.in_scale[i]);
+    }
+    xin[idx] = v;
+  }
+  __syncthreads();
+
+  float acc[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) acc[s] = 0.f;
+
+  const HT* slab = reinterpret_cast<const HT*>(a.slab) + (size_t)c * a.slab_elems;
+  const int nchunks = (a.nj + VEC - 1) / VEC;
+  bool cl[JPT];
+  const HT* colp[JPT];
+#pragma unroll
+  for (int jj = 0; jj < JPT; ++jj) {
+    const int ch = lr + jj * Lr;
+    cl[jj] = ch < nchunks;
+    colp[jj] = slab + (size_t)ch * VEC;
+  }
+
+  for (int i0 = rg; i0 < a.ni; i0 += R * U) {
+    raw_t raw[U][JPT];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * R;
+#pragma unroll
+      for (int jj = 0; jj < JPT; ++jj) {
+        if (i < a.ni && cl[jj]) {
+          raw[u][jj] = __builtin_nontemporal_load(
+              reinterpret_cast<const raw_t*>(colp[jj] + (size_t)i * a.s_row));
+        } else {
+          raw[u][jj] = raw_t(0);
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * R;
+      if (i >= a.ni) break;
+      float2 xv[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) xv[g] = xin[i * G + g];
+#pragma unroll
+      for (int jj = 0; jj < JPT; ++jj) {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+          const float h = SL::get(raw[u][jj], v);
+#pragma unroll
+          for (int g = 0; g < G; ++g) {
+            float* p = &acc[((jj * VEC + v) * G + g) * 2];
+            p[0] = fmaf(h, xv[g].x, p[0]);
+            p[1] = fmaf(h, xv[g].y, p[1]);
+          }
+        }
+      }
+    }
+  }
+
+  // add the partial sums of the R row groups (fixed order: deterministic)
+  for (int half = R >> 1; half >= 1; half >>= 1) {
+    __syncthreads();
+    const int span = half * Lr;
+    if (rg >= half && rg < 2 * half) {
+      const int w = (rg - half) * Lr + lr;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) red[s * span + w] = acc[s];
+    }
+    __syncthreads();
+    if (rg < half) {
+      const int w = rg * Lr + lr;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) acc[s] += red[s * span + w];
+    }
+  }
+
+  if (rg == 0) {
+#pragma unroll
+    for (int jj = 0; jj < JPT; ++jj) {
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        const int j = (lr + jj * Lr) * VEC + v;
+        if (j >= a.nj) continue;
+        const float sc = a.out_scale ? a.out_scale[j] : 1.f;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          if (kg[g] < 0) continue;
+          const float* p = &acc[((jj * VEC + v) * G + g) * 2];
+          a.out[(size_t)kg[g] * a.out_rs + (size_t)b * a.nj + j] = make_float2(p[0] * sc, p[1] * sc);
+        }
+      }
+    }
+  }
+}
+
+template <typename HT, int G>
+static pat_status launch_t(const ContractArgs& a, int B, hipStream_t st) {
+  constexpr int VEC = Slab<HT>::VEC;
+  const int nchunks = (a.nj + VEC - 1) / VEC;
+  int lr_log2 = 0;
+  while ((1 << lr_log2) < nchunks && lr_log2 < 8) ++lr_log2;
+  const int Lr = 1 << lr_log2, R = 256 / Lr;
+  const int jpt = (nchunks + Lr - 1) / Lr;
+  if (jpt > 2) return fail(PAT_EUNSUPPORTED, "contraction row longer than 512 vectors");
+  const int ns = jpt * VEC * G * 2;
+  size_t red_bytes = R > 1 ? (size_t)(R / 2) * Lr * ns * sizeof(float) : 0;
+  size_t in_bytes = (size_t)a.ni * G * sizeof(float2);
+  size_t lds = red_bytes > in_bytes ? red_bytes : in_bytes;
+  if (lds > 160 * 1024) return fail(PAT_EUNSUPPORTED, "contraction input vector does not fit in LDS");
+  dim3 grid(a.nclass, B);
+  if (jpt == 1)
+    k_contract<HT, G, 1><<<grid, 256, lds, st>>>(a, lr_log2);
+  else
+    k_contract<HT, G, 2><<<grid, 256, lds, st>>>(a, lr_log2);
+  PAT_LAUNCHED("contraction");
+  return PAT_OK;
+}
+
+pat_status contract(const ContractArgs& a, int hdtype, int G, int B, hipStream_t st) {
+  if (a.nclass == 0 || B == 0) return PAT_OK;
+  if (G == 4) {
+    if (hdtype == PAT_H_F32) return launch_t<float, 4>(a, B, st);
+    if (hdtype == PAT_H_BF16) return launch_t<bf16_t, 4>(a, B, st);
+    return launch_t<f16_t, 4>(a, B, st);
+  }
+  if (hdtype == PAT_H_F32) return launch_t<float, 2>(a, B, st);
+  if (hdtype == PAT_H_BF16) return launch_t<bf16_t, 2>(a, B, st);
+  return launch_t<f16_t, 2>(a, B, st);
+}
+
+}  // namespace pat

@@ -1,0 +1,101 @@
+// Small in-register DFTs (sizes 1, 2, 4, 8, 16) used by the 2D FFT kernels.
+// DIR = -1: forward, exp(-2 pi i n k / R); DIR = +1: inverse (unnormalised).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace pat {
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+
+// multiply by exp(DIR * i pi / 2): -i (forward) or +i (inverse)
+template <int DIR>
+__device__ __forceinline__ float2 rot90(float2 a) {
+  return DIR < 0 ? make_float2(a.y, -a.x) : make_float2(-a.y, a.x);
+}
+
+// exp(DIR * 2 pi i e / 16) for 0 <= e < 16, from exact constants.
+template <int DIR>
+__device__ __forceinline__ float2 w16(int e) {
+  constexpr float c1 = 0.92387953251128675613f;  // cos(pi/8)
+  constexpr float s1 = 0.38268343236508977173f;  // sin(pi/8)
+  constexpr float r2 = 0.70710678118654752440f;  // cos(pi/4)
+  const float cs[16] = {1.f, c1, r2, s1, 0.f, -s1, -r2, -c1, -1.f, -c1, -r2, -s1, 0.f, s1, r2, c1};
+  const float sn[16] = {0.f, s1, r2, c1, 1.f, c1, r2, s1, 0.f, -s1, -r2, -c1, -1.f, -c1, -r2, -s1};
+  return make_float2(cs[e & 15], DIR < 0 ? -sn[e & 15] : sn[e & 15]);
+}
+
+template <int DIR>
+__device__ __forceinline__ void dft2(float2& a, float2& b) {
+  float2 t = a;
+  a = cadd(t, b);
+  b = csub(t, b);
+}
+
+// in place on v[0], v[s], v[2s], v[3s]
+template <int DIR>
+__device__ __forceinline__ void dft4(float2* v, int s) {
+  float2 a0 = cadd(v[0], v[2 * s]), a1 = csub(v[0], v[2 * s]);
+  float2 b0 = cadd(v[s], v[3 * s]), b1 = rot90<DIR>(csub(v[s], v[3 * s]));
+  v[0] = cadd(a0, b0);
+  v[2 * s] = csub(a0, b0);
+  v[s] = cadd(a1, b1);
+  v[3 * s] = csub(a1, b1);
+}
+
+// Full DFT of R points held in v[0..R-1]; natural order in and out.
+template <int R, int DIR>
+__device__ __forceinline__ void dft(float2* v) {
+  if constexpr (R == 1) {
+    return;
+  } else if constexpr (R == 2) {
+    dft2<DIR>(v[0], v[1]);
+  } else if constexpr (R == 4) {
+    dft4<DIR>(v, 1);
+  } else if constexpr (R == 8) {
+    // radix 2 x 4: even/odd halves, then combine with exp(DIR 2 pi i k / 8)
+    float2 e[4] = {v[0], v[2], v[4], v[6]};
+    float2 o[4] = {v[1], v[3], v[5], v[7]};
+    dft4<DIR>(e, 1);
+    dft4<DIR>(o, 1);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      float2 t = cmul(o[k], w16<DIR>(2 * k));
+      v[k] = cadd(e[k], t);
+      v[k + 4] = csub(e[k], t);
+    }
+  } else if constexpr (R == 16) {
+    // four-step 4 x 4: input n = n2 + 4 n1, output k = k1 + 4 k2
+    float2 y[16];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+      float2 t[4] = {v[n2], v[n2 + 4], v[n2 + 8], v[n2 + 12]};
+      dft4<DIR>(t, 1);
+#pragma unroll
+      for (int k1 = 0; k1 < 4; ++k1) y[n2 * 4 + k1] = (n2 * k1 == 0) ? t[k1] : cmul(t[k1], w16<DIR>(n2 * k1));
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      float2 t[4] = {y[k1], y[4 + k1], y[8 + k1], y[12 + k1]};
+      dft4<DIR>(t, 1);
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[k2];
+    }
+  }
+}
+
+// Split of N = N1 * N2 used by the four-step kernels (N1 >= N2).
+template <int N> struct Split;
+template <> struct Split<16> { static constexpr int N1 = 4, N2 = 4; };
+template <> struct Split<32> { static constexpr int N1 = 8, N2 = 4; };
+template <> struct Split<64> { static constexpr int N1 = 8, N2 = 8; };
+template <> struct Split<128> { static constexpr int N1 = 16, N2 = 8; };
+template <> struct Split<256> { static constexpr int N1 = 16, N2 = 16; };
+
+}  // namespace pat

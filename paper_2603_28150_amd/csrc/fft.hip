@@ -1,0 +1,277 @@
+// Batched 2D transverse FFTs for power-of-two sizes 16..256 (gfx950).
+//
+// Step (i) and step (iii) of the FFT realisation of the operator (Sec. 3.2):
+// every depth or time slice is transformed over (x, y).  Each 1D transform
+// is a four-step FFT, N = N1 * N2: every thread does one N1-point DFT in
+// registers, multiplies by the twiddles, and after a single LDS exchange does
+// one N2-point DFT.  Two passes move the data through HBM:
+//   rows:    real rows (x) <-> half spectrum along x, transposed so that the
+//            slice index is fastest, pairs of real rows packed into one
+//            complex transform;
+//   columns: complex transforms along y on the frequency-major layout, slices
+//            fastest, so that loads and stores are contiguous across threads.
+// Twiddles exp(-2 pi i e / 256) are tabulated on the host in float64 and
+// rounded once to float32.
+#include <cmath>
+
+#include "dft.hpp"
+#include "pat_internal.hpp"
+
+namespace pat {
+
+__device__ float2 g_tw256[256];
+
+pat_status fft_init_device() {
+  float2 host[256];
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int e = 0; e < 256; ++e) {
+    double a = two_pi * e / 256.0;
+    host[e] = make_float2((float)std::cos(a), (float)-std::sin(a));
+  }
+  PAT_HIP(hipMemcpyToSymbol(HIP_SYMBOL(g_tw256), host, sizeof(host), 0, hipMemcpyHostToDevice));
+  return PAT_OK;
+}
+
+template <int N, int DIR>
+__device__ __forceinline__ void load_twiddles(float2* tw, int tid, int nthreads) {
+  for (int e = tid; e < N; e += nthreads) {
+    float2 w = g_tw256[e * (256 / N)];
+    tw[e] = DIR < 0 ? w : cconj(w);
+  }
+}
+
+// ------------------------------------------------------------- columns (y)
+// out[(p*nh + m)*rs + s] = sum_j exp(DIR 2 pi i p j / N) in[(j*nh + m)*rs + s]
+template <int N, int DIR>
+__global__ __launch_bounds__(256) void k_fft_cols(const float2* __restrict__ in,
+                                                  float2* __restrict__ out, int nh, int S,
+                                                  int rs) {
+  constexpr int N1 = Split<N>::N1, N2 = Split<N>::N2;
+  constexpr int SB = 16;       // slices per block
+  constexpr int PAD = N + 1;   // LDS stride per slice (complex)
+  constexpr int NT = SB * N1;  // threads
+  __shared__ float2 tw[N];
+  __shared__ float2 ex[SB * PAD];
+  const int tid = threadIdx.x;
+  const int s = tid % SB, t = tid / SB;
+  const int m = blockIdx.x;
+  const int sg = blockIdx.y * SB + s;
+  const bool live = sg < S;
+  load_twiddles<N, DIR>(tw, tid, NT);
+  __syncthreads();
+  if (t < N2) {
+    float2 v[N1];
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) {
+      const int y = t + N2 * n1;
+      v[n1] = live ? in[(size_t)(y * nh + m) * rs + sg] : make_float2(0.f, 0.f);
+    }
+    dft<N1, DIR>(v);
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) ex[s * PAD + t * N1 + k1] = cmul(v[k1], tw[t * k1]);
+  }
+  __syncthreads();
+  float2 v[N2];
+#pragma unroll
+  for (int n2 = 0; n2 < N2; ++n2) v[n2] = ex[s * PAD + n2 * N1 + t];
+  dft<N2, DIR>(v);
+  if (live) {
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) {
+      const int p = t + N1 * k2;
+      out[(size_t)(p * nh + m) * rs + sg] = v[k2];
+    }
+  }
+}
+
+// ---------------------------------------------------------- rows, r2c (x)
+// T[(j*nh + m)*rs + s] = sum_i exp(-2 pi i m i / N) f[s][j][i],  m = 0..N/2
+template <int N>
+__global__ __launch_bounds__(256) void k_fft_rows_r2c(const float* __restrict__ f,
+                                                      float2* __restrict__ T, int ny, int S,
+                                                      int rs) {
+  constexpr int N1 = Split<N>::N1, N2 = Split<N>::N2;
+  constexpr int Q = 16;        // packed complex sequences = 32 real slices
+  constexpr int PAD = N + 1;
+  constexpr int NT = Q * N1;
+  constexpr int NH = N / 2 + 1;
+  __shared__ float2 tw[N];
+  __shared__ float2 ex[Q * PAD];
+  const int tid = threadIdx.x;
+  const int t = tid % N1, q = tid / N1;
+  const int j = blockIdx.x;
+  const int s0 = blockIdx.y * 2 * Q;
+  const int sa = s0 + 2 * q, sb = sa + 1;
+  load_twiddles<N, -1>(tw, tid, NT);
+  __syncthreads();
+  float2 v[N1];
+  if (t < N2) {
+    const float* ra = f + ((size_t)sa * ny + j) * N;
+    const float* rb = f + ((size_t)sb * ny + j) * N;
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) {
+      const int i = t + N2 * n1;
+      v[n1] = make_float2(sa < S ? ra[i] : 0.f, sb < S ? rb[i] : 0.f);
+    }
+    dft<N1, -1>(v);
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) ex[q * PAD + t * N1 + k1] = cmul(v[k1], tw[t * k1]);
+  }
+  __syncthreads();
+  float2 w[N2];
+#pragma unroll
+  for (int n2 = 0; n2 < N2; ++n2) w[n2] = ex[q * PAD + n2 * N1 + t];
+  dft<N2, -1>(w);
+  __syncthreads();
+#pragma unroll
+  for (int k2 = 0; k2 < N2; ++k2) ex[q * PAD + t + N1 * k2] = w[k2];
+  __syncthreads();
+  // separate the two packed real transforms and store slice-fastest
+  for (int idx = tid; idx < NH * 2 * Q; idx += NT) {
+    const int m = idx / (2 * Q), sl = idx % (2 * Q);
+    const int s = s0 + sl;
+    if (s >= S) continue;
+    const int qq = sl >> 1;
+    const float2 zm = ex[qq * PAD + m];
+    const float2 zc = cconj(ex[qq * PAD + ((N - m) & (N - 1))]);
+    float2 r;
+    if ((sl & 1) == 0) {
+      r = make_float2(0.5f * (zm.x + zc.x), 0.5f * (zm.y + zc.y));
+    } else {
+      const float2 d = csub(zm, zc);
+      r = make_float2(0.5f * d.y, -0.5f * d.x);
+    }
+    T[(size_t)(j * NH + m) * rs + s] = r;
+  }
+}
+
+// ---------------------------------------------------------- rows, c2r (x)
+// f[s][j][i] = scale * sum_{m=0}^{N-1} exp(+2 pi i m i / N) F[m] - sub[s][j][i],
+// F Hermitian-extended from m = 0..N/2 (imaginary parts of m = 0, N/2 dropped)
+template <int N>
+__global__ __launch_bounds__(256) void k_fft_rows_c2r(const float2* __restrict__ T,
+                                                      float* __restrict__ f, int ny, int S,
+                                                      int rs, float scale,
+                                                      const float* __restrict__ sub) {
+  constexpr int N1 = Split<N>::N1, N2 = Split<N>::N2;
+  constexpr int Q = 16;
+  constexpr int PAD = N + 1;
+  constexpr int NT = Q * N1;
+  constexpr int NH = N / 2 + 1;
+  constexpr int BUF = (2 * Q * NH > Q * PAD) ? 2 * Q * NH : Q * PAD;
+  __shared__ float2 tw[N];
+  __shared__ float2 buf[BUF];
+  const int tid = threadIdx.x;
+  const int j = blockIdx.x;
+  const int s0 = blockIdx.y * 2 * Q;
+  for (int idx = tid; idx < NH * 2 * Q; idx += NT) {
+    const int m = idx / (2 * Q), sl = idx % (2 * Q);
+    const int s = s0 + sl;
+    float2 F = s < S ? T[(size_t)(j * NH + m) * rs + s] : make_float2(0.f, 0.f);
+    if (m == 0 || m == N / 2) F.y = 0.f;
+    buf[sl * NH + m] = F;
+  }
+  load_twiddles<N, +1>(tw, tid, NT);
+  __syncthreads();
+  const int t = tid % N1, q = tid / N1;
+  float2 v[N1];
+  if (t < N2) {
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) {
+      const int i = t + N2 * n1;
+      float2 fa, fb;
+      if (i <= N / 2) {
+        fa = buf[(2 * q) * NH + i];
+        fb = buf[(2 * q + 1) * NH + i];
+      } else {
+        fa = cconj(buf[(2 * q) * NH + N - i]);
+        fb = cconj(buf[(2 * q + 1) * NH + N - i]);
+      }
+      v[n1] = make_float2(fa.x - fb.y, fa.y + fb.x);  // Fa + i Fb
+    }
+    dft<N1, +1>(v);
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) v[k1] = cmul(v[k1], tw[t * k1]);
+  }
+  __syncthreads();
+  if (t < N2) {
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) buf[q * PAD + t * N1 + k1] = v[k1];
+  }
+  __syncthreads();
+  float2 w[N2];
+#pragma unroll
+  for (int n2 = 0; n2 < N2; ++n2) w[n2] = buf[q * PAD + n2 * N1 + t];
+  dft<N2, +1>(w);
+  const int sa = s0 + 2 * q, sb = sa + 1;
+#pragma unroll
+  for (int k2 = 0; k2 < N2; ++k2) {
+    const int i = t + N1 * k2;
+    if (sa < S) {
+      const size_t o = ((size_t)sa * ny + j) * N + i;
+      f[o] = w[k2].x * scale - (sub ? sub[o] : 0.f);
+    }
+    if (sb < S) {
+      const size_t o = ((size_t)sb * ny + j) * N + i;
+      f[o] = w[k2].y * scale - (sub ? sub[o] : 0.f);
+    }
+  }
+}
+
+// ------------------------------------------------------------- launchers
+template <int N, int DIR>
+static void launch_cols(const float2* in, float2* out, int nh, int S, int rs, hipStream_t st) {
+  dim3 grid(nh, (S + 15) / 16);
+  k_fft_cols<N, DIR><<<grid, 16 * Split<N>::N1, 0, st>>>(in, out, nh, S, rs);
+}
+
+template <int DIR>
+static pat_status cols(const float2* in, float2* out, int ny, int nh, int S, int rs,
+                       hipStream_t st) {
+  switch (ny) {
+    case 16: launch_cols<16, DIR>(in, out, nh, S, rs, st); break;
+    case 32: launch_cols<32, DIR>(in, out, nh, S, rs, st); break;
+    case 64: launch_cols<64, DIR>(in, out, nh, S, rs, st); break;
+    case 128: launch_cols<128, DIR>(in, out, nh, S, rs, st); break;
+    case 256: launch_cols<256, DIR>(in, out, nh, S, rs, st); break;
+    default: return fail(PAT_EUNSUPPORTED, "ny must be a power of two in [16, 256]");
+  }
+  PAT_LAUNCHED("fft columns");
+  return PAT_OK;
+}
+
+pat_status fft2_r2c(const float* f, float2* T, float2* X, int nx, int ny, int S, hipStream_t st) {
+  if (S <= 0) return PAT_OK;
+  const int nh = nx / 2 + 1;
+  dim3 grid(ny, (S + 31) / 32);
+  switch (nx) {
+    case 16: k_fft_rows_r2c<16><<<grid, 16 * Split<16>::N1, 0, st>>>(f, T, ny, S, S); break;
+    case 32: k_fft_rows_r2c<32><<<grid, 16 * Split<32>::N1, 0, st>>>(f, T, ny, S, S); break;
+    case 64: k_fft_rows_r2c<64><<<grid, 16 * Split<64>::N1, 0, st>>>(f, T, ny, S, S); break;
+    case 128: k_fft_rows_r2c<128><<<grid, 16 * Split<128>::N1, 0, st>>>(f, T, ny, S, S); break;
+    case 256: k_fft_rows_r2c<256><<<grid, 16 * Split<256>::N1, 0, st>>>(f, T, ny, S, S); break;
+    default: return fail(PAT_EUNSUPPORTED, "nx must be a power of two in [16, 256]");
+  }
+  PAT_LAUNCHED("fft rows r2c");
+  return cols<-1>(T, X, ny, nh, S, S, st);
+}
+
+pat_status fft2_c2r(const float2* X, float2* T, float* f, int nx, int ny, int S, float scale,
+                    const float* sub, hipStream_t st) {
+  if (S <= 0) return PAT_OK;
+  const int nh = nx / 2 + 1;
+  PAT_TRY(cols<+1>(X, T, ny, nh, S, S, st));
+  dim3 grid(ny, (S + 31) / 32);
+  switch (nx) {
+    case 16: k_fft_rows_c2r<16><<<grid, 16 * Split<16>::N1, 0, st>>>(T, f, ny, S, S, scale, sub); break;
+    case 32: k_fft_rows_c2r<32><<<grid, 16 * Split<32>::N1, 0, st>>>(T, f, ny, S, S, scale, sub); break;
+    case 64: k_fft_rows_c2r<64><<<grid, 16 * Split<64>::N1, 0, st>>>(T, f, ny, S, S, scale, sub); break;
+    case 128: k_fft_rows_c2r<128><<<grid, 16 * Split<128>::N1, 0, st>>>(T, f, ny, S, S, scale, sub); break;
+    case 256: k_fft_rows_c2r<256><<<grid, 16 * Split<256>::N1, 0, st>>>(T, f, ny, S, S, scale, sub); break;
+    default: return fail(PAT_EUNSUPPORTED, "nx must be a power of two in [16, 256]");
+  }
+  PAT_LAUNCHED("fft rows c2r");
+  return PAT_OK;
+}
+
+}  // namespace pat

@@ -1,0 +1,207 @@
+// Kernel library build: the sensor-plane response of a unit point absorber at
+// each depth, in the transverse Fourier domain (the depth-indexed impulse
+// responses of Sec. 2.1, built once and reused by every apply, Sec. 3.2).
+//
+// On the grid that is periodic in x, y and z (z-period nq = nz_sim) the exact
+// semi-discrete solution of the wave equation with zero initial velocity is
+// cos(c t |k|) times the initial spectrum.  Restricted to the sensor plane:
+//
+//   H^[l, n] = (1/nq) sum_{q} cos(n c dt |k(q)|) cos(2 pi q l / nq)
+//            = sum_{q=0}^{floor(nq/2)} w_q/nq cos(n theta_q) cos(2 pi q l / nq),
+//
+// with theta_q = c dt sqrt(kx^2 + ky^2 + kz(q)^2), w_q = 2 for the pairs
+// {q, -q} and 1 for q = 0 and the Nyquist plane; the imaginary parts cancel
+// in pairs, so H^ is real.  Phases reach several hundred radians, so the
+// whole build runs in float64 and rounds once (to float32, then to 16 bits
+// for the reduced-precision forms).
+#include <cmath>
+
+#include "pat_internal.hpp"
+
+namespace pat {
+
+constexpr int kNT = 64;   // time samples per workgroup
+constexpr int kLP = 64;   // depths per pass (4 groups x 16)
+constexpr int kQB = 32;   // q values per LDS chunk
+constexpr int kMaxNq = 4096;
+
+__device__ __forceinline__ int ceil_log2_d(double v) {
+  int e;
+  const double f = frexp(v, &e);  // v = f 2^e, 0.5 <= f < 1
+  return f == 0.5 ? e - 1 : e;
+}
+
+__device__ __forceinline__ double depth_scale(const unsigned long long* amax, int l, int hdtype) {
+  if (hdtype == PAT_H_F32) return 1.0;
+  const double m = __longlong_as_double((long long)amax[l]);
+  if (!(m > 0.0)) return 1.0;
+  const int e = hdtype == PAT_H_BF16 ? 0 : 15;
+  return ldexp(1.0, e - ceil_log2_d(m));
+}
+
+__device__ __forceinline__ unsigned short to_bf16(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+
+__device__ __forceinline__ unsigned short to_f16(float f) {
+  _Float16 h = (_Float16)f;
+  unsigned short b;
+  __builtin_memcpy(&b, &h, 2);
+  return b;
+}
+
+template <int MODE>  // 0: per-depth max |H^| only, 1: write the slabs
+__global__ __launch_bounds__(256) void k_hbuild(HBuildArgs a) {
+  __shared__ double ctab[kMaxNq];
+  __shared__ double P[kQB * kNT];
+  __shared__ float tile[kNT * (kLP + 1)];
+  const int tid = threadIdx.x;
+  const int nl = tid & (kNT - 1), lg = tid >> 6;
+  const int c = blockIdx.y;
+  const int n = blockIdx.x * kNT + nl;
+  const int nq = a.nq;
+  const int Qn = nq / 2 + 1;
+  const double two_pi = 6.283185307179586476925286766559;
+
+  for (int r = tid; r < nq; r += 256) ctab[r] = cos(two_pi * (double)r / (double)nq);
+
+  const int fx = a.cls_freq[2 * c], fy = a.cls_freq[2 * c + 1];
+  const double kx = two_pi * fx / (a.nx * a.dx);
+  const double ky = two_pi * fy / (a.ny * a.dy);
+  const double kperp2 = kx * kx + ky * ky;
+  const double cdt = a.c * a.dt;
+  const double inv_nq = 1.0 / nq;
+
+  for (int l0 = 0; l0 < a.nz; l0 += kLP) {
+    double acc[16];
+    int idx[16], stp[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      acc[u] = 0.0;
+      idx[u] = 0;
+      stp[u] = (l0 + lg + 4 * u) % nq;
+    }
+    for (int q0 = 0; q0 < Qn; q0 += kQB) {
+      __syncthreads();
+      for (int e = tid; e < kQB * kNT; e += 256) {
+        const int qq = e / kNT, nn = e % kNT;
+        const int q = q0 + qq, ng = blockIdx.x * kNT + nn;
+        double v = 0.0;
+        if (q < Qn && ng < a.nt) {
+          const double kz = two_pi * q / (nq * a.dz);
+          const double theta = cdt * sqrt(kperp2 + kz * kz);
+          const double w = (q == 0 || 2 * q == nq) ? 1.0 : 2.0;
+          v = w * inv_nq * cos((double)ng * theta);
+        }
+        P[e] = v;
+      }
+      __syncthreads();
+      const int qe = (Qn - q0) < kQB ? (Qn - q0) : kQB;
+      for (int qq = 0; qq < qe; ++qq) {
+        const double p = P[qq * kNT + nl];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          acc[u] = fma(p, ctab[idx[u]], acc[u]);
+          idx[u] += stp[u];
+          if (idx[u] >= nq) idx[u] -= nq;
+        }
+      }
+    }
+
+    if (MODE == 0) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int l = l0 + lg + 4 * u;
+        double m = (n < a.nt) ? fabs(acc[u]) : 0.0;
+        for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+        if (nl == 0 && l < a.nz)
+          atomicMax(&a.amax[l], (unsigned long long)__double_as_longlong(m));
+      }
+    } else {
+      // [l][n] slab: lanes along n, coalesced
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int ll = lg + 4 * u, l = l0 + ll;
+        float f = 0.f;
+        if (l < a.nz) f = (float)(acc[u] * depth_scale(a.amax, l, a.hdtype));
+        tile[nl * (kLP + 1) + ll] = f;
+        if (l < a.nz && n < a.nt) {
+          const size_t o = ((size_t)c * a.nz + l) * a.sA_row + n;
+          if (a.hdtype == PAT_H_F32) reinterpret_cast<float*>(a.slabA)[o] = f;
+          else if (a.hdtype == PAT_H_BF16) reinterpret_cast<unsigned short*>(a.slabA)[o] = to_bf16(f);
+          else reinterpret_cast<unsigned short*>(a.slabA)[o] = to_f16(f);
+        }
+      }
+      __syncthreads();
+      // [n][l] slab: transpose through LDS so that lanes run along l
+      for (int e = tid; e < kNT * kLP; e += 256) {
+        const int nn = e / kLP, ll = e % kLP;
+        const int ng = blockIdx.x * kNT + nn, l = l0 + ll;
+        if (ng >= a.nt || l >= a.nz) continue;
+        const float f = tile[nn * (kLP + 1) + ll];
+        const size_t o = ((size_t)c * a.nt + ng) * a.sT_row + l;
+        if (a.hdtype == PAT_H_F32) reinterpret_cast<float*>(a.slabT)[o] = f;
+        else if (a.hdtype == PAT_H_BF16) reinterpret_cast<unsigned short*>(a.slabT)[o] = to_bf16(f);
+        else reinterpret_cast<unsigned short*>(a.slabT)[o] = to_f16(f);
+      }
+    }
+  }
+}
+
+__global__ void k_scales(const unsigned long long* amax, float* inv_scale, int nz, int hdtype) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l < nz) inv_scale[l] = (float)(1.0 / depth_scale(amax, l, hdtype));
+}
+
+pat_status hbuild(const HBuildArgs& a, hipStream_t st) {
+  if (a.nq > kMaxNq) return fail(PAT_EUNSUPPORTED, "nz_sim above 4096 is not supported");
+  dim3 grid((a.nt + kNT - 1) / kNT, a.nclass);
+  if (a.hdtype != PAT_H_F32) {
+    k_hbuild<0><<<grid, 256, 0, st>>>(a);
+    PAT_LAUNCHED("H build (max pass)");
+  }
+  k_scales<<<(a.nz + 127) / 128, 128, 0, st>>>(a.amax, a.inv_scale, a.nz, a.hdtype);
+  PAT_LAUNCHED("H build (scales)");
+  k_hbuild<1><<<grid, 256, 0, st>>>(a);
+  PAT_LAUNCHED("H build");
+  return PAT_OK;
+}
+
+// ------------------------------------------------------------ export
+__global__ void k_hexport(const void* slabA, int hdtype, const int32_t* kclass,
+                          const float* inv_scale, int k0, int nz, int nt, int sA_row,
+                          float* out) {
+  const int kk = blockIdx.x;
+  const int c = kclass[k0 + kk];
+  for (int e = threadIdx.x; e < nz * nt; e += blockDim.x) {
+    const int l = e / nt, n = e % nt;
+    const size_t o = ((size_t)c * nz + l) * sA_row + n;
+    float f;
+    if (hdtype == PAT_H_F32) {
+      f = reinterpret_cast<const float*>(slabA)[o];
+    } else {
+      const unsigned short b = reinterpret_cast<const unsigned short*>(slabA)[o];
+      if (hdtype == PAT_H_BF16) {
+        f = __uint_as_float((unsigned)b << 16);
+      } else {
+        _Float16 h;
+        __builtin_memcpy(&h, &b, 2);
+        f = (float)h;
+      }
+    }
+    out[(size_t)kk * nz * nt + e] = f * inv_scale[l];
+  }
+}
+
+pat_status hexport(const void* slabA, int hdtype, const int32_t* kclass, const float* inv_scale,
+                   int k0, int nk, int nz, int nt, int sA_row, float* out, hipStream_t st) {
+  if (nk <= 0) return PAT_OK;
+  k_hexport<<<nk, 256, 0, st>>>(slabA, hdtype, kclass, inv_scale, k0, nz, nt, sA_row, out);
+  PAT_LAUNCHED("H export");
+  return PAT_OK;
+}
+
+}  // namespace pat

@@ -1,0 +1,601 @@
+// C ABI of libpat.so: argument checking, kernel-library layout, workspace
+// layout and the order of launches for each call of include/pat.h.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pat_internal.hpp"
+
+struct pat_ctx {
+  int device;
+};
+
+struct pat_op {
+  pat_ctx* ctx;
+  pat_geometry g;
+  int nq;
+  int nh, nk;
+  int G;        // member slots per class (4: octant fold, 2: quadrant fold)
+  int nclass;
+  int vec;      // storage elements per 16-byte load
+  int sA_row, sT_row;
+  char* hbuf;
+  int32_t* members;   // [nclass][G]
+  int32_t* kclass;    // [nk]
+  int32_t* cls_freq;  // [nclass][2]
+  float* inv_scale;   // [nz]
+  unsigned long long* amax;  // [nz]
+  void* slabA;        // [nclass][nz][sA_row]
+  void* slabT;        // [nclass][nt][sT_row]
+  std::vector<int32_t> h_members, h_kclass, h_cls_freq;
+};
+
+namespace pat {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+pat_status fail(pat_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+pat_status hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return PAT_OK;
+  return fail(PAT_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------- geometry rules
+static bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
+
+static int default_nq(const pat_geometry& g) {
+  const double reach = std::ceil(g.c * g.dt * (double)(g.nt - 1) / g.dz);
+  const long long need = (long long)g.nz + (long long)reach + 1;
+  int nq = 1;
+  while (nq < need) nq <<= 1;
+  return nq;
+}
+
+static pat_status check_geometry(const pat_geometry* g) {
+  if (!g) return fail(PAT_EINVAL, "geometry is null");
+  if (g->nz < 1 || g->nt < 1) return fail(PAT_EINVAL, "nz and nt must be >= 1");
+  if (!(g->dx > 0 && g->dy > 0 && g->dz > 0 && g->dt > 0 && g->c > 0))
+    return fail(PAT_EINVAL, "dx, dy, dz, dt and c must be > 0");
+  if (g->nz_sim != 0 && g->nz_sim < g->nz) return fail(PAT_EINVAL, "nz_sim must be 0 or >= nz");
+  if (g->h_dtype < PAT_H_F32 || g->h_dtype > PAT_H_F16) return fail(PAT_EINVAL, "unknown h_dtype");
+  if (!pow2_in(g->nx, 16, 256) || !pow2_in(g->ny, 16, 256))
+    return fail(PAT_EUNSUPPORTED, "nx and ny must be powers of two in [16, 256]");
+  if (g->nz > 2048 || g->nt > 2048) return fail(PAT_EUNSUPPORTED, "nz and nt must be <= 2048");
+  return PAT_OK;
+}
+
+// -------------------------------------------------------- frequency classes
+// H^ depends on (m, p) only through kx^2 + ky^2.  Classes: (|m~|, |p~|), or
+// the sorted pair when the grid is square with dx == dy.  Members are the
+// half-spectrum indices k = p*nh + m of the class.
+struct Classes {
+  int G = 2;
+  std::vector<int32_t> members, kclass, freq;
+  int n() const { return (int)freq.size() / 2; }
+};
+
+static Classes make_classes(const pat_geometry& g) {
+  Classes C;
+  const int nh = g.nx / 2 + 1, hx = g.nx / 2, hy = g.ny / 2;
+  const bool octant = g.nx == g.ny && g.dx == g.dy;
+  C.G = octant ? 4 : 2;
+  C.kclass.assign((size_t)g.ny * nh, -1);
+  auto add_member = [&](int c, int slot_base, int m, int pa, std::vector<int32_t>& mem) {
+    int slot = slot_base;
+    const int p1 = pa, p2 = (g.ny - pa) % g.ny;
+    mem[(size_t)c * C.G + slot++] = p1 * nh + m;
+    if (p2 != p1) mem[(size_t)c * C.G + slot++] = p2 * nh + m;
+    return slot;
+  };
+  if (octant) {
+    for (int a = 0; a <= hx; ++a)
+      for (int b = a; b <= hx; ++b) {
+        C.freq.push_back(a);
+        C.freq.push_back(b);
+      }
+  } else {
+    for (int m = 0; m <= hx; ++m)
+      for (int pa = 0; pa <= hy; ++pa) {
+        C.freq.push_back(m);
+        C.freq.push_back(pa);
+      }
+  }
+  C.members.assign((size_t)C.n() * C.G, -1);
+  for (int c = 0; c < C.n(); ++c) {
+    const int fa = C.freq[2 * c], fb = C.freq[2 * c + 1];
+    int slot = add_member(c, 0, fa, fb, C.members);
+    if (octant && fa != fb) add_member(c, slot, fb, fa, C.members);
+  }
+  for (int c = 0; c < C.n(); ++c)
+    for (int s = 0; s < C.G; ++s) {
+      const int k = C.members[(size_t)c * C.G + s];
+      if (k >= 0) C.kclass[k] = c;
+    }
+  return C;
+}
+
+struct HLayout {
+  size_t off_members, off_kclass, off_freq, off_inv, off_amax, off_A, off_T, total;
+  int nclass, G, vec, sA_row, sT_row;
+};
+
+static HLayout h_layout(const pat_geometry& g, const Classes& C) {
+  HLayout L;
+  L.nclass = C.n();
+  L.G = C.G;
+  const size_t esz = g.h_dtype == PAT_H_F32 ? 4 : 2;
+  L.vec = (int)(16 / esz);
+  L.sA_row = (int)align_up((size_t)g.nt, (size_t)L.vec);
+  L.sT_row = (int)align_up((size_t)g.nz, (size_t)L.vec);
+  const int nk = g.ny * (g.nx / 2 + 1);
+  size_t o = 0;
+  L.off_members = o; o = align_up(o + (size_t)L.nclass * L.G * 4, 256);
+  L.off_kclass = o;  o = align_up(o + (size_t)nk * 4, 256);
+  L.off_freq = o;    o = align_up(o + (size_t)L.nclass * 8, 256);
+  L.off_inv = o;     o = align_up(o + (size_t)g.nz * 4, 256);
+  L.off_amax = o;    o = align_up(o + (size_t)g.nz * 8, 256);
+  L.off_A = o;       o = align_up(o + (size_t)L.nclass * g.nz * L.sA_row * esz, 256);
+  L.off_T = o;       o = align_up(o + (size_t)L.nclass * g.nt * L.sT_row * esz, 256);
+  L.total = o;
+  return L;
+}
+
+// ------------------------------------------------------------- workspace
+struct Work {
+  float2 *Xs, *Ds, *T;
+  float *V, *U, *Z, *R;
+  double* part64;
+  float* part32;
+  double* s64;   // 8 doubles
+  float* s32;    // 8 floats + trace of the power iteration
+  size_t total;
+};
+constexpr int kMaxPowerIter = 4096;
+
+static Work work_layout(const pat_op* op, int B, char* base) {
+  const pat_geometry& g = op->g;
+  const size_t nxy = (size_t)g.nx * g.ny;
+  const size_t Sz = (size_t)B * g.nz, St = (size_t)B * g.nt;
+  Work w;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    char* p = base ? base + o : nullptr;
+    o = align_up(o + bytes, 256);
+    return p;
+  };
+  w.Xs = (float2*)take((size_t)op->nk * Sz * 8);
+  w.Ds = (float2*)take((size_t)op->nk * St * 8);
+  w.T = (float2*)take((size_t)g.ny * op->nh * std::max(Sz, St) * 8);
+  w.V = (float*)take(Sz * nxy * 4);
+  w.U = (float*)take(Sz * nxy * 4);
+  w.Z = (float*)take(Sz * nxy * 4);
+  w.R = (float*)take(St * nxy * 4);
+  w.part64 = (double*)take(kRedBlocks * 8);
+  w.part32 = (float*)take(kRedBlocks * 4);
+  w.s64 = (double*)take(8 * 8);
+  w.s32 = (float*)take((8 + kMaxPowerIter) * 4);
+  w.total = o;
+  return w;
+}
+
+static bool misaligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) != 0; }
+
+static pat_status check_op_call(pat_op* op, int B, void* ws, size_t ws_bytes, Work* w) {
+  if (!op) return fail(PAT_EINVAL, "operator is null");
+  if (B < 1) return fail(PAT_EINVAL, "batch B must be >= 1");
+  if (!ws || misaligned(ws)) return fail(PAT_EINVAL, "workspace is null or not 16-byte aligned");
+  *w = work_layout(op, B, (char*)ws);
+  if (ws_bytes < w->total)
+    return fail(PAT_EINVAL, "workspace too small: need " + std::to_string(w->total) + " bytes");
+  PAT_HIP(hipSetDevice(op->ctx->device));
+  return PAT_OK;
+}
+
+static pat_status check_ptr(const void* p, const char* name) {
+  if (!p) return fail(PAT_EINVAL, std::string(name) + " is null");
+  if (misaligned(p)) return fail(PAT_EINVAL, std::string(name) + " is not 16-byte aligned");
+  return PAT_OK;
+}
+
+// step (ii): per-frequency contraction of B spectra
+static pat_status run_contract(pat_op* op, bool adjoint, const float2* in, float2* out, int B,
+                               hipStream_t st) {
+  const pat_geometry& g = op->g;
+  ContractArgs a;
+  a.members = op->members;
+  a.in = in;
+  a.out = out;
+  a.nclass = op->nclass;
+  const float* sc = g.h_dtype == PAT_H_F32 ? nullptr : op->inv_scale;
+  if (!adjoint) {
+    a.slab = op->slabA;
+    a.in_scale = sc;
+    a.out_scale = nullptr;
+    a.ni = g.nz;
+    a.nj = g.nt;
+    a.s_row = op->sA_row;
+  } else {
+    a.slab = op->slabT;
+    a.in_scale = nullptr;
+    a.out_scale = sc;
+    a.ni = g.nt;
+    a.nj = g.nz;
+    a.s_row = op->sT_row;
+  }
+  a.slab_elems = (long long)a.ni * a.s_row;
+  a.in_rs = B * a.ni;
+  a.out_rs = B * a.nj;
+  return contract(a, g.h_dtype, op->G, B, st);
+}
+
+// y = A x (- sub), B objects
+static pat_status run_A(pat_op* op, const float* x, float* y, int B, const float* sub, const Work& w,
+                        hipStream_t st) {
+  const pat_geometry& g = op->g;
+  PAT_TRY(fft2_r2c(x, w.T, w.Xs, g.nx, g.ny, B * g.nz, st));
+  PAT_TRY(run_contract(op, false, w.Xs, w.Ds, B, st));
+  return fft2_c2r(w.Ds, w.T, y, g.nx, g.ny, B * g.nt, 1.0f / (float)(g.nx * g.ny), sub, st);
+}
+
+// x = A^T y, B data sets
+static pat_status run_AT(pat_op* op, const float* y, float* x, int B, const Work& w, hipStream_t st) {
+  const pat_geometry& g = op->g;
+  PAT_TRY(fft2_r2c(y, w.T, w.Ds, g.nx, g.ny, B * g.nt, st));
+  PAT_TRY(run_contract(op, true, w.Ds, w.Xs, B, st));
+  return fft2_c2r(w.Xs, w.T, x, g.nx, g.ny, B * g.nz, 1.0f / (float)(g.nx * g.ny), nullptr, st);
+}
+
+}  // namespace pat
+
+using namespace pat;
+
+// =================================================================== ABI
+extern "C" {
+
+const char* pat_status_str(pat_status s) {
+  switch (s) {
+    case PAT_OK: return "PAT_OK";
+    case PAT_EINVAL: return "PAT_EINVAL";
+    case PAT_EUNSUPPORTED: return "PAT_EUNSUPPORTED";
+    case PAT_ENOMEM: return "PAT_ENOMEM";
+    case PAT_EHIP: return "PAT_EHIP";
+    case PAT_ENONFINITE: return "PAT_ENONFINITE";
+  }
+  return "PAT_UNKNOWN";
+}
+
+const char* pat_last_error(void) { return g_last_error.c_str(); }
+
+pat_status pat_ctx_create(int device, pat_ctx** out) {
+  if (!out) return fail(PAT_EINVAL, "out is null");
+  *out = nullptr;
+  int n = 0;
+  PAT_HIP(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) return fail(PAT_EINVAL, "no such HIP device");
+  hipDeviceProp_t prop;
+  PAT_HIP(hipGetDeviceProperties(&prop, device));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(PAT_EUNSUPPORTED, std::string("device is ") + prop.gcnArchName + ", not gfx950");
+  PAT_HIP(hipSetDevice(device));
+  PAT_TRY(fft_init_device());
+  pat_ctx* c = new (std::nothrow) pat_ctx;
+  if (!c) return fail(PAT_ENOMEM, "host allocation failed");
+  c->device = device;
+  *out = c;
+  return PAT_OK;
+}
+
+void pat_ctx_destroy(pat_ctx* ctx) { delete ctx; }
+
+pat_status pat_H_bytes(const pat_geometry* geom, size_t* h_bytes, size_t* scratch_bytes) {
+  PAT_TRY(check_geometry(geom));
+  if (!h_bytes) return fail(PAT_EINVAL, "h_bytes is null");
+  Classes C = make_classes(*geom);
+  *h_bytes = h_layout(*geom, C).total;
+  if (scratch_bytes) *scratch_bytes = 0;
+  return PAT_OK;
+}
+
+pat_status pat_H_build(pat_ctx* ctx, const pat_geometry* geom, void* h_buf, size_t h_bytes,
+                       void* scratch, size_t scratch_bytes, void* stream, pat_op** out) {
+  (void)scratch;
+  (void)scratch_bytes;
+  if (!ctx || !out) return fail(PAT_EINVAL, "ctx or out is null");
+  *out = nullptr;
+  PAT_TRY(check_geometry(geom));
+  PAT_TRY(check_ptr(h_buf, "h_buf"));
+  Classes C = make_classes(*geom);
+  HLayout L = h_layout(*geom, C);
+  if (h_bytes < L.total)
+    return fail(PAT_EINVAL, "h_buf too small: need " + std::to_string(L.total) + " bytes");
+  for (int32_t kc : C.kclass)
+    if (kc < 0) return fail(PAT_EINVAL, "internal: frequency without class");
+  PAT_HIP(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+
+  pat_op* op = new (std::nothrow) pat_op;
+  if (!op) return fail(PAT_ENOMEM, "host allocation failed");
+  op->ctx = ctx;
+  op->g = *geom;
+  op->nq = geom->nz_sim ? geom->nz_sim : default_nq(*geom);
+  op->g.nz_sim = op->nq;
+  op->nh = geom->nx / 2 + 1;
+  op->nk = geom->ny * op->nh;
+  op->G = L.G;
+  op->nclass = L.nclass;
+  op->vec = L.vec;
+  op->sA_row = L.sA_row;
+  op->sT_row = L.sT_row;
+  op->hbuf = (char*)h_buf;
+  op->members = (int32_t*)(op->hbuf + L.off_members);
+  op->kclass = (int32_t*)(op->hbuf + L.off_kclass);
+  op->cls_freq = (int32_t*)(op->hbuf + L.off_freq);
+  op->inv_scale = (float*)(op->hbuf + L.off_inv);
+  op->amax = (unsigned long long*)(op->hbuf + L.off_amax);
+  op->slabA = op->hbuf + L.off_A;
+  op->slabT = op->hbuf + L.off_T;
+  op->h_members = std::move(C.members);
+  op->h_kclass = std::move(C.kclass);
+  op->h_cls_freq = std::move(C.freq);
+
+  auto bail = [&](pat_status s) {
+    delete op;
+    return s;
+  };
+  pat_status s;
+  // zero everything first: slab padding must read as zero
+  if ((s = fill_zero(h_buf, L.total, st)) != PAT_OK) return bail(s);
+  if ((s = hip_check(hipMemcpyAsync(op->members, op->h_members.data(), op->h_members.size() * 4,
+                                    hipMemcpyHostToDevice, st), "upload members")) != PAT_OK)
+    return bail(s);
+  if ((s = hip_check(hipMemcpyAsync(op->kclass, op->h_kclass.data(), op->h_kclass.size() * 4,
+                                    hipMemcpyHostToDevice, st), "upload classes")) != PAT_OK)
+    return bail(s);
+  if ((s = hip_check(hipMemcpyAsync(op->cls_freq, op->h_cls_freq.data(), op->h_cls_freq.size() * 4,
+                                    hipMemcpyHostToDevice, st), "upload frequencies")) != PAT_OK)
+    return bail(s);
+  HBuildArgs a;
+  a.cls_freq = op->cls_freq;
+  a.nclass = op->nclass;
+  a.nx = geom->nx;
+  a.ny = geom->ny;
+  a.nz = geom->nz;
+  a.nt = geom->nt;
+  a.nq = op->nq;
+  a.dx = geom->dx;
+  a.dy = geom->dy;
+  a.dz = geom->dz;
+  a.dt = geom->dt;
+  a.c = geom->c;
+  a.slabA = op->slabA;
+  a.slabT = op->slabT;
+  a.sA_row = op->sA_row;
+  a.sT_row = op->sT_row;
+  a.amax = op->amax;
+  a.inv_scale = op->inv_scale;
+  a.hdtype = geom->h_dtype;
+  if ((s = hbuild(a, st)) != PAT_OK) return bail(s);
+  *out = op;
+  return PAT_OK;
+}
+
+pat_status pat_op_destroy(pat_op* op) {
+  delete op;
+  return PAT_OK;
+}
+
+pat_status pat_H_export(pat_op* op, int32_t k0, int32_t nk, float* out, void* stream) {
+  if (!op) return fail(PAT_EINVAL, "operator is null");
+  if (k0 < 0 || nk < 0 || (long long)k0 + nk > op->nk) return fail(PAT_EINVAL, "frequency range out of bounds");
+  if (nk == 0) return PAT_OK;
+  PAT_TRY(check_ptr(out, "out"));
+  PAT_HIP(hipSetDevice(op->ctx->device));
+  return hexport(op->slabA, op->g.h_dtype, op->kclass, op->inv_scale, k0, nk, op->g.nz, op->g.nt,
+                 op->sA_row, out, (hipStream_t)stream);
+}
+
+pat_status pat_get_info(const pat_op* op, pat_op_info* info) {
+  if (!op || !info) return fail(PAT_EINVAL, "null argument");
+  const size_t esz = op->g.h_dtype == PAT_H_F32 ? 4 : 2;
+  info->nk = op->nk;
+  info->nclass = op->nclass;
+  info->members_max = op->G;
+  info->nz_sim = op->nq;
+  info->slab_bytes_A = (size_t)op->nclass * op->g.nz * op->sA_row * esz;
+  info->slab_bytes_AT = (size_t)op->nclass * op->g.nt * op->sT_row * esz;
+  return PAT_OK;
+}
+
+pat_status pat_workspace_bytes(const pat_op* op, int32_t B, size_t* bytes) {
+  if (!op || !bytes) return fail(PAT_EINVAL, "null argument");
+  if (B < 1) return fail(PAT_EINVAL, "batch B must be >= 1");
+  *bytes = work_layout(op, B, nullptr).total;
+  return PAT_OK;
+}
+
+pat_status pat_apply_A(pat_op* op, const float* x, float* y, int32_t B, void* ws, size_t ws_bytes,
+                       void* stream) {
+  Work w;
+  PAT_TRY(check_op_call(op, B, ws, ws_bytes, &w));
+  PAT_TRY(check_ptr(x, "x"));
+  PAT_TRY(check_ptr(y, "y"));
+  return run_A(op, x, y, B, nullptr, w, (hipStream_t)stream);
+}
+
+pat_status pat_apply_AT(pat_op* op, const float* y, float* x, int32_t B, void* ws, size_t ws_bytes,
+                        void* stream) {
+  Work w;
+  PAT_TRY(check_op_call(op, B, ws, ws_bytes, &w));
+  PAT_TRY(check_ptr(x, "x"));
+  PAT_TRY(check_ptr(y, "y"));
+  return run_AT(op, y, x, B, w, (hipStream_t)stream);
+}
+
+// workspace rows of T (complex) available for S slices
+static pat_status check_stage(pat_op* op, int S, void* ws, size_t ws_bytes, Work* w) {
+  if (!op) return fail(PAT_EINVAL, "operator is null");
+  if (S < 1) return fail(PAT_EINVAL, "S must be >= 1");
+  const int per = std::max(op->g.nz, op->g.nt);
+  const int B = (S + per - 1) / per;
+  return check_op_call(op, B, ws, ws_bytes, w);
+}
+
+pat_status pat_spectrum(pat_op* op, const float* f, float* spec, int32_t S, void* ws,
+                        size_t ws_bytes, void* stream) {
+  Work w;
+  PAT_TRY(check_stage(op, S, ws, ws_bytes, &w));
+  PAT_TRY(check_ptr(f, "f"));
+  PAT_TRY(check_ptr(spec, "spec"));
+  return fft2_r2c(f, w.T, (float2*)spec, op->g.nx, op->g.ny, S, (hipStream_t)stream);
+}
+
+pat_status pat_inverse_spectrum(pat_op* op, const float* spec, float* f, int32_t S, const float* sub,
+                                void* ws, size_t ws_bytes, void* stream) {
+  Work w;
+  PAT_TRY(check_stage(op, S, ws, ws_bytes, &w));
+  PAT_TRY(check_ptr(f, "f"));
+  PAT_TRY(check_ptr(spec, "spec"));
+  if (sub) PAT_TRY(check_ptr(sub, "sub"));
+  return fft2_c2r((const float2*)spec, w.T, f, op->g.nx, op->g.ny, S,
+                  1.0f / (float)(op->g.nx * op->g.ny), sub, (hipStream_t)stream);
+}
+
+pat_status pat_contract(pat_op* op, int32_t adjoint, const float* in, float* out, int32_t B,
+                        void* stream) {
+  if (!op) return fail(PAT_EINVAL, "operator is null");
+  if (B < 1) return fail(PAT_EINVAL, "batch B must be >= 1");
+  PAT_TRY(check_ptr(in, "in"));
+  PAT_TRY(check_ptr(out, "out"));
+  PAT_HIP(hipSetDevice(op->ctx->device));
+  return run_contract(op, adjoint != 0, (const float2*)in, (float2*)out, B, (hipStream_t)stream);
+}
+
+pat_status pat_power_norm(pat_op* op, const float* v0, int32_t niter, double* L_out,
+                          double* L_trace, void* ws, size_t ws_bytes, void* stream) {
+  Work w;
+  PAT_TRY(check_op_call(op, 1, ws, ws_bytes, &w));
+  PAT_TRY(check_ptr(v0, "v0"));
+  if (!L_out) return fail(PAT_EINVAL, "L_out is null");
+  if (niter < 1 || niter > kMaxPowerIter) return fail(PAT_EINVAL, "niter must be in [1, 4096]");
+  hipStream_t st = (hipStream_t)stream;
+  const pat_geometry& g = op->g;
+  const long long n = (long long)g.nz * g.nx * g.ny;
+  float* Ls = w.s32 + 8;
+  PAT_TRY(dot_f32(v0, v0, n, w.part32, w.s32, 1.f, st));
+  PAT_TRY(scale_rsqrt(w.V, v0, n, w.s32, st));
+  for (int i = 0; i < niter; ++i) {
+    PAT_TRY(run_A(op, w.V, w.R, 1, nullptr, w, st));
+    PAT_TRY(run_AT(op, w.R, w.U, 1, w, st));
+    PAT_TRY(dot_f32(w.V, w.U, n, w.part32, Ls + i, 1.f, st));
+    PAT_TRY(dot_f32(w.U, w.U, n, w.part32, w.s32 + 1, 1.f, st));
+    PAT_TRY(scale_rsqrt(w.V, w.U, n, w.s32 + 1, st));
+  }
+  std::vector<float> hL(niter);
+  PAT_HIP(hipMemcpyAsync(hL.data(), Ls, niter * sizeof(float), hipMemcpyDeviceToHost, st));
+  PAT_HIP(hipStreamSynchronize(st));
+  *L_out = hL[niter - 1];
+  if (L_trace)
+    for (int i = 0; i < niter; ++i) L_trace[i] = hL[i];
+  return PAT_OK;
+}
+
+pat_status pat_recon_fista(pat_op* op, const float* d, float* x, int32_t niter, float tau,
+                           float lambda, int32_t nonneg, int32_t momentum, float* trace, void* ws,
+                           size_t ws_bytes, void* stream) {
+  Work w;
+  PAT_TRY(check_op_call(op, 1, ws, ws_bytes, &w));
+  PAT_TRY(check_ptr(d, "d"));
+  PAT_TRY(check_ptr(x, "x"));
+  if (niter < 0) return fail(PAT_EINVAL, "niter must be >= 0");
+  if (!(tau > 0.f) || !(lambda >= 0.f)) return fail(PAT_EINVAL, "tau must be > 0 and lambda >= 0");
+  hipStream_t st = (hipStream_t)stream;
+  const pat_geometry& g = op->g;
+  const long long n = (long long)g.nz * g.nx * g.ny;
+  const long long nd = (long long)g.nt * g.nx * g.ny;
+  PAT_TRY(fill_zero(x, n * 4, st));
+  PAT_TRY(fill_zero(w.Z, n * 4, st));
+  double t = 1.0;
+  FistaBatch p;
+  std::memset(&p, 0, sizeof(p));
+  for (int k = 1; k <= niter; ++k) {
+    PAT_TRY(run_A(op, w.Z, w.R, 1, d, w, st));  // R = A z - d
+    if (trace) PAT_TRY(dot_f32(w.R, w.R, nd, w.part32, trace + (k - 1), 0.5f, st));
+    PAT_TRY(run_AT(op, w.R, w.U, 1, w, st));    // U = A^T (A z - d)
+    double beta = 0.0;
+    if (momentum) {
+      const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
+      beta = (t - 1.0) / tn;
+      t = tn;
+    }
+    p.o[0].tau = tau;
+    p.o[0].thr = tau * lambda;
+    p.o[0].beta = (float)beta;
+    p.o[0].nonneg = nonneg ? 1 : 0;
+    PAT_TRY(fista_update(x, w.Z, w.U, n, 1, p, nullptr, st));
+  }
+  return PAT_OK;
+}
+
+pat_status pat_fista_step(pat_op* op, int32_t B, const float* d, float* x, float* z,
+                          const double* beta, const float* tau, const float* lambda,
+                          const int32_t* nonneg, int32_t* nonfinite, void* ws, size_t ws_bytes,
+                          void* stream) {
+  Work w;
+  PAT_TRY(check_op_call(op, B, ws, ws_bytes, &w));
+  if (B > 32) return fail(PAT_EINVAL, "B must be <= 32");
+  PAT_TRY(check_ptr(d, "d"));
+  PAT_TRY(check_ptr(x, "x"));
+  PAT_TRY(check_ptr(z, "z"));
+  if (!beta || !tau || !lambda || !nonneg) return fail(PAT_EINVAL, "per-object parameters are null");
+  hipStream_t st = (hipStream_t)stream;
+  const pat_geometry& g = op->g;
+  const long long n = (long long)g.nz * g.nx * g.ny;
+  FistaBatch p;
+  std::memset(&p, 0, sizeof(p));
+  for (int b = 0; b < B; ++b) {
+    if (!(tau[b] > 0.f) || !(lambda[b] >= 0.f)) return fail(PAT_EINVAL, "tau must be > 0 and lambda >= 0");
+    p.o[b].tau = tau[b];
+    p.o[b].thr = tau[b] * lambda[b];
+    p.o[b].beta = (float)beta[b];
+    p.o[b].nonneg = nonneg[b] ? 1 : 0;
+  }
+  PAT_TRY(run_A(op, z, w.R, B, d, w, st));
+  PAT_TRY(run_AT(op, w.R, w.U, B, w, st));
+  return fista_update(x, z, w.U, n, B, p, nonfinite, st);
+}
+
+pat_status pat_adjoint_check(pat_op* op, const float* x, const float* y, double* rel_out, void* ws,
+                             size_t ws_bytes, void* stream) {
+  Work w;
+  PAT_TRY(check_op_call(op, 1, ws, ws_bytes, &w));
+  PAT_TRY(check_ptr(x, "x"));
+  PAT_TRY(check_ptr(y, "y"));
+  if (!rel_out) return fail(PAT_EINVAL, "rel_out is null");
+  hipStream_t st = (hipStream_t)stream;
+  const pat_geometry& g = op->g;
+  const long long n = (long long)g.nz * g.nx * g.ny;
+  const long long nd = (long long)g.nt * g.nx * g.ny;
+  PAT_TRY(run_A(op, x, w.R, 1, nullptr, w, st));
+  PAT_TRY(run_AT(op, y, w.U, 1, w, st));
+  PAT_TRY(dot_f64(w.R, y, nd, w.part64, w.s64 + 0, st));
+  PAT_TRY(dot_f64(x, w.U, n, w.part64, w.s64 + 1, st));
+  PAT_TRY(dot_f64(w.R, w.R, nd, w.part64, w.s64 + 2, st));
+  PAT_TRY(dot_f64(y, y, nd, w.part64, w.s64 + 3, st));
+  double h[4];
+  PAT_HIP(hipMemcpyAsync(h, w.s64, sizeof(h), hipMemcpyDeviceToHost, st));
+  PAT_HIP(hipStreamSynchronize(st));
+  *rel_out = std::fabs(h[0] - h[1]) / std::sqrt(h[2] * h[3]);
+  return PAT_OK;
+}
+
+}  // extern "C"

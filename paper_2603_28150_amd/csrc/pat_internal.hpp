@@ -1,0 +1,101 @@
+// Internal declarations shared by the translation units of libpat.so.
+// Not part of the ABI (see include/pat.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/pat.h"
+
+namespace pat {
+
+// ------------------------------------------------------------------ errors
+void set_error(const std::string& msg);
+pat_status fail(pat_status s, const std::string& msg);
+pat_status hip_check(hipError_t e, const char* what);
+#define PAT_TRY(expr)                       \
+  do {                                      \
+    pat_status _s = (expr);                 \
+    if (_s != PAT_OK) return _s;            \
+  } while (0)
+#define PAT_HIP(expr) PAT_TRY(::pat::hip_check((expr), #expr))
+// After a launch: reports launch-configuration errors.
+#define PAT_LAUNCHED(what) PAT_TRY(::pat::hip_check(hipGetLastError(), what))
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// --------------------------------------------------------------- 2D FFTs
+// Slice layouts (S slices, element type float / float2):
+//   real slices      f[s][ny][nx]
+//   half spectrum    X[(p*nh + m) * rs + s]   (frequency-major, slice fastest;
+//                    nh = nx/2 + 1; rs = row stride in complex elements)
+//   row-transformed  T[(j*nh + m) * rs + s]   (same shape, y not yet transformed)
+// Forward transforms are unnormalised; the inverse multiplies by `scale`.
+pat_status fft_init_device();  // uploads the twiddle table to the current device
+pat_status fft2_r2c(const float* f, float2* T, float2* X, int nx, int ny, int S,
+                    hipStream_t st);
+// f = scale * c2r(X) - sub (sub may be null; same layout as f)
+pat_status fft2_c2r(const float2* X, float2* T, float* f, int nx, int ny, int S,
+                    float scale, const float* sub, hipStream_t st);
+
+// ------------------------------------------------------ contraction (VALU)
+// out[k_g][obj*nj + j] = sum_i slab_c[i][j] * in[k_g][obj*ni + i] (* scales)
+// for every class c and its members k_g (g < G, -1 = none).
+struct ContractArgs {
+  const void* slab;        // [C][ni][s_row] of the storage type
+  const int32_t* members;  // [C][G]
+  const float2* in;        // [nk][in_rs]
+  float2* out;             // [nk][out_rs]
+  const float* in_scale;   // [ni] or null
+  const float* out_scale;  // [nj] or null
+  int ni, nj, s_row;
+  long long slab_elems;    // ni * s_row
+  int in_rs, out_rs;
+  int nclass;
+};
+pat_status contract(const ContractArgs& a, int hdtype, int G, int B, hipStream_t st);
+
+// ------------------------------------------------------------- H^ build
+struct HBuildArgs {
+  const int32_t* cls_freq;  // [C][2]: |m~|, |p~| (x and y frequency indices)
+  int nclass, nx, ny, nz, nt, nq;
+  double dx, dy, dz, dt, c;
+  void* slabA;              // [C][nz][sA_row]  (n fastest)
+  void* slabT;              // [C][nt][sT_row]  (l fastest)
+  int sA_row, sT_row;
+  unsigned long long* amax; // [nz] bit patterns of max |H^| per depth
+  float* inv_scale;         // [nz] 1/s_l
+  int hdtype;
+};
+pat_status hbuild(const HBuildArgs& a, hipStream_t st);
+pat_status hexport(const void* slabA, int hdtype, const int32_t* kclass, const float* inv_scale,
+                   int k0, int nk, int nz, int nt, int sA_row, float* out, hipStream_t st);
+
+// ------------------------------------------------------- vector kernels
+pat_status fill_zero(void* p, size_t bytes, hipStream_t st);
+// partial sums of a*b (or a*a when b == a) over n floats into part[nblk]; float or double accumulation
+pat_status dot_f32(const float* a, const float* b, long long n, float* part, float* result,
+                   float post_scale, hipStream_t st);
+pat_status dot_f64(const float* a, const float* b, long long n, double* part, double* result,
+                   hipStream_t st);
+// dst = src / sqrt(*nrm2)
+pat_status scale_rsqrt(float* dst, const float* src, long long n, const float* nrm2, hipStream_t st);
+
+struct FistaObj {
+  float tau, thr, beta;
+  int nonneg;
+};
+struct FistaBatch {
+  FistaObj o[32];
+};
+// per object b: x_old = x; x = prox(z - tau g); z = x + beta (x - x_old)
+pat_status fista_update(float* x, float* z, const float* g, long long n_per_obj, int B,
+                        const FistaBatch& p, int32_t* nonfinite, hipStream_t st);
+
+constexpr int kRedBlocks = 512;
+
+}  // namespace pat

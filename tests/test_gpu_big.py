@@ -1,0 +1,60 @@
+"""GPU parity at the full 256^2 x 128 x 512 operator (the benchmark workload),
+checked where the oracle can afford it: the kernel library and the output
+spectra at sampled transverse frequencies (direct DFT sums, float64), plus
+the adjoint identity with float64 dot products on the GPU."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import hlib, operators as ops
+from oracle.geometry import Geometry as OGeom
+from paper_2603_28150_amd import inputs
+from paper_2603_28150_amd.op import Geometry, Operator
+
+pytestmark = pytest.mark.gpu
+
+BIG = Geometry.paper_like(256, 256, 128, 512)
+# (m, p): DC, axes, Nyquist corners, a class with four members and random ones
+M = np.array([0, 128, 0, 128, 3, 7, 100, 41, 129 - 1, 17])
+P = np.array([0, 0, 128, 128, 250, 3, 9, 200, 77, 17])
+
+
+@pytest.fixture(scope="module")
+def big():
+    op = Operator(BIG)
+    o = OGeom(BIG.nx, BIG.ny, BIG.nz, BIG.nt, BIG.dx, BIG.dy, BIG.dz, BIG.dt, BIG.c)
+    Hk = hlib.H_hat(o, M, P)
+    return op, Hk
+
+
+def test_big_kernel_library_at_sampled_frequencies(big):
+    op, Hk = big
+    nh = BIG.nx // 2 + 1
+    for i, (m, p) in enumerate(zip(M, P)):
+        Hg = op.export_H(int(p * nh + m), 1)[0].cpu().numpy().astype(np.float64)
+        assert np.abs(Hg - Hk[i]).max() <= 1e-7 * np.abs(Hk[i]).max()
+
+
+def test_big_forward_and_adjoint_spectra(big):
+    op, Hk = big
+    x = inputs.gaussian_random((BIG.nz, BIG.ny, BIG.nx), seed=90)
+    y = op.apply_A(torch.from_numpy(x.astype(np.float32)).cuda())
+    Dg = ops.dft_at(y.cpu().numpy().astype(np.float64), M, P)       # [K, nt]
+    Do = ops.A_at_freqs(Hk, x, M, P)
+    scale = np.linalg.norm(Do) / np.sqrt(len(M))
+    for i in range(len(M)):
+        assert np.linalg.norm(Dg[i] - Do[i]) < 1e-5 * scale, (M[i], P[i])
+    r = inputs.gaussian_random((BIG.nt, BIG.ny, BIG.nx), seed=91)
+    g = op.apply_AT(torch.from_numpy(r.astype(np.float32)).cuda())
+    Gg = ops.dft_at(g.cpu().numpy().astype(np.float64), M, P)
+    Go = ops.AT_at_freqs(Hk, r, M, P)
+    scale = np.linalg.norm(Go) / np.sqrt(len(M))
+    for i in range(len(M)):
+        assert np.linalg.norm(Gg[i] - Go[i]) < 1e-5 * scale, (M[i], P[i])
+
+
+def test_big_adjoint_identity(big):
+    op, _ = big
+    x = torch.from_numpy(inputs.gaussian_random((BIG.nz, BIG.ny, BIG.nx), seed=92).astype(np.float32)).cuda()
+    y = torch.from_numpy(inputs.gaussian_random((BIG.nt, BIG.ny, BIG.nx), seed=93).astype(np.float32)).cuda()
+    assert op.adjoint_check(x, y) < 1e-5

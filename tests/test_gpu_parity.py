@@ -1,0 +1,258 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Bars (relative l2 unless stated): kernel library 1e-7 (float32 storage),
+A, A^T and every FISTA iterate 1e-5 (float32 arithmetic), 16-bit library
+5e-3 against the exact oracle and 2e-5 against the oracle applying the same
+quantised library.  The adjoint check uses float64 dot products on the GPU.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import hlib, operators as ops, quant, solvers
+from oracle.geometry import Geometry as OGeom
+from paper_2603_28150_amd import _lib, inputs
+from paper_2603_28150_amd.op import Geometry, Operator
+
+pytestmark = pytest.mark.gpu
+
+TINY = Geometry.paper_like(32, 32, 16, 64)                       # octant fold
+RAGGED = Geometry(32, 16, 13, 37, 1e-4, 1.3e-4, 1e-4, 2e-8, 1500.0)  # quadrant fold, ragged
+MID = Geometry.paper_like(64, 64, 40, 130)                       # several tiles per row
+GEOMS = {"tiny": TINY, "ragged": RAGGED, "mid": MID}
+
+
+def og(g: Geometry) -> OGeom:
+    return OGeom(g.nx, g.ny, g.nz, g.nt, g.dx, g.dy, g.dz, g.dt, g.c, g.nz_sim)
+
+
+def dev(a) -> torch.Tensor:
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def host(t: torch.Tensor) -> np.ndarray:
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+_cache = {}
+
+
+def setup(name, h_dtype="f32"):
+    key = (name, h_dtype)
+    if key not in _cache:
+        g = GEOMS[name]
+        Hh = hlib.H_half(og(g))
+        _cache[key] = (g, Operator(g, h_dtype), Hh)
+    return _cache[key]
+
+
+@pytest.mark.parametrize("name", list(GEOMS))
+def test_kernel_library_matches_oracle(name):
+    g, op, Hh = setup(name)
+    Hg = host(op.export_H())
+    Ho = Hh.reshape(op.nk, g.nz, g.nt)
+    assert np.abs(Hg - Ho).max() <= 1e-7 * np.abs(Ho).max()
+    assert rel(Hg, Ho) < 1e-7
+
+
+@pytest.mark.parametrize("name", list(GEOMS))
+def test_forward_matches_oracle(name):
+    g, op, Hh = setup(name)
+    x = inputs.gaussian_blobs((g.nz, g.ny, g.nx), seed=21)
+    y = host(op.apply_A(dev(x)))
+    assert rel(y, ops.A_fft(Hh, x)) < 1e-5
+    xr = inputs.gaussian_random((g.nz, g.ny, g.nx), seed=22)
+    assert rel(host(op.apply_A(dev(xr))), ops.A_fft(Hh, xr)) < 1e-5
+
+
+@pytest.mark.parametrize("name", list(GEOMS))
+def test_adjoint_matches_oracle(name):
+    g, op, Hh = setup(name)
+    y = inputs.gaussian_random((g.nt, g.ny, g.nx), seed=23)
+    assert rel(host(op.apply_AT(dev(y))), ops.AT_fft(Hh, y)) < 1e-5
+
+
+@pytest.mark.parametrize("name", list(GEOMS))
+def test_adjoint_identity_on_gpu(name):
+    g, op, Hh = setup(name)
+    x = dev(inputs.gaussian_random((g.nz, g.ny, g.nx), seed=24))
+    y = dev(inputs.gaussian_random((g.nt, g.ny, g.nx), seed=25))
+    assert op.adjoint_check(x, y) < 1e-5
+
+
+def test_direct_sum_form_on_tiny_grid():
+    # the GPU agrees with eq. 7 written as circular convolution sums too
+    g = Geometry.paper_like(16, 16, 6, 20)
+    op = Operator(g)
+    o = og(g)
+    h = hlib.h_space(o)
+    x = inputs.gaussian_random((g.nz, g.ny, g.nx), seed=26)
+    assert rel(host(op.apply_A(dev(x))), ops.A_direct(h, x)) < 1e-5
+    y = inputs.gaussian_random((g.nt, g.ny, g.nx), seed=27)
+    assert rel(host(op.apply_AT(dev(y))), ops.AT_direct(h, y)) < 1e-5
+
+
+def test_batch_matches_single_and_is_repeatable():
+    g, op, Hh = setup("ragged")
+    xs = np.stack([inputs.gaussian_random((g.nz, g.ny, g.nx), seed=30 + b) for b in range(3)])
+    yb = op.apply_A(dev(xs))
+    yb2 = op.apply_A(dev(xs))
+    assert torch.equal(yb, yb2)                      # same stream, same bits: no races
+    for b in range(3):
+        assert rel(host(yb[b]), ops.A_fft(Hh, xs[b])) < 1e-5
+        assert rel(host(yb[b]), host(op.apply_A(dev(xs[b])))) < 1e-6
+    ds = np.stack([inputs.gaussian_random((g.nt, g.ny, g.nx), seed=40 + b) for b in range(3)])
+    gb = op.apply_AT(dev(ds))
+    for b in range(3):
+        assert rel(host(gb[b]), ops.AT_fft(Hh, ds[b])) < 1e-5
+
+
+@pytest.mark.parametrize("shape", [(16, 16, 1, 1), (16, 16, 1, 7), (16, 32, 3, 1), (256, 16, 2, 3)])
+def test_degenerate_sizes(shape):
+    nx, ny, nz, nt = shape
+    g = Geometry(nx, ny, nz, nt, 1e-4, 1e-4, 1e-4, 2e-8, 1500.0)
+    op = Operator(g)
+    Hh = hlib.H_half(og(g))
+    x = inputs.gaussian_random((nz, ny, nx), seed=50)
+    y = host(op.apply_A(dev(x)))
+    assert rel(y, ops.A_fft(Hh, x)) < 1e-5
+    # t = 0 sees only the sensor-plane slice
+    assert np.abs(y[0] - x[0]).max() < 1e-5 * np.abs(x).max()
+    d = inputs.gaussian_random((nt, ny, nx), seed=51)
+    assert rel(host(op.apply_AT(dev(d))), ops.AT_fft(Hh, d)) < 1e-5
+
+
+def test_invalid_arguments_raise():
+    g, op, Hh = setup("tiny")
+    x = dev(np.zeros((g.nz, g.ny, g.nx)))
+    y = torch.empty((g.nt, g.ny, g.nx), device="cuda")
+    ws = op.workspace(1)
+    L = _lib.load()
+    assert L.pat_apply_A(op.handle, x.data_ptr(), y.data_ptr(), 0, ws.data_ptr(), ws.numel(), None) == -1
+    assert L.pat_apply_A(op.handle, x.data_ptr(), y.data_ptr(), 1, ws.data_ptr(), 16, None) == -1
+    assert L.pat_apply_A(op.handle, x.data_ptr() + 4, y.data_ptr(), 1, ws.data_ptr(), ws.numel(), None) == -1
+    with pytest.raises(_lib.PatError):
+        Operator(Geometry(48, 32, 4, 4, 1e-4, 1e-4, 1e-4, 2e-8, 1500.0))
+
+
+def test_power_iteration_matches_oracle():
+    g, op, Hh = setup("tiny")
+    v0 = inputs.gaussian_random((g.nz, g.ny, g.nx), seed=1002)
+    L, trace = op.power_norm(dev(v0), 30)
+    Lo = solvers.power_iteration(lambda v: ops.A_fft(Hh, v), lambda v: ops.AT_fft(Hh, v), v0, 30)
+    assert np.max(np.abs(np.array(trace) - Lo) / np.array(Lo)) < 1e-5
+    assert L == trace[-1]
+    assert L <= solvers.norm_exact(Hh) * (1 + 1e-5)
+
+
+def _problem(name, seed_obj=0, seed_noise=1, nu=inputs.NOISE_1PCT):
+    g, op, Hh = setup(name)
+    p0 = inputs.gaussian_blobs((g.nz, g.ny, g.nx), seed=seed_obj)
+    clean = ops.A_fft(Hh, p0)
+    d = clean + nu * np.sqrt(np.mean(clean ** 2)) * inputs.noise_like(clean.shape, seed=seed_noise)
+    return g, op, Hh, d
+
+
+def test_fista_every_iterate_matches_oracle():
+    # the tiny workload: 4 blobs, 1 % noise, 20 iterations with non-negativity
+    g, op, Hh, d = _problem("tiny")
+    A = lambda v: ops.A_fft(Hh, v)
+    AT = lambda v: ops.AT_fft(Hh, v)
+    tau = 1.0 / solvers.power_iteration(A, AT, inputs.gaussian_random((g.nz, g.ny, g.nx), seed=1002), 30)[-1]
+    tau = float(np.float32(tau))
+    K = 20
+    xs = solvers.fista(A, AT, d, (g.nz, g.ny, g.nx), K, tau, 0.0, nonneg=True)
+    # GPU trajectory one step at a time through the batched step entry point
+    dd = dev(d)[None]
+    x = torch.zeros((1, g.nz, g.ny, g.nx), device="cuda")
+    z = torch.zeros_like(x)
+    betas = solvers.momentum_weights(K)
+    for k in range(K):
+        op.fista_step(dd, x, z, [betas[k]], [tau], [0.0], [True])
+        assert rel(host(x[0]), xs[k]) < 1e-5, k
+        assert host(x[0]).min() >= 0.0
+    # the whole-loop entry point takes exactly the same steps
+    xf, tr = op.recon_fista(dev(d), K, tau, 0.0, nonneg=True, momentum=True, trace=True)
+    assert torch.equal(xf, x[0])
+    # trace: 1/2 ||A z_k - d||^2 at the gradient point of step k
+    zs = [np.zeros_like(xs[0])]
+    for k in range(1, K):
+        zs.append(xs[k - 1] + betas[k - 1] * (xs[k - 1] - (xs[k - 2] if k >= 2 else 0.0)))
+    fo = np.array([0.5 * np.sum((A(z_) - d) ** 2) for z_ in zs])
+    assert np.max(np.abs(host(tr) - fo) / fo) < 1e-5
+
+
+def test_fista_teacher_forced_step():
+    # one oracle step from the GPU's own state lands on the GPU's next iterate
+    g, op, Hh, d = _problem("ragged", nu=inputs.NOISE_20DB)
+    A = lambda v: ops.A_fft(Hh, v)
+    AT = lambda v: ops.AT_fft(Hh, v)
+    tau = float(np.float32(0.9 / solvers.norm_exact(Hh)))
+    dd = dev(d)[None]
+    x = torch.zeros((1, g.nz, g.ny, g.nx), device="cuda")
+    z = torch.zeros_like(x)
+    betas = solvers.momentum_weights(12)
+    for k in range(12):
+        xp, zp = host(x[0]), host(z[0])
+        op.fista_step(dd, x, z, [betas[k]], [tau], [1e-3], [True])
+        xo = solvers.fista(A, AT, d, xp.shape, 1, tau, 1e-3, nonneg=True, z0=zp, x_prev0=xp, k0=k)[0]
+        assert rel(host(x[0]), xo) < 1e-5, k
+
+
+def test_projected_gradient_soft_threshold():
+    g, op, Hh, d = _problem("mid", seed_obj=5, seed_noise=6)
+    A = lambda v: ops.A_fft(Hh, v)
+    AT = lambda v: ops.AT_fft(Hh, v)
+    tau = float(np.float32(1.0 / solvers.norm_exact(Hh)))
+    xs = solvers.fista(A, AT, d, (g.nz, g.ny, g.nx), 8, tau, 0.01, nonneg=False, momentum=False)
+    xg = op.recon_fista(dev(d), 8, tau, 0.01, nonneg=False, momentum=False)
+    assert rel(host(xg), xs[-1]) < 1e-5
+
+
+def test_batched_fista_step_isolates_objects():
+    # three problems with different tau/lambda/nonneg in one batched step equal
+    # the same problems stepped alone
+    g, op, Hh = setup("tiny")
+    ds = np.stack([_problem("tiny", seed_obj=60 + b, seed_noise=70 + b)[3] for b in range(3)])
+    taus = [0.3, 0.5, 0.7]
+    lams = [0.0, 0.01, 0.0]
+    nn = [True, False, True]
+    xb = torch.zeros((3, g.nz, g.ny, g.nx), device="cuda")
+    zb = torch.zeros_like(xb)
+    bad = torch.zeros(3, dtype=torch.int32, device="cuda")
+    for k in range(4):
+        op.fista_step(dev(ds), xb, zb, [0.1 * k] * 3, taus, lams, nn, nonfinite=bad)
+    for b in range(3):
+        x1 = torch.zeros((1, g.nz, g.ny, g.nx), device="cuda")
+        z1 = torch.zeros_like(x1)
+        for k in range(4):
+            op.fista_step(dev(ds[b])[None], x1, z1, [0.1 * k], [taus[b]], [lams[b]], [nn[b]])
+        assert rel(host(xb[b]), host(x1[0])) < 1e-6
+    assert int(bad.sum()) == 0
+
+
+@pytest.mark.parametrize("kind", ["bf16", "f16"])
+def test_quantised_library(kind):
+    g = TINY
+    op = Operator(g, kind)
+    Hh = setup("tiny")[2]
+    Hq, s = quant.quantise(Hh, kind)
+    Hg = host(op.export_H()).reshape(Hh.shape)
+    # identical up to rare last-place differences of the 16-bit format
+    ulp = 2.0 ** -8 if kind == "bf16" else 2.0 ** -11
+    diff = np.abs(Hg - Hq)
+    assert np.mean(diff > 0) < 1e-3
+    assert np.all(diff <= ulp * np.abs(Hq) * 1.01 + 1e-30)
+    x = inputs.gaussian_blobs((g.nz, g.ny, g.nx), seed=80)
+    y = host(op.apply_A(dev(x)))
+    assert rel(y, ops.A_fft(Hq, x)) < 2e-5
+    assert rel(y, ops.A_fft(Hh, x)) < 5e-3
+    d = inputs.gaussian_random((g.nt, g.ny, g.nx), seed=81)
+    gq = host(op.apply_AT(dev(d)))
+    assert rel(gq, ops.AT_fft(Hq, d)) < 2e-5
+    assert rel(gq, ops.AT_fft(Hh, d)) < 5e-3
+    assert op.adjoint_check(dev(x), dev(d)) < 1e-5
