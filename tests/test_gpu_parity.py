@@ -245,8 +245,13 @@ def test_quantised_library(kind):
     # identical up to rare last-place differences of the 16-bit format
     ulp = 2.0 ** -8 if kind == "bf16" else 2.0 ** -11
     diff = np.abs(Hg - Hq)
-    assert np.mean(diff > 0) < 1e-3
-    assert np.all(diff <= ulp * np.abs(Hq) * 1.01 + 1e-30)
+    # entries whose exact value is 0 (e.g. t = 0 off the sensor plane) hold
+    # float64 rounding noise on both sides: compare those absolutely
+    top = np.abs(Hq).max()
+    big = np.abs(Hq) > 1e-12 * top
+    assert np.all(diff[~big] <= 1e-12 * top)
+    assert np.mean(diff[big] > 0) < 1e-3
+    assert np.all(diff[big] <= ulp * np.abs(Hq[big]) * 1.01)
     x = inputs.gaussian_blobs((g.nz, g.ny, g.nx), seed=80)
     y = host(op.apply_A(dev(x)))
     assert rel(y, ops.A_fft(Hq, x)) < 2e-5
