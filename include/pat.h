@@ -123,8 +123,13 @@ pat_status pat_H_export(pat_op* op, int32_t k0, int32_t nk, float* out, void* st
 typedef struct {
   int32_t nk, nclass, members_max, nz_sim;
   size_t slab_bytes_A, slab_bytes_AT;
+  int32_t spec_rows; /* rows of a spectrum array (see pat_spectrum), = nclass * members_max */
 } pat_op_info;
 pat_status pat_get_info(const pat_op* op, pat_op_info* info);
+
+/* Frequency of every spectrum row: host array k_of_row[spec_rows]; -1 marks
+ * rows no frequency maps to.  Host only. */
+pat_status pat_spectrum_rows(const pat_op* op, int32_t* k_of_row);
 
 /* Workspace bytes every call below needs for a batch of B objects. */
 pat_status pat_workspace_bytes(const pat_op* op, int32_t B, size_t* bytes);
@@ -141,10 +146,13 @@ pat_status pat_apply_AT(pat_op* op, const float* y, float* x, int32_t B,
 
 /* The three steps of an apply (Sec. 3.2), for callers that work in the
  * transverse Fourier domain.  Spectra are complex64 (interleaved re, im
- * float pairs), frequency-major over the r2c half spectrum:
- *     spec[k][s],  k = p*(nx/2+1) + m  (nk = ny*(nx/2+1) rows),
- * with s = b*n + i the slice index (n = nz for object spectra, nt for data
- * spectra).  pat_apply_A is pat_spectrum(x, B*nz) -> pat_contract(0) ->
+ * float pairs), one row per r2c half-spectrum frequency, slice index fastest:
+ *     spec[r][s],  r = 0 .. spec_rows-1,  s = b*n + i
+ * (n = nz for object spectra, nt for data spectra).  Rows are ordered by
+ * symmetry class, members of a class adjacent, so that the contraction
+ * streams contiguous rows; row r holds frequency k = k_of_row[r] from
+ * pat_spectrum_rows (k = p*(nx/2+1) + m; -1 marks an unused row, whose
+ * content is undefined).  pat_apply_A is pat_spectrum(x, B*nz) -> pat_contract(0) ->
  * pat_inverse_spectrum(B*nt), and pat_apply_AT the same with nz and nt
  * swapped and pat_contract(1); the calls launch the same kernels.
  *

@@ -15,7 +15,8 @@ LIB_PATH = os.path.join(_HERE, "libpat.so")
 class OpInfo(C.Structure):
     """pat_op_info."""
     _fields_ = [("nk", C.c_int32), ("nclass", C.c_int32), ("members_max", C.c_int32),
-                ("nz_sim", C.c_int32), ("slab_bytes_A", C.c_size_t), ("slab_bytes_AT", C.c_size_t)]
+                ("nz_sim", C.c_int32), ("slab_bytes_A", C.c_size_t), ("slab_bytes_AT", C.c_size_t),
+                ("spec_rows", C.c_int32)]
 
 
 class Geometry(C.Structure):
@@ -52,6 +53,7 @@ SIGNATURES = {
     "pat_H_export": [_vp, _i32, _i32, _vp, _vp],
     "pat_workspace_bytes": [_vp, _i32, C.POINTER(_sz)],
     "pat_get_info": [_vp, C.POINTER(OpInfo)],
+    "pat_spectrum_rows": [_vp, C.POINTER(_i32)],
     "pat_apply_A": [_vp, _vp, _vp, _i32, _vp, _sz, _vp],
     "pat_apply_AT": [_vp, _vp, _vp, _i32, _vp, _sz, _vp],
     "pat_power_norm": [_vp, _vp, _i32, C.POINTER(_f64), C.POINTER(_f64), _vp, _sz, _vp],

@@ -82,7 +82,7 @@ __global__ __launch_bounds__(256) void k_contract(ContractArgs a, int lr_log2) {
     for (int gg = 0; gg < G; ++gg) k = (gg == g) ? kg[gg] : k;
     float2 v = make_float2(0.f, 0.f);
     if (k >= 0) {
-      v = a.in[(size_t)k * a.in_rs + (size_t)b * a.ni + i];
+      v = a.in[(size_t)(c * G + g) * a.in_rs + (size_t)b * a.ni + i];
       if (a.in_scale) v = cscale(v, a.in_scale[i]);
     }
     xin[idx] = v;
@@ -171,7 +171,7 @@ __global__ __launch_bounds__(256) void k_contract(ContractArgs a, int lr_log2) {
         for (int g = 0; g < G; ++g) {
           if (kg[g] < 0) continue;
           const float* p = &acc[((jj * VEC + v) * G + g) * 2];
-          a.out[(size_t)kg[g] * a.out_rs + (size_t)b * a.nj + j] = make_float2(p[0] * sc, p[1] * sc);
+          a.out[(size_t)(c * G + g) * a.out_rs + (size_t)b * a.nj + j] = make_float2(p[0] * sc, p[1] * sc);
         }
       }
     }

@@ -41,30 +41,38 @@ __device__ __forceinline__ void load_twiddles(float2* tw, int tid, int nthreads)
 }
 
 // ------------------------------------------------------------- columns (y)
-// out[(p*nh + m)*rs + s] = sum_j exp(DIR 2 pi i p j / N) in[(j*nh + m)*rs + s]
+// out[orow(p*nh + m)*rs + s] = sum_j exp(DIR 2 pi i p j / N) in[irow(j*nh + m)*rs + s]
+// irow / orow: row maps (null = identity); the spectrum side uses the
+// class-major map so that the contraction reads and writes contiguous rows.
 template <int N, int DIR>
 __global__ __launch_bounds__(256) void k_fft_cols(const float2* __restrict__ in,
                                                   float2* __restrict__ out, int nh, int S,
-                                                  int rs) {
+                                                  int rs, const int32_t* __restrict__ imap,
+                                                  const int32_t* __restrict__ omap) {
   constexpr int N1 = Split<N>::N1, N2 = Split<N>::N2;
   constexpr int SB = 16;       // slices per block
   constexpr int PAD = N + 1;   // LDS stride per slice (complex)
   constexpr int NT = SB * N1;  // threads
   __shared__ float2 tw[N];
   __shared__ float2 ex[SB * PAD];
+  __shared__ int rin[N], rout[N];
   const int tid = threadIdx.x;
   const int s = tid % SB, t = tid / SB;
   const int m = blockIdx.x;
   const int sg = blockIdx.y * SB + s;
   const bool live = sg < S;
   load_twiddles<N, DIR>(tw, tid, NT);
+  for (int y = tid; y < N; y += NT) {
+    rin[y] = imap ? imap[y * nh + m] : y * nh + m;
+    rout[y] = omap ? omap[y * nh + m] : y * nh + m;
+  }
   __syncthreads();
   if (t < N2) {
     float2 v[N1];
 #pragma unroll
     for (int n1 = 0; n1 < N1; ++n1) {
       const int y = t + N2 * n1;
-      v[n1] = live ? in[(size_t)(y * nh + m) * rs + sg] : make_float2(0.f, 0.f);
+      v[n1] = live ? in[(size_t)rin[y] * rs + sg] : make_float2(0.f, 0.f);
     }
     dft<N1, DIR>(v);
 #pragma unroll
@@ -79,7 +87,7 @@ __global__ __launch_bounds__(256) void k_fft_cols(const float2* __restrict__ in,
 #pragma unroll
     for (int k2 = 0; k2 < N2; ++k2) {
       const int p = t + N1 * k2;
-      out[(size_t)(p * nh + m) * rs + sg] = v[k2];
+      out[(size_t)rout[p] * rs + sg] = v[k2];
     }
   }
 }
@@ -220,27 +228,29 @@ __global__ __launch_bounds__(256) void k_fft_rows_c2r(const float2* __restrict__
 
 // ------------------------------------------------------------- launchers
 template <int N, int DIR>
-static void launch_cols(const float2* in, float2* out, int nh, int S, int rs, hipStream_t st) {
+static void launch_cols(const float2* in, float2* out, int nh, int S, int rs, const int32_t* imap,
+                        const int32_t* omap, hipStream_t st) {
   dim3 grid(nh, (S + 15) / 16);
-  k_fft_cols<N, DIR><<<grid, 16 * Split<N>::N1, 0, st>>>(in, out, nh, S, rs);
+  k_fft_cols<N, DIR><<<grid, 16 * Split<N>::N1, 0, st>>>(in, out, nh, S, rs, imap, omap);
 }
 
 template <int DIR>
 static pat_status cols(const float2* in, float2* out, int ny, int nh, int S, int rs,
-                       hipStream_t st) {
+                       const int32_t* imap, const int32_t* omap, hipStream_t st) {
   switch (ny) {
-    case 16: launch_cols<16, DIR>(in, out, nh, S, rs, st); break;
-    case 32: launch_cols<32, DIR>(in, out, nh, S, rs, st); break;
-    case 64: launch_cols<64, DIR>(in, out, nh, S, rs, st); break;
-    case 128: launch_cols<128, DIR>(in, out, nh, S, rs, st); break;
-    case 256: launch_cols<256, DIR>(in, out, nh, S, rs, st); break;
+    case 16: launch_cols<16, DIR>(in, out, nh, S, rs, imap, omap, st); break;
+    case 32: launch_cols<32, DIR>(in, out, nh, S, rs, imap, omap, st); break;
+    case 64: launch_cols<64, DIR>(in, out, nh, S, rs, imap, omap, st); break;
+    case 128: launch_cols<128, DIR>(in, out, nh, S, rs, imap, omap, st); break;
+    case 256: launch_cols<256, DIR>(in, out, nh, S, rs, imap, omap, st); break;
     default: return fail(PAT_EUNSUPPORTED, "ny must be a power of two in [16, 256]");
   }
   PAT_LAUNCHED("fft columns");
   return PAT_OK;
 }
 
-pat_status fft2_r2c(const float* f, float2* T, float2* X, int nx, int ny, int S, hipStream_t st) {
+pat_status fft2_r2c(const float* f, float2* T, float2* X, int nx, int ny, int S,
+                    const int32_t* rowmap, hipStream_t st) {
   if (S <= 0) return PAT_OK;
   const int nh = nx / 2 + 1;
   dim3 grid(ny, (S + 31) / 32);
@@ -253,14 +263,14 @@ pat_status fft2_r2c(const float* f, float2* T, float2* X, int nx, int ny, int S,
     default: return fail(PAT_EUNSUPPORTED, "nx must be a power of two in [16, 256]");
   }
   PAT_LAUNCHED("fft rows r2c");
-  return cols<-1>(T, X, ny, nh, S, S, st);
+  return cols<-1>(T, X, ny, nh, S, S, nullptr, rowmap, st);
 }
 
 pat_status fft2_c2r(const float2* X, float2* T, float* f, int nx, int ny, int S, float scale,
-                    const float* sub, hipStream_t st) {
+                    const float* sub, const int32_t* rowmap, hipStream_t st) {
   if (S <= 0) return PAT_OK;
   const int nh = nx / 2 + 1;
-  PAT_TRY(cols<+1>(X, T, ny, nh, S, S, st));
+  PAT_TRY(cols<+1>(X, T, ny, nh, S, S, rowmap, nullptr, st));
   dim3 grid(ny, (S + 31) / 32);
   switch (nx) {
     case 16: k_fft_rows_c2r<16><<<grid, 16 * Split<16>::N1, 0, st>>>(T, f, ny, S, S, scale, sub); break;

@@ -24,14 +24,16 @@ struct pat_op {
   int vec;      // storage elements per 16-byte load
   int sA_row, sT_row;
   char* hbuf;
+  int nrows;          // spectrum rows: nclass * G, class-major
   int32_t* members;   // [nclass][G]
   int32_t* kclass;    // [nk]
+  int32_t* rowmap;    // [nk] spectrum row of frequency k
   int32_t* cls_freq;  // [nclass][2]
   float* inv_scale;   // [nz]
   unsigned long long* amax;  // [nz]
   void* slabA;        // [nclass][nz][sA_row]
   void* slabT;        // [nclass][nt][sT_row]
-  std::vector<int32_t> h_members, h_kclass, h_cls_freq;
+  std::vector<int32_t> h_members, h_kclass, h_cls_freq, h_rowmap;
 };
 
 namespace pat {
@@ -80,7 +82,7 @@ static pat_status check_geometry(const pat_geometry* g) {
 // half-spectrum indices k = p*nh + m of the class.
 struct Classes {
   int G = 2;
-  std::vector<int32_t> members, kclass, freq;
+  std::vector<int32_t> members, kclass, freq, rowmap;
   int n() const { return (int)freq.size() / 2; }
 };
 
@@ -116,16 +118,20 @@ static Classes make_classes(const pat_geometry& g) {
     int slot = add_member(c, 0, fa, fb, C.members);
     if (octant && fa != fb) add_member(c, slot, fb, fa, C.members);
   }
+  C.rowmap.assign(C.kclass.size(), -1);
   for (int c = 0; c < C.n(); ++c)
     for (int s = 0; s < C.G; ++s) {
       const int k = C.members[(size_t)c * C.G + s];
-      if (k >= 0) C.kclass[k] = c;
+      if (k >= 0) {
+        C.kclass[k] = c;
+        C.rowmap[k] = c * C.G + s;
+      }
     }
   return C;
 }
 
 struct HLayout {
-  size_t off_members, off_kclass, off_freq, off_inv, off_amax, off_A, off_T, total;
+  size_t off_members, off_kclass, off_rowmap, off_freq, off_inv, off_amax, off_A, off_T, total;
   int nclass, G, vec, sA_row, sT_row;
 };
 
@@ -141,6 +147,7 @@ static HLayout h_layout(const pat_geometry& g, const Classes& C) {
   size_t o = 0;
   L.off_members = o; o = align_up(o + (size_t)L.nclass * L.G * 4, 256);
   L.off_kclass = o;  o = align_up(o + (size_t)nk * 4, 256);
+  L.off_rowmap = o;  o = align_up(o + (size_t)nk * 4, 256);
   L.off_freq = o;    o = align_up(o + (size_t)L.nclass * 8, 256);
   L.off_inv = o;     o = align_up(o + (size_t)g.nz * 4, 256);
   L.off_amax = o;    o = align_up(o + (size_t)g.nz * 8, 256);
@@ -173,8 +180,8 @@ static Work work_layout(const pat_op* op, int B, char* base) {
     o = align_up(o + bytes, 256);
     return p;
   };
-  w.Xs = (float2*)take((size_t)op->nk * Sz * 8);
-  w.Ds = (float2*)take((size_t)op->nk * St * 8);
+  w.Xs = (float2*)take((size_t)op->nrows * Sz * 8);
+  w.Ds = (float2*)take((size_t)op->nrows * St * 8);
   w.T = (float2*)take((size_t)g.ny * op->nh * std::max(Sz, St) * 8);
   w.V = (float*)take(Sz * nxy * 4);
   w.U = (float*)take(Sz * nxy * 4);
@@ -242,17 +249,19 @@ static pat_status run_contract(pat_op* op, bool adjoint, const float2* in, float
 static pat_status run_A(pat_op* op, const float* x, float* y, int B, const float* sub, const Work& w,
                         hipStream_t st) {
   const pat_geometry& g = op->g;
-  PAT_TRY(fft2_r2c(x, w.T, w.Xs, g.nx, g.ny, B * g.nz, st));
+  PAT_TRY(fft2_r2c(x, w.T, w.Xs, g.nx, g.ny, B * g.nz, op->rowmap, st));
   PAT_TRY(run_contract(op, false, w.Xs, w.Ds, B, st));
-  return fft2_c2r(w.Ds, w.T, y, g.nx, g.ny, B * g.nt, 1.0f / (float)(g.nx * g.ny), sub, st);
+  return fft2_c2r(w.Ds, w.T, y, g.nx, g.ny, B * g.nt, 1.0f / (float)(g.nx * g.ny), sub,
+                  op->rowmap, st);
 }
 
 // x = A^T y, B data sets
 static pat_status run_AT(pat_op* op, const float* y, float* x, int B, const Work& w, hipStream_t st) {
   const pat_geometry& g = op->g;
-  PAT_TRY(fft2_r2c(y, w.T, w.Ds, g.nx, g.ny, B * g.nt, st));
+  PAT_TRY(fft2_r2c(y, w.T, w.Ds, g.nx, g.ny, B * g.nt, op->rowmap, st));
   PAT_TRY(run_contract(op, true, w.Ds, w.Xs, B, st));
-  return fft2_c2r(w.Xs, w.T, x, g.nx, g.ny, B * g.nz, 1.0f / (float)(g.nx * g.ny), nullptr, st);
+  return fft2_c2r(w.Xs, w.T, x, g.nx, g.ny, B * g.nz, 1.0f / (float)(g.nx * g.ny), nullptr,
+                  op->rowmap, st);
 }
 
 }  // namespace pat
@@ -337,8 +346,10 @@ pat_status pat_H_build(pat_ctx* ctx, const pat_geometry* geom, void* h_buf, size
   op->sA_row = L.sA_row;
   op->sT_row = L.sT_row;
   op->hbuf = (char*)h_buf;
+  op->nrows = L.nclass * L.G;
   op->members = (int32_t*)(op->hbuf + L.off_members);
   op->kclass = (int32_t*)(op->hbuf + L.off_kclass);
+  op->rowmap = (int32_t*)(op->hbuf + L.off_rowmap);
   op->cls_freq = (int32_t*)(op->hbuf + L.off_freq);
   op->inv_scale = (float*)(op->hbuf + L.off_inv);
   op->amax = (unsigned long long*)(op->hbuf + L.off_amax);
@@ -347,6 +358,7 @@ pat_status pat_H_build(pat_ctx* ctx, const pat_geometry* geom, void* h_buf, size
   op->h_members = std::move(C.members);
   op->h_kclass = std::move(C.kclass);
   op->h_cls_freq = std::move(C.freq);
+  op->h_rowmap = std::move(C.rowmap);
 
   auto bail = [&](pat_status s) {
     delete op;
@@ -363,6 +375,9 @@ pat_status pat_H_build(pat_ctx* ctx, const pat_geometry* geom, void* h_buf, size
     return bail(s);
   if ((s = hip_check(hipMemcpyAsync(op->cls_freq, op->h_cls_freq.data(), op->h_cls_freq.size() * 4,
                                     hipMemcpyHostToDevice, st), "upload frequencies")) != PAT_OK)
+    return bail(s);
+  if ((s = hip_check(hipMemcpyAsync(op->rowmap, op->h_rowmap.data(), op->h_rowmap.size() * 4,
+                                    hipMemcpyHostToDevice, st), "upload row map")) != PAT_OK)
     return bail(s);
   HBuildArgs a;
   a.cls_freq = op->cls_freq;
@@ -413,6 +428,13 @@ pat_status pat_get_info(const pat_op* op, pat_op_info* info) {
   info->nz_sim = op->nq;
   info->slab_bytes_A = (size_t)op->nclass * op->g.nz * op->sA_row * esz;
   info->slab_bytes_AT = (size_t)op->nclass * op->g.nt * op->sT_row * esz;
+  info->spec_rows = op->nrows;
+  return PAT_OK;
+}
+
+pat_status pat_spectrum_rows(const pat_op* op, int32_t* k_of_row) {
+  if (!op || !k_of_row) return fail(PAT_EINVAL, "null argument");
+  for (int r = 0; r < op->nrows; ++r) k_of_row[r] = op->h_members[r];
   return PAT_OK;
 }
 
@@ -456,7 +478,7 @@ pat_status pat_spectrum(pat_op* op, const float* f, float* spec, int32_t S, void
   PAT_TRY(check_stage(op, S, ws, ws_bytes, &w));
   PAT_TRY(check_ptr(f, "f"));
   PAT_TRY(check_ptr(spec, "spec"));
-  return fft2_r2c(f, w.T, (float2*)spec, op->g.nx, op->g.ny, S, (hipStream_t)stream);
+  return fft2_r2c(f, w.T, (float2*)spec, op->g.nx, op->g.ny, S, op->rowmap, (hipStream_t)stream);
 }
 
 pat_status pat_inverse_spectrum(pat_op* op, const float* spec, float* f, int32_t S, const float* sub,
@@ -467,7 +489,7 @@ pat_status pat_inverse_spectrum(pat_op* op, const float* spec, float* f, int32_t
   PAT_TRY(check_ptr(spec, "spec"));
   if (sub) PAT_TRY(check_ptr(sub, "sub"));
   return fft2_c2r((const float2*)spec, w.T, f, op->g.nx, op->g.ny, S,
-                  1.0f / (float)(op->g.nx * op->g.ny), sub, (hipStream_t)stream);
+                  1.0f / (float)(op->g.nx * op->g.ny), sub, op->rowmap, (hipStream_t)stream);
 }
 
 pat_status pat_contract(pat_op* op, int32_t adjoint, const float* in, float* out, int32_t B,

@@ -31,25 +31,26 @@ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // --------------------------------------------------------------- 2D FFTs
 // Slice layouts (S slices, element type float / float2):
 //   real slices      f[s][ny][nx]
-//   half spectrum    X[(p*nh + m) * rs + s]   (frequency-major, slice fastest;
-//                    nh = nx/2 + 1; rs = row stride in complex elements)
-//   row-transformed  T[(j*nh + m) * rs + s]   (same shape, y not yet transformed)
+//   half spectrum    X[row(p*nh + m) * S + s] (frequency rows, slice fastest;
+//                    nh = nx/2 + 1; row() is the class-major row map, or the
+//                    identity when rowmap is null)
+//   row-transformed  T[(j*nh + m) * S + s]   (y not yet transformed)
 // Forward transforms are unnormalised; the inverse multiplies by `scale`.
 pat_status fft_init_device();  // uploads the twiddle table to the current device
 pat_status fft2_r2c(const float* f, float2* T, float2* X, int nx, int ny, int S,
-                    hipStream_t st);
+                    const int32_t* rowmap, hipStream_t st);
 // f = scale * c2r(X) - sub (sub may be null; same layout as f)
 pat_status fft2_c2r(const float2* X, float2* T, float* f, int nx, int ny, int S,
-                    float scale, const float* sub, hipStream_t st);
+                    float scale, const float* sub, const int32_t* rowmap, hipStream_t st);
 
 // ------------------------------------------------------ contraction (VALU)
-// out[k_g][obj*nj + j] = sum_i slab_c[i][j] * in[k_g][obj*ni + i] (* scales)
-// for every class c and its members k_g (g < G, -1 = none).
+// out[c*G+g][obj*nj + j] = sum_i slab_c[i][j] * in[c*G+g][obj*ni + i] (* scales)
+// for every class c and its member slots g < G (members[c*G+g] < 0: empty).
 struct ContractArgs {
   const void* slab;        // [C][ni][s_row] of the storage type
   const int32_t* members;  // [C][G]
-  const float2* in;        // [nk][in_rs]
-  float2* out;             // [nk][out_rs]
+  const float2* in;        // [C*G][in_rs]  class-major spectrum rows
+  float2* out;             // [C*G][out_rs]
   const float* in_scale;   // [ni] or null
   const float* out_scale;  // [nj] or null
   int ni, nj, s_row;

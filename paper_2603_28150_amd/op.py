@@ -142,8 +142,15 @@ class Operator:
                   B, _stream(self.device))
         return spec_out
 
+    def spectrum_rows(self):
+        """Frequency index k of every spectrum row (-1: unused row)."""
+        n = self.info()["spec_rows"]
+        arr = (C.c_int32 * n)()
+        _lib.call("pat_spectrum_rows", self.handle, arr)
+        return list(arr)
+
     def spectrum_buffer(self, S: int) -> torch.Tensor:
-        return torch.empty((self.nk, S, 2), dtype=torch.float32, device=self.device)
+        return torch.empty((self.info()["spec_rows"], S, 2), dtype=torch.float32, device=self.device)
 
     def workspace_bytes(self, B: int = 1) -> int:
         n = C.c_size_t()

@@ -261,3 +261,28 @@ def test_quantised_library(kind):
     assert rel(gq, ops.AT_fft(Hq, d)) < 2e-5
     assert rel(gq, ops.AT_fft(Hh, d)) < 5e-3
     assert op.adjoint_check(dev(x), dev(d)) < 1e-5
+
+
+@pytest.mark.parametrize("name", ["tiny", "ragged"])
+def test_stage_calls_compose_apply_and_row_map(name):
+    g, op, Hh = setup(name)
+    x = inputs.gaussian_random((g.nz, g.ny, g.nx), seed=95)
+    xd = dev(x)
+    Xs = op.spectrum_buffer(g.nz)
+    op.spectrum(xd, g.nz, Xs)
+    rows = op.spectrum_rows()
+    assert sorted(k for k in rows if k >= 0) == list(range(op.nk))
+    ref = np.fft.rfft2(x, axes=(1, 2))              # [nz, ny, nx/2+1]
+    nh = g.nx // 2 + 1
+    Xh = Xs.cpu().numpy().astype(np.float64)
+    for r, k in enumerate(rows):
+        if k < 0:
+            continue
+        p, m = divmod(k, nh)
+        got = Xh[r, :, 0] + 1j * Xh[r, :, 1]
+        assert np.abs(got - ref[:, p, m]).max() <= 1e-5 * np.abs(ref).max()
+    Ds = op.spectrum_buffer(g.nt)
+    op.contract(Xs, Ds, adjoint=False)
+    y = torch.empty(op.d_shape, device="cuda")
+    op.inverse_spectrum(Ds, g.nt, y)
+    assert torch.equal(y, op.apply_A(xd))
