@@ -119,6 +119,41 @@ __global__ __launch_bounds__(256) void k_hbuild(HBuildArgs a) {
         if (nl == 0 && l < a.nz)
           atomicMax(&a.amax[l], (unsigned long long)__double_as_longlong(m));
       }
+    } else if (a.hdtype != PAT_H_F32) {
+      // 16-bit library: MFMA fragments for both directions, through the LDS tile
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int ll = lg + 4 * u, l = l0 + ll;
+        tile[nl * (kLP + 1) + ll] = (l < a.nz) ? (float)(acc[u] * depth_scale(a.amax, l, a.hdtype)) : 0.f;
+      }
+      __syncthreads();
+      const int n0 = blockIdx.x * kNT;
+      for (int dir = 0; dir < 2; ++dir) {
+        // dir 0: rows n, k = l (forward);  dir 1: rows l, k = n (adjoint)
+        const int nt = dir == 0 ? a.ntA : a.ntT, ks = dir == 0 ? a.ksA : a.ksT;
+        const int rt0 = (dir == 0 ? n0 : l0) / 32, kt0 = (dir == 0 ? l0 : n0) / 16;
+        unsigned short* dst = reinterpret_cast<unsigned short*>(dir == 0 ? a.slabA : a.slabT);
+        for (int unit = tid; unit < 8 * 64; unit += 256) {
+          const int f = unit >> 6, L = unit & 63;
+          const int rt = f >> 2, kt = f & 3;
+          if (rt0 + rt >= nt || kt0 + kt >= ks) continue;
+          const int r = rt * 32 + (L & 31), k = kt * 16 + 8 * (L >> 5);
+          unsigned short v[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const float x = dir == 0 ? tile[r * (kLP + 1) + k + e] : tile[(k + e) * (kLP + 1) + r];
+            v[e] = a.hdtype == PAT_H_BF16 ? to_bf16(x) : to_f16(x);
+          }
+          uint4 pk;
+          pk.x = v[0] | ((unsigned)v[1] << 16);
+          pk.y = v[2] | ((unsigned)v[3] << 16);
+          pk.z = v[4] | ((unsigned)v[5] << 16);
+          pk.w = v[6] | ((unsigned)v[7] << 16);
+          const size_t o = (((size_t)c * nt + rt0 + rt) * ks + kt0 + kt) * 64 + L;
+          reinterpret_cast<uint4*>(dst)[o] = pk;
+        }
+      }
     } else {
       // [l][n] slab: lanes along n, coalesced
       __syncthreads();
@@ -172,17 +207,18 @@ pat_status hbuild(const HBuildArgs& a, hipStream_t st) {
 
 // ------------------------------------------------------------ export
 __global__ void k_hexport(const void* slabA, int hdtype, const int32_t* kclass,
-                          const float* inv_scale, int k0, int nz, int nt, int sA_row,
-                          float* out) {
+                          const float* inv_scale, int k0, int nz, int nt, int sA_row, int ntA,
+                          int ksA, float* out) {
   const int kk = blockIdx.x;
   const int c = kclass[k0 + kk];
   for (int e = threadIdx.x; e < nz * nt; e += blockDim.x) {
     const int l = e / nt, n = e % nt;
-    const size_t o = ((size_t)c * nz + l) * sA_row + n;
     float f;
     if (hdtype == PAT_H_F32) {
-      f = reinterpret_cast<const float*>(slabA)[o];
+      f = reinterpret_cast<const float*>(slabA)[((size_t)c * nz + l) * sA_row + n];
     } else {
+      // fragment (n/32, l/16), lane n%32 + 32*((l%16)/8), element l%8
+      const size_t o = ((((size_t)c * ntA + n / 32) * ksA + l / 16) * 64 + (n & 31) + 32 * ((l >> 3) & 1)) * 8 + (l & 7);
       const unsigned short b = reinterpret_cast<const unsigned short*>(slabA)[o];
       if (hdtype == PAT_H_BF16) {
         f = __uint_as_float((unsigned)b << 16);
@@ -197,9 +233,11 @@ __global__ void k_hexport(const void* slabA, int hdtype, const int32_t* kclass,
 }
 
 pat_status hexport(const void* slabA, int hdtype, const int32_t* kclass, const float* inv_scale,
-                   int k0, int nk, int nz, int nt, int sA_row, float* out, hipStream_t st) {
+                   int k0, int nk, int nz, int nt, int sA_row, int ntA, int ksA, float* out,
+                   hipStream_t st) {
   if (nk <= 0) return PAT_OK;
-  k_hexport<<<nk, 256, 0, st>>>(slabA, hdtype, kclass, inv_scale, k0, nz, nt, sA_row, out);
+  k_hexport<<<nk, 256, 0, st>>>(slabA, hdtype, kclass, inv_scale, k0, nz, nt, sA_row, ntA, ksA,
+                                out);
   PAT_LAUNCHED("H export");
   return PAT_OK;
 }

@@ -23,6 +23,7 @@ struct pat_op {
   int nclass;
   int vec;      // storage elements per 16-byte load
   int sA_row, sT_row;
+  int ntA, ksA, ntT, ksT;  // 16-bit fragment tiling
   char* hbuf;
   int nrows;          // spectrum rows: nclass * G, class-major
   int32_t* members;   // [nclass][G]
@@ -132,7 +133,9 @@ static Classes make_classes(const pat_geometry& g) {
 
 struct HLayout {
   size_t off_members, off_kclass, off_rowmap, off_freq, off_inv, off_amax, off_A, off_T, total;
+  size_t bytes_A, bytes_T;
   int nclass, G, vec, sA_row, sT_row;
+  int ntA, ksA, ntT, ksT;
 };
 
 static HLayout h_layout(const pat_geometry& g, const Classes& C) {
@@ -143,6 +146,18 @@ static HLayout h_layout(const pat_geometry& g, const Classes& C) {
   L.vec = (int)(16 / esz);
   L.sA_row = (int)align_up((size_t)g.nt, (size_t)L.vec);
   L.sT_row = (int)align_up((size_t)g.nz, (size_t)L.vec);
+  // 16-bit libraries are stored as MFMA fragments: 32 output rows x 16 k
+  L.ntA = (g.nt + 31) / 32;
+  L.ksA = (g.nz + 15) / 16;
+  L.ntT = (g.nz + 31) / 32;
+  L.ksT = (g.nt + 15) / 16;
+  if (g.h_dtype == PAT_H_F32) {
+    L.bytes_A = (size_t)L.nclass * g.nz * L.sA_row * esz;
+    L.bytes_T = (size_t)L.nclass * g.nt * L.sT_row * esz;
+  } else {
+    L.bytes_A = (size_t)L.nclass * L.ntA * L.ksA * 1024;
+    L.bytes_T = (size_t)L.nclass * L.ntT * L.ksT * 1024;
+  }
   const int nk = g.ny * (g.nx / 2 + 1);
   size_t o = 0;
   L.off_members = o; o = align_up(o + (size_t)L.nclass * L.G * 4, 256);
@@ -151,8 +166,8 @@ static HLayout h_layout(const pat_geometry& g, const Classes& C) {
   L.off_freq = o;    o = align_up(o + (size_t)L.nclass * 8, 256);
   L.off_inv = o;     o = align_up(o + (size_t)g.nz * 4, 256);
   L.off_amax = o;    o = align_up(o + (size_t)g.nz * 8, 256);
-  L.off_A = o;       o = align_up(o + (size_t)L.nclass * g.nz * L.sA_row * esz, 256);
-  L.off_T = o;       o = align_up(o + (size_t)L.nclass * g.nt * L.sT_row * esz, 256);
+  L.off_A = o;       o = align_up(o + L.bytes_A, 256);
+  L.off_T = o;       o = align_up(o + L.bytes_T, 256);
   L.total = o;
   return L;
 }
@@ -224,6 +239,35 @@ static pat_status run_contract(pat_op* op, bool adjoint, const float2* in, float
   a.out = out;
   a.nclass = op->nclass;
   const float* sc = g.h_dtype == PAT_H_F32 ? nullptr : op->inv_scale;
+  if (g.h_dtype != PAT_H_F32) {
+    MfmaArgs m;
+    m.members = op->members;
+    m.in = in;
+    m.out = out;
+    m.G = op->G;
+    m.B = B;
+    m.nclass = op->nclass;
+    if (!adjoint) {
+      m.frag = op->slabA;
+      m.K = g.nz;
+      m.N = g.nt;
+      m.ntiles = op->ntA;
+      m.ksteps = op->ksA;
+      m.in_scale = sc;
+      m.out_scale = nullptr;
+    } else {
+      m.frag = op->slabT;
+      m.K = g.nt;
+      m.N = g.nz;
+      m.ntiles = op->ntT;
+      m.ksteps = op->ksT;
+      m.in_scale = nullptr;
+      m.out_scale = sc;
+    }
+    m.in_rs = B * m.K;
+    m.out_rs = B * m.N;
+    return contract_mfma(m, g.h_dtype, st);
+  }
   if (!adjoint) {
     a.slab = op->slabA;
     a.in_scale = sc;
@@ -345,6 +389,10 @@ pat_status pat_H_build(pat_ctx* ctx, const pat_geometry* geom, void* h_buf, size
   op->vec = L.vec;
   op->sA_row = L.sA_row;
   op->sT_row = L.sT_row;
+  op->ntA = L.ntA;
+  op->ksA = L.ksA;
+  op->ntT = L.ntT;
+  op->ksT = L.ksT;
   op->hbuf = (char*)h_buf;
   op->nrows = L.nclass * L.G;
   op->members = (int32_t*)(op->hbuf + L.off_members);
@@ -396,6 +444,10 @@ pat_status pat_H_build(pat_ctx* ctx, const pat_geometry* geom, void* h_buf, size
   a.slabT = op->slabT;
   a.sA_row = op->sA_row;
   a.sT_row = op->sT_row;
+  a.ntA = op->ntA;
+  a.ksA = op->ksA;
+  a.ntT = op->ntT;
+  a.ksT = op->ksT;
   a.amax = op->amax;
   a.inv_scale = op->inv_scale;
   a.hdtype = geom->h_dtype;
@@ -416,18 +468,19 @@ pat_status pat_H_export(pat_op* op, int32_t k0, int32_t nk, float* out, void* st
   PAT_TRY(check_ptr(out, "out"));
   PAT_HIP(hipSetDevice(op->ctx->device));
   return hexport(op->slabA, op->g.h_dtype, op->kclass, op->inv_scale, k0, nk, op->g.nz, op->g.nt,
-                 op->sA_row, out, (hipStream_t)stream);
+                 op->sA_row, op->ntA, op->ksA, out, (hipStream_t)stream);
 }
 
 pat_status pat_get_info(const pat_op* op, pat_op_info* info) {
   if (!op || !info) return fail(PAT_EINVAL, "null argument");
-  const size_t esz = op->g.h_dtype == PAT_H_F32 ? 4 : 2;
+  Classes C = make_classes(op->g);
+  const HLayout L = h_layout(op->g, C);
   info->nk = op->nk;
   info->nclass = op->nclass;
   info->members_max = op->G;
   info->nz_sim = op->nq;
-  info->slab_bytes_A = (size_t)op->nclass * op->g.nz * op->sA_row * esz;
-  info->slab_bytes_AT = (size_t)op->nclass * op->g.nt * op->sT_row * esz;
+  info->slab_bytes_A = L.bytes_A;
+  info->slab_bytes_AT = L.bytes_T;
   info->spec_rows = op->nrows;
   return PAT_OK;
 }

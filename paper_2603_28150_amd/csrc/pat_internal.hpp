@@ -60,21 +60,39 @@ struct ContractArgs {
 };
 pat_status contract(const ContractArgs& a, int hdtype, int G, int B, hipStream_t st);
 
+// ------------------------------------------------------ contraction (MFMA)
+// out[c*G+g][b*N + n] = sum_k X[c*G+g][b*K + k] * S_c(k, n) for 16-bit slabs
+// stored as 32 x 16 bf16/f16 fragments in MFMA B-operand lane order:
+// fragment (tile, kstep) of class c holds S_c(kstep*16 + 8*(lane/32) + e,
+// tile*32 + lane%32) at 16-byte unit lane, element e.
+struct MfmaArgs {
+  const void* frag;        // [C][ntiles][ksteps][64] 16-byte units
+  const int32_t* members;  // [C][G]
+  const float2* in;        // [C*G][in_rs]
+  float2* out;             // [C*G][out_rs]
+  const float* in_scale;   // [K] or null
+  const float* out_scale;  // [N] or null
+  int K, N, ntiles, ksteps, in_rs, out_rs, G, B, nclass;
+};
+pat_status contract_mfma(const MfmaArgs& a, int hdtype, hipStream_t st);
+
 // ------------------------------------------------------------- H^ build
 struct HBuildArgs {
   const int32_t* cls_freq;  // [C][2]: |m~|, |p~| (x and y frequency indices)
   int nclass, nx, ny, nz, nt, nq;
   double dx, dy, dz, dt, c;
-  void* slabA;              // [C][nz][sA_row]  (n fastest)
-  void* slabT;              // [C][nt][sT_row]  (l fastest)
+  void* slabA;              // FP32: [C][nz][sA_row] (n fastest); 16-bit: fragments (n, k=l)
+  void* slabT;              // FP32: [C][nt][sT_row] (l fastest); 16-bit: fragments (l, k=n)
   int sA_row, sT_row;
+  int ntA, ksA, ntT, ksT;   // fragment tiling of the 16-bit layouts
   unsigned long long* amax; // [nz] bit patterns of max |H^| per depth
   float* inv_scale;         // [nz] 1/s_l
   int hdtype;
 };
 pat_status hbuild(const HBuildArgs& a, hipStream_t st);
 pat_status hexport(const void* slabA, int hdtype, const int32_t* kclass, const float* inv_scale,
-                   int k0, int nk, int nz, int nt, int sA_row, float* out, hipStream_t st);
+                   int k0, int nk, int nz, int nt, int sA_row, int ntA, int ksA, float* out,
+                   hipStream_t st);
 
 // ------------------------------------------------------- vector kernels
 pat_status fill_zero(void* p, size_t bytes, hipStream_t st);
