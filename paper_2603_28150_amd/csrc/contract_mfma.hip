@@ -177,7 +177,9 @@ __global__ __launch_bounds__(512) void k_contract_mfma(MfmaArgs a) {
     if (kparts > 1) {
       float* red = reinterpret_cast<float*>(lds);
       staged = false;
-      for (int m = 0; m < MT; ++m) {
+#pragma unroll
+      for (int m = 0; m < kMT; ++m) {
+        if (m >= MT) break;
         __syncthreads();
 #pragma unroll
         for (int v = 0; v < 16; ++v) red[(w * 16 + v) * 64 + lane] = acc[m][v];
