@@ -28,7 +28,7 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kWaves = 8;      // waves per workgroup
 constexpr int kKC = 8;         // k-steps (of 16) per staged chunk
-constexpr int kMT = 4;         // 32-column tiles per launch group (64 pairs)
+constexpr int kMT = 4;         // most 32-column tiles per launch group (64 pairs)
 constexpr int kTerms = 2;      // hi + lo split of the spectra
 
 __device__ __forceinline__ unsigned short bf16_rne(float f) {
@@ -57,51 +57,66 @@ __device__ __forceinline__ void split_f16(const Frag& in, Frag& hi, Frag& lo) {
   }
 }
 
-// Stages the spectra of k-chunk ch (A operand), split hi + lo, into LDS.
-__device__ __forceinline__ void stage_chunk(const MfmaArgs& a, unsigned short* lds16, int c,
-                                            int p0, int gp, int ch, int tid) {
+// Stages the spectra of k-chunk ch (the A operand) into LDS, split hi + lo.
+// Work item = (pair, 8 consecutive k): 8 complex values in, four 16-byte
+// fragment units out (re and im columns, hi and lo terms).
+template <int MT>
+__device__ __forceinline__ void stage_chunk(const MfmaArgs& a, u32x4* lds, int c, int p0, int gp,
+                                            int ch, int tid) {
   const int k0 = ch * kKC * 16;
-  for (int idx = tid; idx < kMT * 16 * kKC * 16; idx += kWaves * 64) {
-    const int pl = idx / (kKC * 16), kk = idx % (kKC * 16);
-    const int k = k0 + kk;
-    float2 v = make_float2(0.f, 0.f);
-    if (pl < gp && k < a.K) {
+  constexpr int items = MT * 16 * kKC * 2;  // pairs x k-octets
+  for (int it = tid; it < items; it += kWaves * 64) {
+    const int pl = it / (kKC * 2), ko = it % (kKC * 2);
+    float2 v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = make_float2(0.f, 0.f);
+    if (pl < gp) {
       const int pair = p0 + pl;
       const int g = pair / a.B, b = pair % a.B;
       if (a.members[c * a.G + g] >= 0) {
-        v = a.in[(size_t)(c * a.G + g) * a.in_rs + (size_t)b * a.K + k];
-        if (a.in_scale) {
-          const float s = a.in_scale[k];
-          v.x *= s;
-          v.y *= s;
+        const float2* src = a.in + (size_t)(c * a.G + g) * a.in_rs + (size_t)b * a.K;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int k = k0 + ko * 8 + e;
+          if (k < a.K) {
+            v[e] = src[k];
+            if (a.in_scale) {
+              const float sc = a.in_scale[k];
+              v[e].x *= sc;
+              v[e].y *= sc;
+            }
+          }
         }
       }
     }
-    const int ks = kk >> 4, half = (kk >> 3) & 1, e = kk & 7;
+    const int ks = ko >> 1, half = ko & 1;
 #pragma unroll
     for (int part = 0; part < 2; ++part) {
       const int col = 2 * pl + part;
       const int mt = col >> 5, r = col & 31;
-      const float x = part ? v.y : v.x;
-      const unsigned short hi = bf16_rne(x);
-      const unsigned short lo = bf16_rne(x - bf16_to_f(hi));
-      const int unit = (ks * kMT + mt) * 64 + r + 32 * half;
-      lds16[(size_t)unit * 8 + e] = hi;
-      lds16[((size_t)kKC * kMT * 64 + unit) * 8 + e] = lo;
+      Frag hi, lo;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float x = part ? v[e].y : v[e].x;
+        hi.s[e] = bf16_rne(x);
+        lo.s[e] = bf16_rne(x - bf16_to_f(hi.s[e]));
+      }
+      const int unit = (ks * MT + mt) * 64 + r + 32 * half;
+      lds[unit] = hi.u;
+      lds[kKC * MT * 64 + unit] = lo.u;
     }
   }
 }
 
-template <bool F16>
-__global__ __launch_bounds__(512) void k_contract_mfma(MfmaArgs a) {
+template <bool F16, int MT>
+__global__ __launch_bounds__(512, MT == 4 ? 2 : 4) void k_contract_mfma(MfmaArgs a) {
   extern __shared__ u32x4 lds[];  // [term][ks][mt][lane] 16-byte units
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
   const int c = blockIdx.x, cg = blockIdx.y;
   const int npairs = a.G * a.B;
   const int p0 = cg * (kMT * 16);
-  const int gp = min(kMT * 16, npairs - p0);  // pairs in this launch group
-  const int MT = (2 * gp + 31) / 32;
+  const int gp = min(MT * 16, npairs - p0);  // pairs in this launch group
   // waves -> (N-tile, k-part): a wave owns one N-tile per pass; when there
   // are fewer N-tiles than waves, waves sharing a tile split its k-steps
   int kparts = 1;
@@ -110,25 +125,24 @@ __global__ __launch_bounds__(512) void k_contract_mfma(MfmaArgs a) {
   const int wslot = w / kparts;
   const int wstride = kWaves / kparts;
   const int nchunks = (a.ksteps + kKC - 1) / kKC;
-  unsigned short* lds16 = reinterpret_cast<unsigned short*>(lds);
   const u32x4* slab = reinterpret_cast<const u32x4*>(a.frag) + (size_t)c * a.ntiles * a.ksteps * 64;
-  bool staged = false;  // LDS holds chunk 0 (only kept when there is one chunk)
+  bool staged = false;  // LDS holds chunk 0 (kept only when there is one chunk)
 
   for (int tile0 = 0; tile0 < a.ntiles; tile0 += wstride) {
     const int tile = tile0 + wslot;
-    const bool has = wslot < wstride && tile < a.ntiles;
-    f32x16 acc[kMT];
+    const bool has = tile < a.ntiles;
+    f32x16 acc[MT];
 #pragma unroll
-    for (int m = 0; m < kMT; ++m) acc[m] = f32x16(0.f);
+    for (int m = 0; m < MT; ++m) acc[m] = f32x16(0.f);
 
     for (int ch = 0; ch < nchunks; ++ch) {
+      const int nks = min(kKC, a.ksteps - ch * kKC);
       if (!(staged && nchunks == 1)) {
         __syncthreads();
-        stage_chunk(a, lds16, c, p0, gp, ch, tid);
+        stage_chunk<MT>(a, lds, c, p0, gp, ch, tid);
         __syncthreads();
         staged = true;
       }
-      const int nks = min(kKC, a.ksteps - ch * kKC);
       // this wave's slab fragments of the chunk, all loads issued up front
       Frag fr[kKC];
 #pragma unroll
@@ -146,11 +160,10 @@ __global__ __launch_bounds__(512) void k_contract_mfma(MfmaArgs a) {
           if (s * kparts >= kKC || ks >= nks) break;
           if constexpr (!F16) {
 #pragma unroll
-            for (int m = 0; m < kMT; ++m) {
-              if (m >= MT) continue;
+            for (int m = 0; m < MT; ++m) {
               Frag ah, al;
-              ah.u = lds[(ks * kMT + m) * 64 + lane];
-              al.u = lds[(kKC * kMT + ks * kMT + m) * 64 + lane];
+              ah.u = lds[(ks * MT + m) * 64 + lane];
+              al.u = lds[(kKC * MT + ks * MT + m) * 64 + lane];
               acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah.b, fr[s].b, acc[m], 0, 0, 0);
               acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al.b, fr[s].b, acc[m], 0, 0, 0);
             }
@@ -158,11 +171,10 @@ __global__ __launch_bounds__(512) void k_contract_mfma(MfmaArgs a) {
             Frag hh, hl;
             split_f16(fr[s], hh, hl);
 #pragma unroll
-            for (int m = 0; m < kMT; ++m) {
-              if (m >= MT) continue;
+            for (int m = 0; m < MT; ++m) {
               Frag ah, al;
-              ah.u = lds[(ks * kMT + m) * 64 + lane];
-              al.u = lds[(kKC * kMT + ks * kMT + m) * 64 + lane];
+              ah.u = lds[(ks * MT + m) * 64 + lane];
+              al.u = lds[(kKC * MT + ks * MT + m) * 64 + lane];
               acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah.b, hh.b, acc[m], 0, 0, 0);
               acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al.b, hh.b, acc[m], 0, 0, 0);
               acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah.b, hl.b, acc[m], 0, 0, 0);
@@ -178,8 +190,7 @@ __global__ __launch_bounds__(512) void k_contract_mfma(MfmaArgs a) {
       float* red = reinterpret_cast<float*>(lds);
       staged = false;
 #pragma unroll
-      for (int m = 0; m < kMT; ++m) {
-        if (m >= MT) break;
+      for (int m = 0; m < MT; ++m) {
         __syncthreads();
 #pragma unroll
         for (int v = 0; v < 16; ++v) red[(w * 16 + v) * 64 + lane] = acc[m][v];
@@ -197,8 +208,7 @@ __global__ __launch_bounds__(512) void k_contract_mfma(MfmaArgs a) {
     if (has && kpart == 0 && row < a.N) {
       const float sc = a.out_scale ? a.out_scale[row] : 1.f;
 #pragma unroll
-      for (int m = 0; m < kMT; ++m) {
-        if (m >= MT) continue;
+      for (int m = 0; m < MT; ++m) {
 #pragma unroll
         for (int v = 0; v < 16; v += 2) {
           const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);  // even: the re part
@@ -215,15 +225,29 @@ __global__ __launch_bounds__(512) void k_contract_mfma(MfmaArgs a) {
   }
 }
 
+template <int MT>
+static void launch_mt(const MfmaArgs& a, int hdtype, dim3 grid, hipStream_t st) {
+  const size_t lds = (size_t)kTerms * kKC * MT * 64 * 16;
+  const size_t red = (size_t)kWaves * 16 * 64 * 4;  // k-part reduction buffer
+  const size_t bytes = lds > red ? lds : red;
+  if (hdtype == PAT_H_F16)
+    k_contract_mfma<true, MT><<<grid, kWaves * 64, bytes, st>>>(a);
+  else
+    k_contract_mfma<false, MT><<<grid, kWaves * 64, bytes, st>>>(a);
+}
+
 pat_status contract_mfma(const MfmaArgs& a, int hdtype, hipStream_t st) {
   if (a.nclass == 0 || a.B == 0) return PAT_OK;
-  const int groups = (a.G * a.B + kMT * 16 - 1) / (kMT * 16);
-  const size_t lds = (size_t)kTerms * kKC * kMT * 64 * 16;  // 64 KB; >= the k-part buffer
+  const int npairs = a.G * a.B;
+  const int groups = (npairs + kMT * 16 - 1) / (kMT * 16);
+  const int cols = 2 * (groups > 1 ? kMT * 16 : npairs);  // columns of the widest group
   dim3 grid(a.nclass, groups);
-  if (hdtype == PAT_H_F16)
-    k_contract_mfma<true><<<grid, kWaves * 64, lds, st>>>(a);
+  if (cols <= 32)
+    launch_mt<1>(a, hdtype, grid, st);
+  else if (cols <= 64)
+    launch_mt<2>(a, hdtype, grid, st);
   else
-    k_contract_mfma<false><<<grid, kWaves * 64, lds, st>>>(a);
+    launch_mt<4>(a, hdtype, grid, st);
   PAT_LAUNCHED("contraction (MFMA)");
   return PAT_OK;
 }
