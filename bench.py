@@ -132,6 +132,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-forms", action="store_true", help="skip the BF16/FP16/batch/FISTA forms")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
+    ap.add_argument("--serve-requests", type=int, default=120)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU; --gpus must be 1", file=sys.stderr)
@@ -186,6 +188,10 @@ def main():
 
     if not args.no_forms:
         out["forms"] = forms(op, x, x64, args)
+    if not args.no_serve:
+        del op
+        torch.cuda.empty_cache()
+        out["serving"] = serving(args)
     if not args.no_cpu:
         log("cpu baseline (oracle sample) ...")
         out["cpu_baseline"] = cpu_baseline(x64)
@@ -240,6 +246,96 @@ def forms(op, x, x64, args) -> dict:
             del o
         torch.cuda.empty_cache()
     return res
+
+
+def serving(args) -> dict:
+    """Poisson stream (mean 20 req/s) of 50-iteration FISTA reconstructions over
+    three geometries x {FP32, BF16} libraries; the same stream is served by the
+    plain FIFO (one request at a time, no batching) and by continuous batching.
+    Libraries are pre-built (cache warm); latency = completion - arrival."""
+    import torch
+    from paper_2603_28150_amd import inputs
+    from paper_2603_28150_amd.op import Geometry
+    from paper_2603_28150_amd.serve import HipBackend, Request, Server, run_fifo
+    geoms = [Geometry.paper_like(64, 64, 64, 256), Geometry.paper_like(128, 128, 96, 384),
+             Geometry.paper_like(256, 256, 128, 512)]
+    classes = [(g, k) for g in geoms for k in ("f32", "bf16")]
+    rng = np.random.default_rng(4001)
+    n = args.serve_requests
+    which = rng.integers(0, len(classes), n)
+    gaps = rng.exponential(1.0 / 20.0, n)
+    be = HipBackend()
+    warm = Server(be, hbm_budget=200 << 30, max_batch=16)
+    t0 = time.perf_counter()
+    for g, k in classes:
+        warm.submit(Request(geom=g, d=torch.zeros((g.nt, g.ny, g.nx), device="cuda"), niter=1, h_dtype=k))
+    warm.run_until_idle()
+    torch.cuda.synchronize()
+    t_cold = time.perf_counter() - t0
+    # request data: 4 seeded phantoms per class, 20 dB noise with a per-request seed
+    clean = {}
+    for ci, (g, k) in enumerate(classes):
+        op = warm.classes[(g, k)].op
+        clean[ci] = []
+        for j in range(4):
+            p0 = torch.from_numpy(inputs.vascular_phantom((g.nz, g.ny, g.nx), seed=5000 + 10 * ci + j)
+                                  .astype(np.float32)).cuda()
+            clean[ci].append(op.apply_A(p0))
+    reqs_data = []
+    for r in range(n):
+        ci = int(which[r])
+        g, k = classes[ci]
+        c = clean[ci][r % 4]
+        sig = float(torch.sqrt(torch.mean(c * c)))
+        noise = torch.from_numpy(inputs.noise_like((g.nt, g.ny, g.nx), seed=5000 + r).astype(np.float32)).cuda()
+        reqs_data.append((g, k, c + inputs.NOISE_20DB * sig * noise))
+    torch.cuda.synchronize()
+    out = {"library_cache_cold_build_s": t_cold, "requests": n, "rate_req_per_s": 20.0,
+           "iterations": 50, "classes": [f"{g.nx}x{g.ny}x{g.nz}x{g.nt}/{k}" for g, k in classes]}
+
+    def stream(srv):
+        reqs = [Request(geom=g, d=d, niter=50, h_dtype=k) for g, k, d in reqs_data]
+        t = time.perf_counter()
+        for r, gap in zip(reqs, gaps):
+            t += gap
+            r.t_arrival = t
+        return reqs
+
+    # continuous batching
+    srv = Server(be, hbm_budget=200 << 30, max_batch=16)
+    srv.classes = warm.classes          # warm library cache
+    srv.used = warm.used
+    reqs = stream(srv)
+    i = 0
+    while i < n or srv.poll():
+        now = time.perf_counter()
+        while i < n and reqs[i].t_arrival <= now:
+            srv.submit(reqs[i])
+            i += 1
+        if i < n and not srv.poll():
+            time.sleep(max(0.0, min(1e-3, reqs[i].t_arrival - time.perf_counter())))
+    torch.cuda.synchronize()
+    st = srv.stats()
+    out["batching"] = {k: st.get(k) for k in ("p50_s", "p99_s", "recon_per_s", "completed")}
+    out["batching"]["batch_hist"] = st["batch_hist"]
+    log(f"serving, continuous batching: {out['batching']}")
+    # plain FIFO on the same stream
+    fifo_reqs = stream(None)
+    srv2 = Server(be, hbm_budget=1 << 62, max_batch=1)
+    srv2.classes = {}
+    for key, cls in warm.classes.items():
+        srv2.classes[key] = cls
+        cls.cap, cls.pool, cls.ws, cls.active, cls.inflight = 0, {}, None, [], None
+    for r in fifo_reqs:
+        while time.perf_counter() < r.t_arrival:
+            pass
+        srv2.submit(r)
+        srv2.run_until_idle()
+    torch.cuda.synchronize()
+    st2 = srv2.stats()
+    out["fifo"] = {k: st2.get(k) for k in ("p50_s", "p99_s", "recon_per_s", "completed")}
+    log(f"serving, FIFO: {out['fifo']}")
+    return out
 
 
 if __name__ == "__main__":

@@ -222,8 +222,9 @@ class Operator:
                   _ptr(tr) if tr is not None else None, _ptr(ws), ws.numel(), _stream(self.device))
         return (out, tr[:niter]) if trace else out
 
-    def fista_step(self, d, x, z, beta, tau, lam, nonneg, nonfinite=None) -> None:
-        """One batched FISTA iteration in place on x and z ([B, nz, ny, nx])."""
+    def fista_step(self, d, x, z, beta, tau, lam, nonneg, nonfinite=None, ws=None) -> None:
+        """One batched FISTA iteration in place on x and z ([B, nz, ny, nx]).
+        ws: optional workspace tensor (at least workspace_bytes(B))."""
         B = x.shape[0]
         self._check(d, self.d_shape, "d")
         self._check(x, self.x_shape, "x")
@@ -232,7 +233,8 @@ class Operator:
         ct = (C.c_float * B)(*[float(t) for t in tau])
         cl = (C.c_float * B)(*[float(v) for v in lam])
         cn = (C.c_int32 * B)(*[int(bool(v)) for v in nonneg])
-        ws = self.workspace(B)
+        if ws is None:
+            ws = self.workspace(B)
         _lib.call("pat_fista_step", self.handle, B, _ptr(d), _ptr(x), _ptr(z), cb, ct, cl, cn,
                   _ptr(nonfinite) if nonfinite is not None else None, _ptr(ws), ws.numel(),
                   _stream(self.device))

@@ -1,0 +1,354 @@
+"""Continuous-batching reconstruction server.
+
+Requests are FISTA reconstructions (Sec. 2.3) on possibly different
+geometries and library precisions.  The unit of GPU work is one batched
+FISTA iteration of one (geometry, precision) class through `pat_fista_step`:
+every request carries its own iteration counter and momentum sequence, so
+requests join a class batch at the next iteration boundary after they are
+admitted and leave it the moment their last iteration is done.  Each class
+runs on its own stream, so batches of different classes overlap on the
+device.  The kernel library of every class is built once and cached; a
+request is admitted only if the HBM it needs (its slot in the class's state
+pool, plus the library and workspace when the class is new) fits the
+budget, evicting libraries of idle classes when necessary.
+
+The scheduler is written against a small backend interface (``HipBackend``
+here; the tests plug in a CPU float64 backend) so its logic can be checked
+without a GPU.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass, field
+
+import torch
+
+from .op import Geometry, Operator
+
+
+@dataclass
+class Request:
+    geom: Geometry
+    d: torch.Tensor                # [nt, ny, nx] data (device or host)
+    niter: int = 50
+    h_dtype: str = "f32"
+    lam: float = 0.0
+    nonneg: bool = True
+    tau: float | None = None       # None: 1/L from 30 power iterations of the class
+    rid: int = -1
+    t_arrival: float | None = None
+    t_admit: float | None = None
+    t_done: float | None = None
+    x: torch.Tensor | None = None  # result x_niter
+    status: str = "pending"        # pending | running | done | nonfinite | rejected
+
+    @property
+    def key(self):
+        return (self.geom, self.h_dtype)
+
+    @property
+    def latency(self):
+        return None if self.t_done is None else self.t_done - self.t_arrival
+
+
+@dataclass
+class _Slot:
+    req: Request
+    k: int = 0          # iterations done
+    t: float = 1.0      # FISTA t_k
+
+
+@dataclass
+class _Class:
+    key: tuple
+    op: object
+    tau: float
+    cap: int = 0
+    pool: dict = field(default_factory=dict)   # x, z, d, bad
+    ws: object = None
+    active: list = field(default_factory=list)  # slot i <-> row i of the pool
+    inflight: object = None                     # (event, n rows stepped)
+    keep: list = field(default_factory=list)    # buffers kept alive until the step ends
+    last_used: float = 0.0
+    bytes_lib: int = 0
+    bytes_pool: int = 0
+
+
+class HipBackend:
+    """GPU backend: libpat operators, torch-owned buffers, one stream per class."""
+
+    def __init__(self, device: int = 0):
+        self.device = torch.device("cuda", device)
+
+    def library_bytes(self, geom, h_dtype) -> int:
+        from .op import h_bytes
+        return h_bytes(geom, h_dtype)
+
+    def build(self, geom, h_dtype, stream):
+        with torch.cuda.stream(stream):
+            op = Operator(geom, h_dtype, device=self.device.index)
+        return op
+
+    def step_size(self, op, stream) -> float:
+        from . import inputs
+        with torch.cuda.stream(stream):
+            v0 = torch.from_numpy(inputs.gaussian_random(op.x_shape, seed=1002).astype("float32")).to(self.device)
+            L, _ = op.power_norm(v0, 30)
+        return 1.0 / L
+
+    def slot_bytes(self, op) -> int:
+        g = op.geom
+        return 4 * g.nx * g.ny * (2 * g.nz + g.nt) + 4
+
+    def workspace_bytes(self, op, cap) -> int:
+        return op.workspace_bytes(cap)
+
+    def new_stream(self):
+        return torch.cuda.Stream(device=self.device)
+
+    def alloc_pool(self, op, cap, stream):
+        g = op.geom
+        with torch.cuda.stream(stream):
+            return {"x": torch.zeros((cap,) + op.x_shape, device=self.device),
+                    "z": torch.zeros((cap,) + op.x_shape, device=self.device),
+                    "d": torch.zeros((cap,) + op.d_shape, device=self.device),
+                    "bad": torch.zeros(cap, dtype=torch.int32, device=self.device)}, \
+                torch.empty(op.workspace_bytes(cap), dtype=torch.uint8, device=self.device)
+
+    def load_row(self, pool, i, d, stream):
+        with torch.cuda.stream(stream):
+            pool["d"][i].copy_(d, non_blocking=True)
+            pool["x"][i].zero_()
+            pool["z"][i].zero_()
+            pool["bad"][i].zero_()
+
+    def move_row(self, pool, src, dst, stream):
+        with torch.cuda.stream(stream):
+            for name in ("x", "z", "d", "bad"):
+                pool[name][dst].copy_(pool[name][src])
+
+    def copy_rows(self, old, new, n, stream):
+        with torch.cuda.stream(stream):
+            for name in ("x", "z", "d", "bad"):
+                new[name][:n].copy_(old[name][:n])
+
+    def step(self, op, pool, ws, n, betas, taus, lams, nonnegs, stream):
+        with torch.cuda.stream(stream):
+            op.fista_step(pool["d"][:n], pool["x"][:n], pool["z"][:n], betas, taus, lams, nonnegs,
+                          nonfinite=pool["bad"][:n], ws=ws)
+            ev = torch.cuda.Event()
+            ev.record(stream)
+        return ev
+
+    def done(self, ev) -> bool:
+        return ev.query()
+
+    def take_result(self, pool, i, stream):
+        with torch.cuda.stream(stream):
+            x = pool["x"][i].clone()
+            bad = int(pool["bad"][i].item())
+        return x, bad != 0
+
+
+class Server:
+    def __init__(self, backend=None, hbm_budget: int = 64 << 30, max_batch: int = 16,
+                 clock=time.perf_counter):
+        self.be = backend if backend is not None else HipBackend()
+        self.budget = int(hbm_budget)
+        self.max_batch = int(max_batch)
+        self.clock = clock
+        self.classes: dict[tuple, _Class] = {}
+        self.pending: list[Request] = []
+        self.finished: list[Request] = []
+        self.used = 0
+        self.peak = 0
+        self.batch_hist: dict[int, int] = {}
+        self.streams: dict[tuple, object] = {}
+        self._rid = 0
+
+    # ------------------------------------------------------------ submit
+    def submit(self, req: Request) -> Request:
+        if req.rid < 0:
+            req.rid = self._rid
+            self._rid += 1
+        if req.t_arrival is None:
+            req.t_arrival = self.clock()
+        self.pending.append(req)
+        return req
+
+    # -------------------------------------------------------- accounting
+    def _charge(self, n: int):
+        self.used += n
+        self.peak = max(self.peak, self.used)
+
+    def _evict_idle(self, need: int, keep_key) -> bool:
+        idle = sorted((c for c in self.classes.values()
+                       if c.key != keep_key and not c.active and c.inflight is None
+                       and not any(r.key == c.key for r in self.pending)),
+                      key=lambda c: c.last_used)
+        for c in idle:
+            if self.used + need <= self.budget:
+                break
+            self._charge(-(c.bytes_lib + c.bytes_pool))
+            del self.classes[c.key]
+        return self.used + need <= self.budget
+
+    def _stream(self, key):
+        if key not in self.streams:
+            self.streams[key] = self.be.new_stream()
+        return self.streams[key]
+
+    def _open_class(self, req: Request):
+        key = req.key
+        lib = self.be.library_bytes(req.geom, req.h_dtype)
+        if lib > self.budget:
+            req.status = "rejected"
+            return None
+        if self.used + lib > self.budget and not self._evict_idle(lib, key):
+            return None
+        st = self._stream(key)
+        op = self.be.build(req.geom, req.h_dtype, st)
+        if lib + self.be.slot_bytes(op) + self.be.workspace_bytes(op, 1) > self.budget:
+            req.status = "rejected"       # one request of this class can never fit
+            return None
+        cls = _Class(key=key, op=op, tau=self.be.step_size(op, st), bytes_lib=lib)
+        self._charge(lib)
+        self.classes[key] = cls
+        return cls
+
+    def _grow(self, cls: _Class) -> bool:
+        new_cap = min(self.max_batch, max(1, 2 * cls.cap))
+        if new_cap <= cls.cap:
+            return False
+        need = new_cap * self.be.slot_bytes(cls.op) + self.be.workspace_bytes(cls.op, new_cap)
+        extra = need - cls.bytes_pool
+        if self.used + extra > self.budget and not self._evict_idle(extra, cls.key):
+            return False
+        st = self._stream(cls.key)
+        pool, ws = self.be.alloc_pool(cls.op, new_cap, st)
+        if cls.cap:
+            self.be.copy_rows(cls.pool, pool, len(cls.active), st)
+            cls.keep.append((cls.pool, cls.ws))
+        cls.pool, cls.ws, cls.cap = pool, ws, new_cap
+        self._charge(extra)
+        cls.bytes_pool = need
+        return True
+
+    # ------------------------------------------------------------ ticks
+    def _admit(self):
+        still = []
+        for req in self.pending:
+            cls = self.classes.get(req.key)
+            if cls is None:
+                cls = self._open_class(req)
+                if cls is None:
+                    if req.status != "rejected":
+                        still.append(req)
+                    else:
+                        self.finished.append(req)
+                    continue
+            if len(cls.active) >= cls.cap and not self._grow(cls):
+                still.append(req)
+                continue
+            i = len(cls.active)
+            st = self._stream(cls.key)
+            self.be.load_row(cls.pool, i, req.d, st)
+            cls.active.append(_Slot(req))
+            req.status = "running"
+            req.t_admit = self.clock()
+            if req.tau is None:
+                req.tau = cls.tau
+        self.pending = still
+
+    def _retire(self, cls: _Class):
+        ev, n = cls.inflight
+        if not self.be.done(ev):
+            return
+        cls.inflight = None
+        cls.keep.clear()
+        st = self._stream(cls.key)
+        finished = []
+        for i in range(n):
+            s = cls.active[i]
+            s.k += 1
+            if s.k >= s.req.niter:
+                finished.append(i)
+        now = self.clock()
+        for i in sorted(finished, reverse=True):
+            s = cls.active[i]
+            x, bad = self.be.take_result(cls.pool, i, st)
+            s.req.x = x
+            s.req.t_done = now
+            s.req.status = "nonfinite" if bad else "done"
+            self.finished.append(s.req)
+            last = len(cls.active) - 1
+            if i != last:
+                self.be.move_row(cls.pool, last, i, st)
+                cls.active[i] = cls.active[last]
+            cls.active.pop()
+
+    def _launch(self, cls: _Class):
+        n = len(cls.active)
+        if n == 0 or cls.inflight is not None:
+            return
+        betas, taus, lams, nns = [], [], [], []
+        for s in cls.active:
+            t_next = (1.0 + math.sqrt(1.0 + 4.0 * s.t * s.t)) / 2.0
+            betas.append((s.t - 1.0) / t_next)
+            s.t = t_next
+            taus.append(s.req.tau)
+            lams.append(s.req.lam)
+            nns.append(s.req.nonneg)
+        ev = self.be.step(cls.op, cls.pool, cls.ws, n, betas, taus, lams, nns, self._stream(cls.key))
+        cls.inflight = (ev, n)
+        cls.last_used = self.clock()
+        self.batch_hist[n] = self.batch_hist.get(n, 0) + 1
+
+    def poll(self) -> bool:
+        """One scheduler tick.  Returns True while work remains."""
+        for cls in list(self.classes.values()):
+            if cls.inflight is not None:
+                self._retire(cls)
+        self._admit()
+        for cls in self.classes.values():
+            self._launch(cls)
+        busy = any(c.active or c.inflight is not None for c in self.classes.values())
+        return busy or bool(self.pending)
+
+    def run_until_idle(self, sleep: float = 0.0):
+        while self.poll():
+            if sleep:
+                time.sleep(sleep)
+
+    # ------------------------------------------------------------ stats
+    def stats(self) -> dict:
+        lat = sorted(r.latency for r in self.finished if r.latency is not None)
+        out = {"completed": len(lat), "hbm_peak_bytes": self.peak, "batch_hist": dict(self.batch_hist)}
+        if lat:
+            out["p50_s"] = _pct(lat, 50)
+            out["p99_s"] = _pct(lat, 99)
+            span = max(r.t_done for r in self.finished if r.t_done) - min(r.t_arrival for r in self.finished)
+            out["recon_per_s"] = len(lat) / span if span > 0 else float("inf")
+        return out
+
+
+def _pct(sorted_vals, p):
+    if not sorted_vals:
+        return None
+    k = (len(sorted_vals) - 1) * p / 100.0
+    lo, hi = math.floor(k), math.ceil(k)
+    return sorted_vals[lo] + (sorted_vals[hi] - sorted_vals[lo]) * (k - lo)
+
+
+def run_fifo(backend, requests, clock=time.perf_counter):
+    """Baseline: one request at a time in arrival order, no batching; requests
+    arrive on their own schedule (t_arrival) and wait for the GPU."""
+    srv = Server(backend, hbm_budget=1 << 62, max_batch=1, clock=clock)
+    order = sorted(requests, key=lambda r: r.t_arrival)
+    for r in order:
+        while clock() < r.t_arrival:
+            pass
+        srv.submit(r)
+        srv.run_until_idle()
+    return srv

@@ -1,0 +1,69 @@
+"""Serving form on the GPU: every request's result is the same alone and in a
+mix of geometries and library precisions (continuous batching)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import hlib, operators as ops, solvers
+from oracle.geometry import Geometry as OGeom
+from paper_2603_28150_amd import inputs
+from paper_2603_28150_amd.op import Geometry
+from paper_2603_28150_amd.serve import HipBackend, Request, Server
+
+pytestmark = pytest.mark.gpu
+
+GA = Geometry.paper_like(64, 64, 64, 256)
+GB = Geometry.paper_like(32, 32, 16, 64)
+
+
+def _data(g, seed):
+    o = OGeom(g.nx, g.ny, g.nz, g.nt, g.dx, g.dy, g.dz, g.dt, g.c)
+    Hh = hlib.H_half(o)
+    p0 = inputs.vascular_phantom((g.nz, g.ny, g.nx), seed=seed, n_tubes=6)
+    clean = ops.A_fft(Hh, p0)
+    d = clean + inputs.NOISE_20DB * np.sqrt(np.mean(clean ** 2)) * inputs.noise_like(clean.shape, seed=seed + 1)
+    return torch.from_numpy(d.astype(np.float32)).cuda(), Hh, d
+
+
+def rel(a, b):
+    return float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+
+
+def test_results_alone_equal_results_in_the_mix():
+    plan = [(GA, "f32", 12), (GB, "f32", 20), (GA, "bf16", 9), (GA, "f32", 15), (GB, "f32", 7),
+            (GA, "bf16", 11), (GA, "f32", 5), (GB, "bf16", 8)]
+    datas = [_data(g, 500 + 7 * i)[0] for i, (g, _, _) in enumerate(plan)]
+    srv = Server(HipBackend(), hbm_budget=8 << 30, max_batch=4)
+    reqs = []
+    for i, ((g, kind, n), d) in enumerate(zip(plan, datas)):
+        r = Request(geom=g, d=d, niter=n, h_dtype=kind, lam=1e-3 * (i % 3))
+        srv.submit(r)
+        reqs.append(r)
+        for _ in range(3):
+            srv.poll()               # later requests arrive while earlier ones run
+    srv.run_until_idle()
+    torch.cuda.synchronize()
+    st = srv.stats()
+    assert st["completed"] == len(plan)
+    assert max(st["batch_hist"]) > 1
+    for r, d in zip(reqs, datas):
+        assert r.status == "done"
+        alone = Server(HipBackend(), hbm_budget=8 << 30, max_batch=4)
+        a = alone.submit(Request(geom=r.geom, d=d, niter=r.niter, h_dtype=r.h_dtype, lam=r.lam))
+        alone.run_until_idle()
+        torch.cuda.synchronize()
+        assert a.tau == r.tau
+        assert rel(r.x, a.x) < 1e-5, (r.rid, r.h_dtype)
+
+
+def test_served_fista_matches_oracle():
+    d, Hh, d64 = _data(GB, 77)
+    srv = Server(HipBackend(), hbm_budget=4 << 30)
+    r = srv.submit(Request(geom=GB, d=d, niter=15))
+    srv.run_until_idle()
+    torch.cuda.synchronize()
+    A = lambda v: ops.A_fft(Hh, v)
+    AT = lambda v: ops.AT_fft(Hh, v)
+    xo = solvers.fista(A, AT, d.double().cpu().numpy(), (GB.nz, GB.ny, GB.nx), 15, float(np.float32(r.tau)), 0.0)[-1]
+    xg = r.x.double().cpu().numpy()
+    assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) < 1e-5

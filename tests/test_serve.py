@@ -1,0 +1,198 @@
+"""Scheduler logic of the continuous-batching server (CPU, float64 fake device)."""
+import numpy as np
+import pytest
+
+from oracle import hlib, operators as ops, solvers
+from oracle.geometry import Geometry as OGeom
+from paper_2603_28150_amd import inputs
+from paper_2603_28150_amd.op import Geometry
+from paper_2603_28150_amd.serve import Request, Server, run_fifo
+
+
+class _Ev:
+    def __init__(self, t):
+        self.t = t
+
+
+class CpuBackend:
+    """Same interface as HipBackend; every step runs at once in float64 and
+    the library/slot sizes are the real ones of the float32 layouts."""
+
+    def __init__(self, clock):
+        self.clock = clock
+        self.built = []
+
+    def _og(self, g):
+        return OGeom(g.nx, g.ny, g.nz, g.nt, g.dx, g.dy, g.dz, g.dt, g.c, g.nz_sim)
+
+    def library_bytes(self, geom, h_dtype):
+        nh = geom.nx // 2 + 1
+        return nh * geom.ny * geom.nz * geom.nt * (4 if h_dtype == "f32" else 2)
+
+    def build(self, geom, h_dtype, stream):
+        self.built.append((geom, h_dtype))
+
+        class Op:
+            pass
+        op = Op()
+        op.geom = geom
+        op.Hh = hlib.H_half(self._og(geom))
+        op.x_shape = (geom.nz, geom.ny, geom.nx)
+        op.d_shape = (geom.nt, geom.ny, geom.nx)
+        return op
+
+    def step_size(self, op, stream):
+        return 1.0 / solvers.norm_exact(op.Hh)
+
+    def slot_bytes(self, op):
+        g = op.geom
+        return 4 * g.nx * g.ny * (2 * g.nz + g.nt)
+
+    def workspace_bytes(self, op, cap):
+        return 0
+
+    def new_stream(self):
+        return None
+
+    def alloc_pool(self, op, cap, stream):
+        return {"x": np.zeros((cap,) + op.x_shape), "z": np.zeros((cap,) + op.x_shape),
+                "d": np.zeros((cap,) + op.d_shape), "bad": np.zeros(cap, dtype=int)}, None
+
+    def load_row(self, pool, i, d, stream):
+        pool["d"][i] = d
+        pool["x"][i] = 0
+        pool["z"][i] = 0
+        pool["bad"][i] = 0
+
+    def move_row(self, pool, src, dst, stream):
+        for k in pool:
+            pool[k][dst] = pool[k][src]
+
+    def copy_rows(self, old, new, n, stream):
+        for k in old:
+            new[k][:n] = old[k][:n]
+
+    def step(self, op, pool, ws, n, betas, taus, lams, nonnegs, stream):
+        for i in range(n):
+            x_prev, z = pool["x"][i].copy(), pool["z"][i].copy()
+            with np.errstate(all="ignore"):
+                x = solvers.fista(lambda v: ops.A_fft(op.Hh, v), lambda v: ops.AT_fft(op.Hh, v),
+                                  pool["d"][i], op.x_shape, 1, taus[i], lams[i], nonneg=nonnegs[i],
+                                  momentum=False, z0=z, x_prev0=x_prev)[0]
+                pool["z"][i] = x + betas[i] * (x - x_prev)
+            pool["x"][i] = x
+            if not np.all(np.isfinite(x)):
+                pool["bad"][i] = 1
+        return _Ev(self.clock())
+
+    def done(self, ev):
+        return True
+
+    def take_result(self, pool, i, stream):
+        return pool["x"][i].copy(), bool(pool["bad"][i])
+
+
+G1 = Geometry.paper_like(16, 16, 8, 24)
+G2 = Geometry.paper_like(32, 16, 6, 20)
+
+
+def _req(g, seed, niter, **kw):
+    o = OGeom(g.nx, g.ny, g.nz, g.nt, g.dx, g.dy, g.dz, g.dt, g.c)
+    Hh = hlib.H_half(o)
+    p0 = inputs.gaussian_blobs((g.nz, g.ny, g.nx), seed=seed)
+    clean = ops.A_fft(Hh, p0)
+    d = clean + inputs.NOISE_20DB * np.sqrt(np.mean(clean ** 2)) * inputs.noise_like(clean.shape, seed=seed + 1)
+    return Request(geom=g, d=d, niter=niter, **kw), Hh
+
+
+class Clock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        self.t += 1e-3
+        return self.t
+
+
+def _standalone(Hh, d, niter, tau, lam=0.0, nonneg=True):
+    return solvers.fista(lambda v: ops.A_fft(Hh, v), lambda v: ops.AT_fft(Hh, v), d,
+                         (d.shape[0] and Hh.shape[2], Hh.shape[0], 2 * (Hh.shape[1] - 1)),
+                         niter, tau, lam, nonneg=nonneg)[-1]
+
+
+def test_mixed_requests_equal_standalone_fista():
+    clock = Clock()
+    srv = Server(CpuBackend(clock), hbm_budget=1 << 40, max_batch=4, clock=clock)
+    reqs = []
+    for i, (g, n) in enumerate([(G1, 5), (G2, 7), (G1, 9), (G1, 3), (G2, 4), (G1, 6)]):
+        r, Hh = _req(g, 100 + 10 * i, n, lam=0.01 * (i % 2))
+        reqs.append((r, Hh))
+        srv.submit(r)
+        srv.poll()                      # requests arrive while others run
+    srv.run_until_idle()
+    for r, Hh in reqs:
+        assert r.status == "done"
+        ref = _standalone(Hh, r.d, r.niter, r.tau, r.lam)
+        assert np.array_equal(r.x, ref), r.rid
+    st = srv.stats()
+    assert st["completed"] == 6 and st["p99_s"] >= st["p50_s"] > 0
+    assert max(st["batch_hist"]) > 1     # batching did happen
+
+
+def test_admission_respects_the_hbm_budget():
+    clock = Clock()
+    be = CpuBackend(clock)
+    lib1, lib2 = be.library_bytes(G1, "f32"), be.library_bytes(G2, "f32")
+    slot1 = 4 * 16 * 16 * (2 * 8 + 24)
+    slot2 = 4 * 32 * 16 * (2 * 6 + 20)
+    # room for the G1 library with two slots, or the G2 library with one
+    budget = max(lib1 + 2 * slot1, lib2 + slot2) + 1000
+    assert lib1 + 4 * slot1 > budget and lib1 + lib2 + slot2 > budget
+    srv = Server(be, hbm_budget=budget, max_batch=8, clock=clock)
+    r1, _ = _req(G1, 1, 4)
+    r2, _ = _req(G1, 2, 4)
+    r3, _ = _req(G1, 3, 4)
+    r4, _ = _req(G2, 4, 3)
+    for r in (r1, r2, r3, r4):
+        srv.submit(r)
+    srv.poll()
+    assert srv.used <= srv.budget
+    assert r3.status == "pending" and r4.status == "pending"   # no room yet
+    srv.run_until_idle()
+    assert all(r.status == "done" for r in (r1, r2, r3, r4))
+    assert srv.peak <= srv.budget
+    assert be.built.count((G1, "f32")) >= 1 and (G2, "f32") in be.built
+
+
+def test_oversized_request_is_rejected():
+    clock = Clock()
+    srv = Server(CpuBackend(clock), hbm_budget=1000, clock=clock)
+    r, _ = _req(G1, 5, 2)
+    srv.submit(r)
+    srv.run_until_idle()
+    assert r.status == "rejected" and r.x is None
+
+
+def test_nonfinite_request_is_isolated():
+    clock = Clock()
+    srv = Server(CpuBackend(clock), hbm_budget=1 << 40, max_batch=4, clock=clock)
+    good, Hh = _req(G1, 7, 6)
+    bad, _ = _req(G1, 8, 80)
+    srv.submit(good)
+    srv.submit(bad)
+    srv.poll()
+    bad.tau = 1e6 * good.tau            # far beyond 2/L: the iterate overflows
+    srv.run_until_idle()
+    assert good.status == "done"
+    assert np.array_equal(good.x, _standalone(Hh, good.d, 6, good.tau))
+    assert bad.status == "nonfinite"
+
+
+def test_fifo_baseline_runs_one_at_a_time():
+    clock = Clock()
+    reqs = [_req(G1, 20 + i, 3)[0] for i in range(3)]
+    for i, r in enumerate(reqs):
+        r.t_arrival = 0.0
+    srv = run_fifo(CpuBackend(clock), reqs, clock=clock)
+    assert set(srv.batch_hist) == {1}
+    assert all(r.status == "done" for r in reqs)
