@@ -54,29 +54,33 @@ def time_pairs(op, x, steps, warmup, B=1):
     gx = torch.empty_like(x)
 
     def pair(ev=None):
-        op.spectrum(x, Sz, Xs, B_ws=B)
         if ev: ev[0].record()
-        op.contract(Xs, Ds, adjoint=False, B=B)
+        op.spectrum(x, Sz, Xs, B_ws=B)
         if ev: ev[1].record()
-        op.inverse_spectrum(Ds, St, y, B_ws=B)
-        op.spectrum(y, St, Ds, B_ws=B)
+        op.contract(Xs, Ds, adjoint=False, B=B)
         if ev: ev[2].record()
-        op.contract(Ds, Xs, adjoint=True, B=B)
+        op.inverse_spectrum(Ds, St, y, B_ws=B)
         if ev: ev[3].record()
+        op.spectrum(y, St, Ds, B_ws=B)
+        if ev: ev[4].record()
+        op.contract(Ds, Xs, adjoint=True, B=B)
+        if ev: ev[5].record()
         op.inverse_spectrum(Xs, Sz, gx, B_ws=B)
+        if ev: ev[6].record()
 
     for _ in range(warmup):
         pair()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
         pair(evs[k])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    tA = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
-    tAT = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
-    return t1 - t0, tA, tAT
+    el = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(6)] for e in evs]).mean(axis=0)
+    log("  stage ms (spec_z, contract_A, ispec_t, spec_t, contract_AT, ispec_z): "
+        + ", ".join(f"{v:.3f}" for v in el))
+    return t1 - t0, float(el[1]), float(el[4])
 
 
 def cpu_baseline(x64: np.ndarray, budget_s: float = 12.0) -> dict:
@@ -134,6 +138,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="skip the BF16/FP16/batch/FISTA forms")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
     ap.add_argument("--serve-requests", type=int, default=120)
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a device copy of 1 GiB (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU; --gpus must be 1", file=sys.stderr)
@@ -144,6 +150,13 @@ def main():
     from paper_2603_28150_amd.op import Geometry, Operator
 
     torch.cuda.set_device(0)
+    if args.copy_calib:
+        a = torch.ones(1 << 28, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     geom = Geometry.paper_like(**BIG)
     t0 = time.perf_counter()
     op = Operator(geom, "f32")

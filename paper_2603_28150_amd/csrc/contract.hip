@@ -159,6 +159,11 @@ __global__ __launch_bounds__(256) void k_contract(ContractArgs a, int lr_log2) {
     }
   }
 
+  // stage the G output rows in LDS, then store each row contiguously (whole
+  // cache lines per store instruction); rows of empty member slots are unused
+  // spectrum rows and receive zeros
+  __syncthreads();
+  float2* ob = reinterpret_cast<float2*>(smem_raw);
   if (rg == 0) {
 #pragma unroll
     for (int jj = 0; jj < JPT; ++jj) {
@@ -169,12 +174,16 @@ __global__ __launch_bounds__(256) void k_contract(ContractArgs a, int lr_log2) {
         const float sc = a.out_scale ? a.out_scale[j] : 1.f;
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-          if (kg[g] < 0) continue;
           const float* p = &acc[((jj * VEC + v) * G + g) * 2];
-          a.out[(size_t)(c * G + g) * a.out_rs + (size_t)b * a.nj + j] = make_float2(p[0] * sc, p[1] * sc);
+          ob[g * a.nj + j] = make_float2(p[0] * sc, p[1] * sc);
         }
       }
     }
+  }
+  __syncthreads();
+  for (int e = tid; e < G * a.nj; e += 256) {
+    const int g = e / a.nj, j = e - g * a.nj;
+    a.out[(size_t)(c * G + g) * a.out_rs + (size_t)b * a.nj + j] = ob[e];
   }
 }
 
@@ -190,7 +199,9 @@ static pat_status launch_t(const ContractArgs& a, int B, hipStream_t st) {
   const int ns = jpt * VEC * G * 2;
   size_t red_bytes = R > 1 ? (size_t)(R / 2) * Lr * ns * sizeof(float) : 0;
   size_t in_bytes = (size_t)a.ni * G * sizeof(float2);
+  size_t out_bytes = (size_t)a.nj * G * sizeof(float2);
   size_t lds = red_bytes > in_bytes ? red_bytes : in_bytes;
+  lds = lds > out_bytes ? lds : out_bytes;
   if (lds > 160 * 1024) return fail(PAT_EUNSUPPORTED, "contraction input vector does not fit in LDS");
   dim3 grid(a.nclass, B);
   if (jpt == 1)

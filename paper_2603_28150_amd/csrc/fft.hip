@@ -58,8 +58,8 @@ __global__ __launch_bounds__(256) void k_fft_cols(const float2* __restrict__ in,
   __shared__ int rin[N], rout[N];
   const int tid = threadIdx.x;
   const int s = tid % SB, t = tid / SB;
-  const int m = blockIdx.x;
-  const int sg = blockIdx.y * SB + s;
+  const int m = blockIdx.y;
+  const int sg = blockIdx.x * SB + s;
   const bool live = sg < S;
   load_twiddles<N, DIR>(tw, tid, NT);
   for (int y = tid; y < N; y += NT) {
@@ -94,6 +94,9 @@ __global__ __launch_bounds__(256) void k_fft_cols(const float2* __restrict__ in,
 
 // ---------------------------------------------------------- rows, r2c (x)
 // T[(j*nh + m)*rs + s] = sum_i exp(-2 pi i m i / N) f[s][j][i],  m = 0..N/2
+// The 32 rows of a block are read with 16-byte loads into LDS, packed in
+// pairs as z = f[2q] + i f[2q+1]; after the transform the two real spectra are
+// separated and written slice-fastest (contiguous across threads).
 template <int N>
 __global__ __launch_bounds__(256) void k_fft_rows_r2c(const float* __restrict__ f,
                                                       float2* __restrict__ T, int ny, int S,
@@ -109,18 +112,37 @@ __global__ __launch_bounds__(256) void k_fft_rows_r2c(const float* __restrict__ 
   const int t = tid % N1, q = tid / N1;
   const int j = blockIdx.x;
   const int s0 = blockIdx.y * 2 * Q;
-  const int sa = s0 + 2 * q, sb = sa + 1;
   load_twiddles<N, -1>(tw, tid, NT);
+  // rows of the block: 2Q rows x N/4 float4, every load issued before any LDS store
+  constexpr int LIT = (2 * Q * (N / 4) + NT - 1) / NT;
+  float4 ld[LIT];
+#pragma unroll
+  for (int it = 0; it < LIT; ++it) {
+    const int u = tid + it * NT;
+    const int row = u / (N / 4), c4 = u % (N / 4);
+    const int s = s0 + row;
+    ld[it] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (u < 2 * Q * (N / 4) && s < S) ld[it] = reinterpret_cast<const float4*>(f + ((size_t)s * ny + j) * N)[c4];
+  }
+#pragma unroll
+  for (int it = 0; it < LIT; ++it) {
+    const int u = tid + it * NT;
+    if (u >= 2 * Q * (N / 4)) break;
+    const int row = u / (N / 4), c4 = u % (N / 4);
+    float* z = reinterpret_cast<float*>(ex + (row >> 1) * PAD + 4 * c4) + (row & 1);
+    z[0] = ld[it].x;
+    z[2] = ld[it].y;
+    z[4] = ld[it].z;
+    z[6] = ld[it].w;
+  }
   __syncthreads();
   float2 v[N1];
   if (t < N2) {
-    const float* ra = f + ((size_t)sa * ny + j) * N;
-    const float* rb = f + ((size_t)sb * ny + j) * N;
 #pragma unroll
-    for (int n1 = 0; n1 < N1; ++n1) {
-      const int i = t + N2 * n1;
-      v[n1] = make_float2(sa < S ? ra[i] : 0.f, sb < S ? rb[i] : 0.f);
-    }
+    for (int n1 = 0; n1 < N1; ++n1) v[n1] = ex[q * PAD + t + N2 * n1];
+  }
+  __syncthreads();
+  if (t < N2) {
     dft<N1, -1>(v);
 #pragma unroll
     for (int k1 = 0; k1 < N1; ++k1) ex[q * PAD + t * N1 + k1] = cmul(v[k1], tw[t * k1]);
@@ -166,16 +188,28 @@ __global__ __launch_bounds__(256) void k_fft_rows_c2r(const float2* __restrict__
   constexpr int PAD = N + 1;
   constexpr int NT = Q * N1;
   constexpr int NH = N / 2 + 1;
-  constexpr int BUF = (2 * Q * NH > Q * PAD) ? 2 * Q * NH : Q * PAD;
+  constexpr int BUF0 = (2 * Q * NH > Q * PAD) ? 2 * Q * NH : Q * PAD;
+  constexpr int BUF = (BUF0 * 2 > 2 * Q * (N + 4)) ? BUF0 : (2 * Q * (N + 4) + 1) / 2;
   __shared__ float2 tw[N];
   __shared__ float2 buf[BUF];
   const int tid = threadIdx.x;
   const int j = blockIdx.x;
   const int s0 = blockIdx.y * 2 * Q;
-  for (int idx = tid; idx < NH * 2 * Q; idx += NT) {
+  constexpr int LIT = (NH * 2 * Q + NT - 1) / NT;
+  float2 ld[LIT];
+#pragma unroll
+  for (int it = 0; it < LIT; ++it) {
+    const int idx = tid + it * NT;
     const int m = idx / (2 * Q), sl = idx % (2 * Q);
     const int s = s0 + sl;
-    float2 F = s < S ? T[(size_t)(j * NH + m) * rs + s] : make_float2(0.f, 0.f);
+    ld[it] = (idx < NH * 2 * Q && s < S) ? T[(size_t)(j * NH + m) * rs + s] : make_float2(0.f, 0.f);
+  }
+#pragma unroll
+  for (int it = 0; it < LIT; ++it) {
+    const int idx = tid + it * NT;
+    if (idx >= NH * 2 * Q) break;
+    const int m = idx / (2 * Q), sl = idx % (2 * Q);
+    float2 F = ld[it];
     if (m == 0 || m == N / 2) F.y = 0.f;
     buf[sl * NH + m] = F;
   }
@@ -211,18 +245,43 @@ __global__ __launch_bounds__(256) void k_fft_rows_c2r(const float2* __restrict__
 #pragma unroll
   for (int n2 = 0; n2 < N2; ++n2) w[n2] = buf[q * PAD + n2 * N1 + t];
   dft<N2, +1>(w);
-  const int sa = s0 + 2 * q, sb = sa + 1;
+  __syncthreads();
+  // real rows 2q (re) and 2q+1 (im) into LDS, then 16-byte row stores
+  float* rows = reinterpret_cast<float*>(buf);
 #pragma unroll
   for (int k2 = 0; k2 < N2; ++k2) {
     const int i = t + N1 * k2;
-    if (sa < S) {
-      const size_t o = ((size_t)sa * ny + j) * N + i;
-      f[o] = w[k2].x * scale - (sub ? sub[o] : 0.f);
+    rows[(2 * q) * (N + 4) + i] = w[k2].x;
+    rows[(2 * q + 1) * (N + 4) + i] = w[k2].y;
+  }
+  __syncthreads();
+  constexpr int SIT = (2 * Q * (N / 4) + NT - 1) / NT;
+  float4 sb4[SIT];
+  if (sub) {
+#pragma unroll
+    for (int it = 0; it < SIT; ++it) {
+      const int u = tid + it * NT;
+      const int row = u / (N / 4), c4 = u % (N / 4);
+      const int s = s0 + row;
+      sb4[it] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (u < 2 * Q * (N / 4) && s < S) sb4[it] = reinterpret_cast<const float4*>(sub + ((size_t)s * ny + j) * N)[c4];
     }
-    if (sb < S) {
-      const size_t o = ((size_t)sb * ny + j) * N + i;
-      f[o] = w[k2].y * scale - (sub ? sub[o] : 0.f);
+  }
+#pragma unroll
+  for (int it = 0; it < SIT; ++it) {
+    const int u = tid + it * NT;
+    const int row = u / (N / 4), c4 = u % (N / 4);
+    const int s = s0 + row;
+    if (u >= 2 * Q * (N / 4) || s >= S) continue;
+    const float4 r = *reinterpret_cast<const float4*>(rows + row * (N + 4) + 4 * c4);
+    float4 v = make_float4(r.x * scale, r.y * scale, r.z * scale, r.w * scale);
+    if (sub) {
+      v.x -= sb4[it].x;
+      v.y -= sb4[it].y;
+      v.z -= sb4[it].z;
+      v.w -= sb4[it].w;
     }
+    reinterpret_cast<float4*>(f + ((size_t)s * ny + j) * N)[c4] = v;
   }
 }
 
@@ -230,7 +289,7 @@ __global__ __launch_bounds__(256) void k_fft_rows_c2r(const float2* __restrict__
 template <int N, int DIR>
 static void launch_cols(const float2* in, float2* out, int nh, int S, int rs, const int32_t* imap,
                         const int32_t* omap, hipStream_t st) {
-  dim3 grid(nh, (S + 15) / 16);
+  dim3 grid((S + 15) / 16, nh);
   k_fft_cols<N, DIR><<<grid, 16 * Split<N>::N1, 0, st>>>(in, out, nh, S, rs, imap, omap);
 }
 
