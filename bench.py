@@ -35,10 +35,11 @@ def log(*a):
 
 
 def contraction_bytes(info: dict, nk: int, nz: int, nt: int, adjoint: bool, B: int = 1) -> int:
-    """Algorithmic bytes of one contraction launch: every stored slab once,
-    the input spectrum read once and the output spectrum written once (nk
-    frequencies; unused spectrum rows are neither read nor written)."""
-    slab = info["slab_bytes_AT"] if adjoint else info["slab_bytes_A"]
+    """Algorithmic bytes of one contraction launch: the library slab of every
+    work item once (read_bytes), the input spectrum read once and the output
+    spectrum written once (nk frequencies; unused spectrum rows are neither
+    read nor written)."""
+    slab = info["read_bytes_AT"] if adjoint else info["read_bytes_A"]
     return slab + B * nk * (nz + nt) * 8
 
 

@@ -117,13 +117,17 @@ pat_status pat_op_destroy(pat_op* op);
 pat_status pat_H_export(pat_op* op, int32_t k0, int32_t nk, float* out, void* stream);
 
 /* Shape of the stored library: nk half-spectrum frequencies, nclass stored
- * slabs (symmetry classes) with up to members_max frequencies each, the
- * z-period used, and the bytes of one stored layout (nclass slabs; the
- * library keeps two layouts, [l][n] for A and [n][l] for A^T). */
+ * slabs (symmetry classes: frequencies with equal kx^2 + ky^2 share one), the
+ * z-period used, and the bytes of one stored layout (the library keeps two,
+ * rows along n for A and along l for A^T).  The contraction runs over
+ * nitems work items of up to members_max frequencies; each streams one slab,
+ * so one apply reads read_bytes_A (or read_bytes_AT) of library. */
 typedef struct {
   int32_t nk, nclass, members_max, nz_sim;
   size_t slab_bytes_A, slab_bytes_AT;
-  int32_t spec_rows; /* rows of a spectrum array (see pat_spectrum), = nclass * members_max */
+  int32_t spec_rows; /* rows of a spectrum array (see pat_spectrum) = nitems * members_max */
+  int32_t nitems;
+  size_t read_bytes_A, read_bytes_AT;
 } pat_op_info;
 pat_status pat_get_info(const pat_op* op, pat_op_info* info);
 

@@ -7,8 +7,8 @@
 // library keeps one slab per class in two layouts, [l][n] for A and [n][l] for
 // A^T.  Both products then have the same shape: the summed index i runs over
 // slab rows, the kept index j runs along a row, and one workgroup streams one
-// slab exactly once while applying it to every member frequency of the class
-// (up to four).  Streaming the slab is the whole cost (it is >95 % of the bytes
+// slab exactly once while applying it to every member frequency of its work
+// item (up to eight).  Streaming the slab is the whole cost (it is >95 % of the bytes
 // an apply moves), so the kernel is built around 16-byte non-temporal loads
 // of whole rows: lanes of a row group cover one row, row groups take
 // interleaved rows, and a short LDS tree adds the row-group partial sums at
@@ -54,35 +54,31 @@ template <> struct Slab<f16_t> {
   }
 };
 
-template <typename HT, int G, int JPT>
-__global__ __launch_bounds__(256) void k_contract(ContractArgs a, int lr_log2) {
+// One work item: GG active member slots (GG <= G, the slot count of the
+// spectrum rows).  Uniform per workgroup.
+template <typename HT, int G, int GG, int JPT>
+__device__ __forceinline__ void contract_item(const ContractArgs& a, int lr_log2, int t, int b,
+                                              const int (&kg)[G], float4* smem_raw) {
   typedef Slab<HT> SL;
   typedef typename SL::raw_t raw_t;
   constexpr int VEC = SL::VEC;
-  constexpr int U = 8 / JPT;               // rows in flight per thread
-  constexpr int NS = JPT * VEC * G * 2;    // accumulators per thread
-  extern __shared__ float4 smem_raw[];
+  constexpr int U = 8 / JPT;                // rows in flight per thread
+  constexpr int NS = JPT * VEC * GG * 2;    // accumulators per thread
   float2* xin = reinterpret_cast<float2*>(smem_raw);
   float* red = reinterpret_cast<float*>(smem_raw);
-
   const int tid = threadIdx.x;
-  const int c = blockIdx.x, b = blockIdx.y;
   const int Lr = 1 << lr_log2, R = 256 >> lr_log2;
   const int lr = tid & (Lr - 1), rg = tid >> lr_log2;
 
-  int kg[G];
-#pragma unroll
-  for (int g = 0; g < G; ++g) kg[g] = a.members[c * G + g];
-
   // member input vectors, [i][g], with the optional per-row scale applied
-  for (int idx = tid; idx < a.ni * G; idx += 256) {
-    const int i = idx / G, g = idx % G;
+  for (int idx = tid; idx < a.ni * GG; idx += 256) {
+    const int i = idx / GG, g = idx % GG;
     int k = -1;
 #pragma unroll
-    for (int gg = 0; gg < G; ++gg) k = (gg == g) ? kg[gg] : k;
+    for (int gg = 0; gg < GG; ++gg) k = (gg == g) ? kg[gg] : k;
     float2 v = make_float2(0.f, 0.f);
     if (k >= 0) {
-      v = a.in[(size_t)(c * G + g) * a.in_rs + (size_t)b * a.ni + i];
+      v = a.in[(size_t)(t * G + g) * a.in_rs + (size_t)b * a.ni + i];
       if (a.in_scale) v = cscale(v, a.in_scale[i]);
     }
     xin[idx] = v;
@@ -93,7 +89,7 @@ __global__ __launch_bounds__(256) void k_contract(ContractArgs a, int lr_log2) {
 #pragma unroll
   for (int s = 0; s < NS; ++s) acc[s] = 0.f;
 
-  const HT* slab = reinterpret_cast<const HT*>(a.slab) + (size_t)c * a.slab_elems;
+  const HT* slab = reinterpret_cast<const HT*>(a.slab) + (size_t)a.item_slab[t] * a.slab_elems;
   const int nchunks = (a.nj + VEC - 1) / VEC;
   bool cl[JPT];
   const HT* colp[JPT];
@@ -123,17 +119,17 @@ __global__ __launch_bounds__(256) void k_contract(ContractArgs a, int lr_log2) {
     for (int u = 0; u < U; ++u) {
       const int i = i0 + u * R;
       if (i >= a.ni) break;
-      float2 xv[G];
+      float2 xv[GG];
 #pragma unroll
-      for (int g = 0; g < G; ++g) xv[g] = xin[i * G + g];
+      for (int g = 0; g < GG; ++g) xv[g] = xin[i * GG + g];
 #pragma unroll
       for (int jj = 0; jj < JPT; ++jj) {
 #pragma unroll
         for (int v = 0; v < VEC; ++v) {
           const float h = SL::get(raw[u][jj], v);
 #pragma unroll
-          for (int g = 0; g < G; ++g) {
-            float* p = &acc[((jj * VEC + v) * G + g) * 2];
+          for (int g = 0; g < GG; ++g) {
+            float* p = &acc[((jj * VEC + v) * GG + g) * 2];
             p[0] = fmaf(h, xv[g].x, p[0]);
             p[1] = fmaf(h, xv[g].y, p[1]);
           }
@@ -159,9 +155,8 @@ __global__ __launch_bounds__(256) void k_contract(ContractArgs a, int lr_log2) {
     }
   }
 
-  // stage the G output rows in LDS, then store each row contiguously (whole
-  // cache lines per store instruction); rows of empty member slots are unused
-  // spectrum rows and receive zeros
+  // stage the member rows in LDS, then store each row contiguously (whole
+  // cache lines per store instruction)
   __syncthreads();
   float2* ob = reinterpret_cast<float2*>(smem_raw);
   if (rg == 0) {
@@ -173,18 +168,37 @@ __global__ __launch_bounds__(256) void k_contract(ContractArgs a, int lr_log2) {
         if (j >= a.nj) continue;
         const float sc = a.out_scale ? a.out_scale[j] : 1.f;
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-          const float* p = &acc[((jj * VEC + v) * G + g) * 2];
+        for (int g = 0; g < GG; ++g) {
+          const float* p = &acc[((jj * VEC + v) * GG + g) * 2];
           ob[g * a.nj + j] = make_float2(p[0] * sc, p[1] * sc);
         }
       }
     }
   }
   __syncthreads();
-  for (int e = tid; e < G * a.nj; e += 256) {
+  for (int e = tid; e < GG * a.nj; e += 256) {
     const int g = e / a.nj, j = e - g * a.nj;
-    a.out[(size_t)(c * G + g) * a.out_rs + (size_t)b * a.nj + j] = ob[e];
+    int k = -1;
+#pragma unroll
+    for (int gg = 0; gg < GG; ++gg) k = (gg == g) ? kg[gg] : k;
+    if (k >= 0) a.out[(size_t)(t * G + g) * a.out_rs + (size_t)b * a.nj + j] = ob[e];
   }
+}
+
+template <typename HT, int G, int JPT>
+__global__ __launch_bounds__(256) void k_contract(ContractArgs a, int lr_log2) {
+  extern __shared__ float4 smem_raw[];
+  const int t = blockIdx.x, b = blockIdx.y;
+  int kg[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) kg[g] = a.members[t * G + g];
+  if constexpr (G > 4) {
+    if (kg[4] < 0) {  // at most four members: the cheaper body
+      contract_item<HT, G, 4, JPT>(a, lr_log2, t, b, kg, smem_raw);
+      return;
+    }
+  }
+  contract_item<HT, G, G, JPT>(a, lr_log2, t, b, kg, smem_raw);
 }
 
 template <typename HT, int G>
@@ -203,7 +217,7 @@ static pat_status launch_t(const ContractArgs& a, int B, hipStream_t st) {
   size_t lds = red_bytes > in_bytes ? red_bytes : in_bytes;
   lds = lds > out_bytes ? lds : out_bytes;
   if (lds > 160 * 1024) return fail(PAT_EUNSUPPORTED, "contraction input vector does not fit in LDS");
-  dim3 grid(a.nclass, B);
+  dim3 grid(a.nitem, B);
   if (jpt == 1)
     k_contract<HT, G, 1><<<grid, 256, lds, st>>>(a, lr_log2);
   else
@@ -213,7 +227,11 @@ static pat_status launch_t(const ContractArgs& a, int B, hipStream_t st) {
 }
 
 pat_status contract(const ContractArgs& a, int hdtype, int G, int B, hipStream_t st) {
-  if (a.nclass == 0 || B == 0) return PAT_OK;
+  if (a.nitem == 0 || B == 0) return PAT_OK;
+  if (G == 8) {  // radial fold: float32 libraries only
+    if (hdtype == PAT_H_F32) return launch_t<float, 8>(a, B, st);
+    return fail(PAT_EUNSUPPORTED, "8-member work items need a float32 library");
+  }
   if (G == 4) {
     if (hdtype == PAT_H_F32) return launch_t<float, 4>(a, B, st);
     if (hdtype == PAT_H_BF16) return launch_t<bf16_t, 4>(a, B, st);

@@ -113,7 +113,7 @@ __global__ __launch_bounds__(512, MT == 4 ? 2 : 4) void k_contract_mfma(MfmaArgs
   extern __shared__ u32x4 lds[];  // [term][ks][mt][lane] 16-byte units
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
-  const int c = blockIdx.x, cg = blockIdx.y;
+  const int c = blockIdx.x, cg = blockIdx.y;  // c: work item
   const int npairs = a.G * a.B;
   const int p0 = cg * (kMT * 16);
   const int gp = min(MT * 16, npairs - p0);  // pairs in this launch group
@@ -125,7 +125,7 @@ __global__ __launch_bounds__(512, MT == 4 ? 2 : 4) void k_contract_mfma(MfmaArgs
   const int wslot = w / kparts;
   const int wstride = kWaves / kparts;
   const int nchunks = (a.ksteps + kKC - 1) / kKC;
-  const u32x4* slab = reinterpret_cast<const u32x4*>(a.frag) + (size_t)c * a.ntiles * a.ksteps * 64;
+  const u32x4* slab = reinterpret_cast<const u32x4*>(a.frag) + (size_t)a.item_slab[c] * a.ntiles * a.ksteps * 64;
   bool staged = false;  // LDS holds chunk 0 (kept only when there is one chunk)
 
   for (int tile0 = 0; tile0 < a.ntiles; tile0 += wstride) {
@@ -237,11 +237,11 @@ static void launch_mt(const MfmaArgs& a, int hdtype, dim3 grid, hipStream_t st) 
 }
 
 pat_status contract_mfma(const MfmaArgs& a, int hdtype, hipStream_t st) {
-  if (a.nclass == 0 || a.B == 0) return PAT_OK;
+  if (a.nitem == 0 || a.B == 0) return PAT_OK;
   const int npairs = a.G * a.B;
   const int groups = (npairs + kMT * 16 - 1) / (kMT * 16);
   const int cols = 2 * (groups > 1 ? kMT * 16 : npairs);  // columns of the widest group
-  dim3 grid(a.nclass, groups);
+  dim3 grid(a.nitem, groups);
   if (cols <= 32)
     launch_mt<1>(a, hdtype, grid, st);
   else if (cols <= 64)

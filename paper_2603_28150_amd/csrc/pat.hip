@@ -19,22 +19,24 @@ struct pat_op {
   pat_geometry g;
   int nq;
   int nh, nk;
-  int G;        // member slots per class (4: octant fold, 2: quadrant fold)
-  int nclass;
+  int G;        // member slots per work item (8: radial, 4: octant, 2: quadrant fold)
+  int nclass;   // stored slabs
+  int nitem;    // contraction work items (each reads one slab)
   int vec;      // storage elements per 16-byte load
   int sA_row, sT_row;
   int ntA, ksA, ntT, ksT;  // 16-bit fragment tiling
   char* hbuf;
-  int nrows;          // spectrum rows: nclass * G, class-major
-  int32_t* members;   // [nclass][G]
-  int32_t* kclass;    // [nk]
+  int nrows;          // spectrum rows: nitem * G, item-major
+  int32_t* members;   // [nitem][G]
+  int32_t* item_slab; // [nitem]
+  int32_t* kclass;    // [nk] slab of frequency k
   int32_t* rowmap;    // [nk] spectrum row of frequency k
   int32_t* cls_freq;  // [nclass][2]
   float* inv_scale;   // [nz]
   unsigned long long* amax;  // [nz]
   void* slabA;        // [nclass][nz][sA_row]
   void* slabT;        // [nclass][nt][sT_row]
-  std::vector<int32_t> h_members, h_kclass, h_cls_freq, h_rowmap;
+  std::vector<int32_t> h_members, h_kclass, h_cls_freq, h_rowmap, h_item_slab;
 };
 
 namespace pat {
@@ -78,69 +80,102 @@ static pat_status check_geometry(const pat_geometry* g) {
 }
 
 // -------------------------------------------------------- frequency classes
-// H^ depends on (m, p) only through kx^2 + ky^2.  Classes: (|m~|, |p~|), or
-// the sorted pair when the grid is square with dx == dy.  Members are the
-// half-spectrum indices k = p*nh + m of the class.
+// H^ depends on (m, p) only through kx^2 + ky^2, so one stored slab serves a
+// whole symmetry class of half-spectrum frequencies:
+//   quadrant fold (any grid):          (|m~|, |p~|), <= 2 members
+//   octant fold (nx = ny, dx = dy):    sorted (|m~|, |p~|), <= 4 members
+//   radial fold (nx = ny, dx = dy):    all frequencies with equal m~^2 + p~^2
+// The radial fold is used for float32 libraries (fewest bytes to stream); the
+// 16-bit libraries keep the octant fold so that a batch of 16 objects fits
+// one matrix-core column group.  A work item of the contraction is one slab
+// with up to G member frequencies (a radial class with more members than G
+// is split into several items that read the same slab); its members occupy
+// spectrum rows item*G .. item*G+G-1.
 struct Classes {
   int G = 2;
-  std::vector<int32_t> members, kclass, freq, rowmap;
+  std::vector<int32_t> freq;       // [nslab][2] representative |m~|, |p~|
+  std::vector<int32_t> item_slab;  // [nitem]
+  std::vector<int32_t> members;    // [nitem][G]
+  std::vector<int32_t> kclass;     // [nk] slab of frequency k
+  std::vector<int32_t> rowmap;     // [nk] spectrum row of frequency k
   int n() const { return (int)freq.size() / 2; }
+  int nitem() const { return (int)item_slab.size(); }
 };
 
 static Classes make_classes(const pat_geometry& g) {
   Classes C;
   const int nh = g.nx / 2 + 1, hx = g.nx / 2, hy = g.ny / 2;
-  const bool octant = g.nx == g.ny && g.dx == g.dy;
-  C.G = octant ? 4 : 2;
-  C.kclass.assign((size_t)g.ny * nh, -1);
-  auto add_member = [&](int c, int slot_base, int m, int pa, std::vector<int32_t>& mem) {
-    int slot = slot_base;
+  const bool square = g.nx == g.ny && g.dx == g.dy;
+  const bool radial = square && g.h_dtype == PAT_H_F32;
+  const int nk = g.ny * nh;
+  // members of the half spectrum with |m~| = m, |p~| = pa
+  auto members_of = [&](int m, int pa, std::vector<int32_t>& out) {
     const int p1 = pa, p2 = (g.ny - pa) % g.ny;
-    mem[(size_t)c * C.G + slot++] = p1 * nh + m;
-    if (p2 != p1) mem[(size_t)c * C.G + slot++] = p2 * nh + m;
-    return slot;
+    out.push_back(p1 * nh + m);
+    if (p2 != p1) out.push_back(p2 * nh + m);
   };
-  if (octant) {
+  std::vector<std::vector<int32_t>> groups;  // member list per slab
+  if (square) {
+    std::vector<int> slot_of_r;
+    if (radial) slot_of_r.assign(2 * hx * hx + 1, -1);
     for (int a = 0; a <= hx; ++a)
       for (int b = a; b <= hx; ++b) {
-        C.freq.push_back(a);
-        C.freq.push_back(b);
+        int gi;
+        if (radial && slot_of_r[a * a + b * b] >= 0) {
+          gi = slot_of_r[a * a + b * b];
+        } else {
+          gi = (int)groups.size();
+          groups.emplace_back();
+          C.freq.push_back(a);
+          C.freq.push_back(b);
+          if (radial) slot_of_r[a * a + b * b] = gi;
+        }
+        members_of(a, b, groups[gi]);
+        if (a != b) members_of(b, a, groups[gi]);
       }
+    C.G = radial ? 8 : 4;
   } else {
     for (int m = 0; m <= hx; ++m)
       for (int pa = 0; pa <= hy; ++pa) {
+        groups.emplace_back();
         C.freq.push_back(m);
         C.freq.push_back(pa);
+        members_of(m, pa, groups.back());
       }
+    C.G = 2;
   }
-  C.members.assign((size_t)C.n() * C.G, -1);
-  for (int c = 0; c < C.n(); ++c) {
-    const int fa = C.freq[2 * c], fb = C.freq[2 * c + 1];
-    int slot = add_member(c, 0, fa, fb, C.members);
-    if (octant && fa != fb) add_member(c, slot, fb, fa, C.members);
-  }
-  C.rowmap.assign(C.kclass.size(), -1);
-  for (int c = 0; c < C.n(); ++c)
-    for (int s = 0; s < C.G; ++s) {
-      const int k = C.members[(size_t)c * C.G + s];
-      if (k >= 0) {
-        C.kclass[k] = c;
-        C.rowmap[k] = c * C.G + s;
+  C.kclass.assign(nk, -1);
+  C.rowmap.assign(nk, -1);
+  for (int gi = 0; gi < (int)groups.size(); ++gi) {
+    const auto& mem = groups[gi];
+    for (size_t i0 = 0; i0 < mem.size(); i0 += C.G) {
+      const int item = (int)C.item_slab.size();
+      C.item_slab.push_back(gi);
+      for (int s = 0; s < C.G; ++s) {
+        const size_t i = i0 + s;
+        const int k = i < mem.size() ? mem[i] : -1;
+        C.members.push_back(k);
+        if (k >= 0) {
+          C.kclass[k] = gi;
+          C.rowmap[k] = item * C.G + s;
+        }
       }
     }
+  }
   return C;
 }
 
 struct HLayout {
-  size_t off_members, off_kclass, off_rowmap, off_freq, off_inv, off_amax, off_A, off_T, total;
+  size_t off_members, off_items, off_kclass, off_rowmap, off_freq, off_inv, off_amax, off_A, off_T, total;
   size_t bytes_A, bytes_T;
-  int nclass, G, vec, sA_row, sT_row;
+  int nclass, nitem, G, vec, sA_row, sT_row;
   int ntA, ksA, ntT, ksT;
 };
 
 static HLayout h_layout(const pat_geometry& g, const Classes& C) {
   HLayout L;
   L.nclass = C.n();
+  L.nitem = C.nitem();
   L.G = C.G;
   const size_t esz = g.h_dtype == PAT_H_F32 ? 4 : 2;
   L.vec = (int)(16 / esz);
@@ -160,7 +195,8 @@ static HLayout h_layout(const pat_geometry& g, const Classes& C) {
   }
   const int nk = g.ny * (g.nx / 2 + 1);
   size_t o = 0;
-  L.off_members = o; o = align_up(o + (size_t)L.nclass * L.G * 4, 256);
+  L.off_members = o; o = align_up(o + (size_t)L.nitem * L.G * 4, 256);
+  L.off_items = o;   o = align_up(o + (size_t)L.nitem * 4, 256);
   L.off_kclass = o;  o = align_up(o + (size_t)nk * 4, 256);
   L.off_rowmap = o;  o = align_up(o + (size_t)nk * 4, 256);
   L.off_freq = o;    o = align_up(o + (size_t)L.nclass * 8, 256);
@@ -195,7 +231,7 @@ static Work work_layout(const pat_op* op, int B, char* base) {
     o = align_up(o + bytes, 256);
     return p;
   };
-  w.Xs = (float2*)take((size_t)op->nrows * Sz * 8);
+  w.Xs = (float2*)take((size_t)op->nrows * Sz * 8);  // nrows = nitem * G
   w.Ds = (float2*)take((size_t)op->nrows * St * 8);
   w.T = (float2*)take((size_t)g.ny * op->nh * std::max(Sz, St) * 8);
   w.V = (float*)take(Sz * nxy * 4);
@@ -235,18 +271,20 @@ static pat_status run_contract(pat_op* op, bool adjoint, const float2* in, float
   const pat_geometry& g = op->g;
   ContractArgs a;
   a.members = op->members;
+  a.item_slab = op->item_slab;
   a.in = in;
   a.out = out;
-  a.nclass = op->nclass;
+  a.nitem = op->nitem;
   const float* sc = g.h_dtype == PAT_H_F32 ? nullptr : op->inv_scale;
   if (g.h_dtype != PAT_H_F32) {
     MfmaArgs m;
     m.members = op->members;
+    m.item_slab = op->item_slab;
     m.in = in;
     m.out = out;
     m.G = op->G;
     m.B = B;
-    m.nclass = op->nclass;
+    m.nitem = op->nitem;
     if (!adjoint) {
       m.frag = op->slabA;
       m.K = g.nz;
@@ -386,6 +424,7 @@ pat_status pat_H_build(pat_ctx* ctx, const pat_geometry* geom, void* h_buf, size
   op->nk = geom->ny * op->nh;
   op->G = L.G;
   op->nclass = L.nclass;
+  op->nitem = L.nitem;
   op->vec = L.vec;
   op->sA_row = L.sA_row;
   op->sT_row = L.sT_row;
@@ -394,8 +433,9 @@ pat_status pat_H_build(pat_ctx* ctx, const pat_geometry* geom, void* h_buf, size
   op->ntT = L.ntT;
   op->ksT = L.ksT;
   op->hbuf = (char*)h_buf;
-  op->nrows = L.nclass * L.G;
+  op->nrows = L.nitem * L.G;
   op->members = (int32_t*)(op->hbuf + L.off_members);
+  op->item_slab = (int32_t*)(op->hbuf + L.off_items);
   op->kclass = (int32_t*)(op->hbuf + L.off_kclass);
   op->rowmap = (int32_t*)(op->hbuf + L.off_rowmap);
   op->cls_freq = (int32_t*)(op->hbuf + L.off_freq);
@@ -407,6 +447,7 @@ pat_status pat_H_build(pat_ctx* ctx, const pat_geometry* geom, void* h_buf, size
   op->h_kclass = std::move(C.kclass);
   op->h_cls_freq = std::move(C.freq);
   op->h_rowmap = std::move(C.rowmap);
+  op->h_item_slab = std::move(C.item_slab);
 
   auto bail = [&](pat_status s) {
     delete op;
@@ -426,6 +467,9 @@ pat_status pat_H_build(pat_ctx* ctx, const pat_geometry* geom, void* h_buf, size
     return bail(s);
   if ((s = hip_check(hipMemcpyAsync(op->rowmap, op->h_rowmap.data(), op->h_rowmap.size() * 4,
                                     hipMemcpyHostToDevice, st), "upload row map")) != PAT_OK)
+    return bail(s);
+  if ((s = hip_check(hipMemcpyAsync(op->item_slab, op->h_item_slab.data(), op->h_item_slab.size() * 4,
+                                    hipMemcpyHostToDevice, st), "upload items")) != PAT_OK)
     return bail(s);
   HBuildArgs a;
   a.cls_freq = op->cls_freq;
@@ -481,6 +525,9 @@ pat_status pat_get_info(const pat_op* op, pat_op_info* info) {
   info->nz_sim = op->nq;
   info->slab_bytes_A = L.bytes_A;
   info->slab_bytes_AT = L.bytes_T;
+  info->nitems = op->nitem;
+  info->read_bytes_A = L.bytes_A / op->nclass * op->nitem;
+  info->read_bytes_AT = L.bytes_T / op->nclass * op->nitem;
   info->spec_rows = op->nrows;
   return PAT_OK;
 }

@@ -44,19 +44,21 @@ pat_status fft2_c2r(const float2* X, float2* T, float* f, int nx, int ny, int S,
                     float scale, const float* sub, const int32_t* rowmap, hipStream_t st);
 
 // ------------------------------------------------------ contraction (VALU)
-// out[c*G+g][obj*nj + j] = sum_i slab_c[i][j] * in[c*G+g][obj*ni + i] (* scales)
-// for every class c and its member slots g < G (members[c*G+g] < 0: empty).
+// out[t*G+g][obj*nj + j] = sum_i slab_s[i][j] * in[t*G+g][obj*ni + i] (* scales)
+// for every work item t, its slab s = item_slab[t] and member slots g < G
+// (members[t*G+g] < 0: empty; filled slots come first).
 struct ContractArgs {
-  const void* slab;        // [C][ni][s_row] of the storage type
-  const int32_t* members;  // [C][G]
-  const float2* in;        // [C*G][in_rs]  class-major spectrum rows
-  float2* out;             // [C*G][out_rs]
+  const void* slab;          // [nslab][ni][s_row] of the storage type
+  const int32_t* members;    // [nitem][G]
+  const int32_t* item_slab;  // [nitem]
+  const float2* in;          // [nitem*G][in_rs]  item-major spectrum rows
+  float2* out;               // [nitem*G][out_rs]
   const float* in_scale;   // [ni] or null
   const float* out_scale;  // [nj] or null
   int ni, nj, s_row;
   long long slab_elems;    // ni * s_row
   int in_rs, out_rs;
-  int nclass;
+  int nitem;
 };
 pat_status contract(const ContractArgs& a, int hdtype, int G, int B, hipStream_t st);
 
@@ -66,13 +68,14 @@ pat_status contract(const ContractArgs& a, int hdtype, int G, int B, hipStream_t
 // fragment (tile, kstep) of class c holds S_c(kstep*16 + 8*(lane/32) + e,
 // tile*32 + lane%32) at 16-byte unit lane, element e.
 struct MfmaArgs {
-  const void* frag;        // [C][ntiles][ksteps][64] 16-byte units
-  const int32_t* members;  // [C][G]
-  const float2* in;        // [C*G][in_rs]
-  float2* out;             // [C*G][out_rs]
-  const float* in_scale;   // [K] or null
-  const float* out_scale;  // [N] or null
-  int K, N, ntiles, ksteps, in_rs, out_rs, G, B, nclass;
+  const void* frag;          // [nslab][ntiles][ksteps][64] 16-byte units
+  const int32_t* members;    // [nitem][G]
+  const int32_t* item_slab;  // [nitem]
+  const float2* in;          // [nitem*G][in_rs]
+  float2* out;               // [nitem*G][out_rs]
+  const float* in_scale;     // [K] or null
+  const float* out_scale;    // [N] or null
+  int K, N, ntiles, ksteps, in_rs, out_rs, G, B, nitem;
 };
 pat_status contract_mfma(const MfmaArgs& a, int hdtype, hipStream_t st);
 

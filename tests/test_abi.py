@@ -50,8 +50,10 @@ def test_host_only_calls(lib):
     g = _lib.Geometry(32, 32, 16, 64, 1e-4, 1e-4, 1e-4, 2e-8, 1500.0, 0, 0)
     hb, sb = ctypes.c_size_t(), ctypes.c_size_t()
     assert L.pat_H_bytes(ctypes.byref(g), ctypes.byref(hb), ctypes.byref(sb)) == 0
-    # octant classes of a 32^2 grid: 17*18/2 = 153 slabs in two layouts
-    assert hb.value >= 153 * 16 * 64 * 4 * 2
+    # float32 library of a square grid: one slab per distinct m^2 + p^2, two layouts
+    radii = {a * a + b * b for a in range(17) for b in range(a, 17)}
+    assert hb.value >= len(radii) * 16 * 64 * 4 * 2
+    assert hb.value < (len(radii) + 1) * 16 * 64 * 4 * 2 + (1 << 20)
     bad = _lib.Geometry(48, 32, 16, 64, 1e-4, 1e-4, 1e-4, 2e-8, 1500.0, 0, 0)
     assert L.pat_H_bytes(ctypes.byref(bad), ctypes.byref(hb), ctypes.byref(sb)) == -2
     assert b"power" in L.pat_last_error()
