@@ -186,10 +186,15 @@ pat_status pat_power_norm(pat_op* op, const float* v0, int32_t niter, double* L_
  *     t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2   (beta_k = 0 if momentum == 0),
  * with prox(v) = max(v - tau*lambda, 0) if nonneg, else soft-thresholding.
  * d: device [nt][ny][nx]; x: device [nz][ny][nx], receives x_niter.
+ * The gradient A^T (A z - d) = A^T A z - A^T d (eq. 15) is formed per
+ * transverse frequency with the Gram blocks H^_k^T H^_k of the library (built
+ * with it, float64 sums of the stored values): one spectrum of z, one
+ * nz x nz contraction and one inverse spectrum per iteration, A^T d once.
  * trace: NULL or a device float array [niter] that receives
  * 1/2 ||A z_k - d||^2, the data term at the point where the gradient of
- * step k is taken.  The momentum weights are computed on the host in
- * float64.  Asynchronous. */
+ * step k is taken, as 1/2 (<z, g> - <z, A^T d> + ||d||^2) with float64 sums
+ * (absolute error of order 1e-7 * ||d||^2).  The momentum weights are
+ * computed on the host in float64.  Asynchronous. */
 pat_status pat_recon_fista(pat_op* op, const float* d, float* x, int32_t niter,
                            float tau, float lambda, int32_t nonneg, int32_t momentum,
                            float* trace, void* ws, size_t ws_bytes, void* stream);

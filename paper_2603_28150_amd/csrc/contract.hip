@@ -181,7 +181,10 @@ __device__ __forceinline__ void contract_item(const ContractArgs& a, int lr_log2
     int k = -1;
 #pragma unroll
     for (int gg = 0; gg < GG; ++gg) k = (gg == g) ? kg[gg] : k;
-    if (k >= 0) a.out[(size_t)(t * G + g) * a.out_rs + (size_t)b * a.nj + j] = ob[e];
+    if (k >= 0) {
+      const size_t o = (size_t)(t * G + g) * a.out_rs + (size_t)b * a.nj + j;
+      a.out[o] = a.out_sub ? csub(ob[e], a.out_sub[o]) : ob[e];
+    }
   }
 }
 

@@ -242,4 +242,77 @@ pat_status hexport(const void* slabA, int hdtype, const int32_t* kclass, const f
   return PAT_OK;
 }
 
+
+// ------------------------------------------------------- normal operator
+// Gram blocks of the stored (dequantised) library: G_s[l][l'] =
+// sum_n H^_s[l][n] H^_s[l'][n], accumulated in float64 and rounded once.  A^T A
+// is block diagonal in the transverse Fourier basis with these blocks, so the
+// gradient of the data term, A^T (A z - d) = A^T A z - A^T d (eq. 15), can be
+// formed per frequency from the spectrum of z alone.
+constexpr int kGN = 32;   // time samples per LDS chunk
+
+__device__ __forceinline__ float lib_value(const GramArgs& a, int s, int l, int n) {
+  if (a.hdtype == PAT_H_F32)
+    return reinterpret_cast<const float*>(a.slabA)[((size_t)s * a.nz + l) * a.sA_row + n];
+  const size_t o = ((((size_t)s * a.ntA + n / 32) * a.ksA + l / 16) * 64 + (n & 31) + 32 * ((l >> 3) & 1)) * 8 + (l & 7);
+  const unsigned short b = reinterpret_cast<const unsigned short*>(a.slabA)[o];
+  float f;
+  if (a.hdtype == PAT_H_BF16) {
+    f = __uint_as_float((unsigned)b << 16);
+  } else {
+    _Float16 h;
+    __builtin_memcpy(&h, &b, 2);
+    f = (float)h;
+  }
+  return f * a.inv_scale[l];
+}
+
+// workgroup = (slab, 64 x 64 output tile); thread = 4 x 4 outputs
+__global__ __launch_bounds__(256) void k_gram(GramArgs a) {
+  __shared__ double hi[64][kGN + 1], hj[64][kGN + 1];
+  const int s = blockIdx.z;
+  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  const int tid = threadIdx.x;
+  const int ti = tid / 16, tj = tid % 16;
+  double acc[4][4] = {};
+  for (int n0 = 0; n0 < a.nt; n0 += kGN) {
+    __syncthreads();
+    for (int e = tid; e < 64 * kGN; e += 256) {
+      const int r = e / kGN, nn = e % kGN;
+      const int n = n0 + nn;
+      hi[r][nn] = (i0 + r < a.nz && n < a.nt) ? (double)lib_value(a, s, i0 + r, n) : 0.0;
+      hj[r][nn] = (j0 + r < a.nz && n < a.nt) ? (double)lib_value(a, s, j0 + r, n) : 0.0;
+    }
+    __syncthreads();
+    for (int nn = 0; nn < kGN; ++nn) {
+      double x[4], y[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        x[u] = hi[ti + 16 * u][nn];
+        y[u] = hj[tj + 16 * u][nn];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = fma(x[u], y[v], acc[u][v]);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = i0 + ti + 16 * u, j = j0 + tj + 16 * v;
+      if (i < a.nz && j < a.nz) a.gram[((size_t)s * a.nz + i) * a.sG_row + j] = (float)acc[u][v];
+    }
+}
+
+pat_status gram_build(const GramArgs& a, hipStream_t st) {
+  if (a.nslab == 0) return PAT_OK;
+  const int nb = (a.nz + 63) / 64;
+  dim3 grid(nb, nb, a.nslab);
+  k_gram<<<grid, 256, 0, st>>>(a);
+  PAT_LAUNCHED("Gram blocks");
+  return PAT_OK;
+}
+
 }  // namespace pat

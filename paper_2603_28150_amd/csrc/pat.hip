@@ -36,6 +36,8 @@ struct pat_op {
   unsigned long long* amax;  // [nz]
   void* slabA;        // [nclass][nz][sA_row]
   void* slabT;        // [nclass][nt][sT_row]
+  float* gram;        // [nclass][nz][sG_row]  Gram blocks of the library
+  int sG_row;
   std::vector<int32_t> h_members, h_kclass, h_cls_freq, h_rowmap, h_item_slab;
 };
 
@@ -166,8 +168,10 @@ static Classes make_classes(const pat_geometry& g) {
 }
 
 struct HLayout {
-  size_t off_members, off_items, off_kclass, off_rowmap, off_freq, off_inv, off_amax, off_A, off_T, total;
-  size_t bytes_A, bytes_T;
+  size_t off_members, off_items, off_kclass, off_rowmap, off_freq, off_inv, off_amax, off_A, off_T,
+      off_G, total;
+  size_t bytes_A, bytes_T, bytes_G;
+  int sG_row;
   int nclass, nitem, G, vec, sA_row, sT_row;
   int ntA, ksA, ntT, ksT;
 };
@@ -202,15 +206,18 @@ static HLayout h_layout(const pat_geometry& g, const Classes& C) {
   L.off_freq = o;    o = align_up(o + (size_t)L.nclass * 8, 256);
   L.off_inv = o;     o = align_up(o + (size_t)g.nz * 4, 256);
   L.off_amax = o;    o = align_up(o + (size_t)g.nz * 8, 256);
+  L.sG_row = (int)align_up((size_t)g.nz, 4);
+  L.bytes_G = (size_t)L.nclass * g.nz * L.sG_row * 4;
   L.off_A = o;       o = align_up(o + L.bytes_A, 256);
   L.off_T = o;       o = align_up(o + L.bytes_T, 256);
+  L.off_G = o;       o = align_up(o + L.bytes_G, 256);
   L.total = o;
   return L;
 }
 
 // ------------------------------------------------------------- workspace
 struct Work {
-  float2 *Xs, *Ds, *T;
+  float2 *Xs, *Ds, *T, *Bs, *Gs;
   float *V, *U, *Z, *R;
   double* part64;
   float* part32;
@@ -234,6 +241,8 @@ static Work work_layout(const pat_op* op, int B, char* base) {
   w.Xs = (float2*)take((size_t)op->nrows * Sz * 8);  // nrows = nitem * G
   w.Ds = (float2*)take((size_t)op->nrows * St * 8);
   w.T = (float2*)take((size_t)g.ny * op->nh * std::max(Sz, St) * 8);
+  w.Bs = (float2*)take((size_t)op->nrows * Sz * 8);
+  w.Gs = (float2*)take((size_t)op->nrows * Sz * 8);
   w.V = (float*)take(Sz * nxy * 4);
   w.U = (float*)take(Sz * nxy * 4);
   w.Z = (float*)take(Sz * nxy * 4);
@@ -274,6 +283,7 @@ static pat_status run_contract(pat_op* op, bool adjoint, const float2* in, float
   a.item_slab = op->item_slab;
   a.in = in;
   a.out = out;
+  a.out_sub = nullptr;
   a.nitem = op->nitem;
   const float* sc = g.h_dtype == PAT_H_F32 ? nullptr : op->inv_scale;
   if (g.h_dtype != PAT_H_F32) {
@@ -325,6 +335,29 @@ static pat_status run_contract(pat_op* op, bool adjoint, const float2* in, float
   a.in_rs = B * a.ni;
   a.out_rs = B * a.nj;
   return contract(a, g.h_dtype, op->G, B, st);
+}
+
+// Gram contraction: out = G z^ - sub per frequency, B spectra of nz slices
+static pat_status run_gram(pat_op* op, const float2* in, float2* out, const float2* sub, int B,
+                           hipStream_t st) {
+  const pat_geometry& g = op->g;
+  ContractArgs a;
+  a.slab = op->gram;
+  a.members = op->members;
+  a.item_slab = op->item_slab;
+  a.in = in;
+  a.out = out;
+  a.in_scale = nullptr;
+  a.out_scale = nullptr;
+  a.out_sub = sub;
+  a.ni = g.nz;
+  a.nj = g.nz;
+  a.s_row = op->sG_row;
+  a.slab_elems = (long long)g.nz * op->sG_row;
+  a.in_rs = B * g.nz;
+  a.out_rs = B * g.nz;
+  a.nitem = op->nitem;
+  return contract(a, PAT_H_F32, op->G, B, st);
 }
 
 // y = A x (- sub), B objects
@@ -443,6 +476,8 @@ pat_status pat_H_build(pat_ctx* ctx, const pat_geometry* geom, void* h_buf, size
   op->amax = (unsigned long long*)(op->hbuf + L.off_amax);
   op->slabA = op->hbuf + L.off_A;
   op->slabT = op->hbuf + L.off_T;
+  op->gram = (float*)(op->hbuf + L.off_G);
+  op->sG_row = L.sG_row;
   op->h_members = std::move(C.members);
   op->h_kclass = std::move(C.kclass);
   op->h_cls_freq = std::move(C.freq);
@@ -496,6 +531,19 @@ pat_status pat_H_build(pat_ctx* ctx, const pat_geometry* geom, void* h_buf, size
   a.inv_scale = op->inv_scale;
   a.hdtype = geom->h_dtype;
   if ((s = hbuild(a, st)) != PAT_OK) return bail(s);
+  GramArgs ga;
+  ga.slabA = op->slabA;
+  ga.inv_scale = op->inv_scale;
+  ga.gram = op->gram;
+  ga.nslab = op->nclass;
+  ga.nz = geom->nz;
+  ga.nt = geom->nt;
+  ga.sA_row = op->sA_row;
+  ga.ntA = op->ntA;
+  ga.ksA = op->ksA;
+  ga.sG_row = op->sG_row;
+  ga.hdtype = geom->h_dtype;
+  if ((s = gram_build(ga, st)) != PAT_OK) return bail(s);
   *out = op;
   return PAT_OK;
 }
@@ -644,15 +692,30 @@ pat_status pat_recon_fista(pat_op* op, const float* d, float* x, int32_t niter, 
   const pat_geometry& g = op->g;
   const long long n = (long long)g.nz * g.nx * g.ny;
   const long long nd = (long long)g.nt * g.nx * g.ny;
+  const float inv = 1.0f / (float)(g.nx * g.ny);
+  // b^ = spectrum of A^T d (the adjoint up to its inverse transform), once
+  PAT_TRY(fft2_r2c(d, w.T, w.Ds, g.nx, g.ny, g.nt, op->rowmap, st));
+  PAT_TRY(run_contract(op, true, w.Ds, w.Bs, 1, st));
+  if (trace) {
+    PAT_TRY(fft2_c2r(w.Bs, w.T, w.V, g.nx, g.ny, g.nz, inv, nullptr, op->rowmap, st));  // b = A^T d
+    PAT_TRY(dot_f64(d, d, nd, w.part64, w.s64 + 2, st));
+  }
   PAT_TRY(fill_zero(x, n * 4, st));
   PAT_TRY(fill_zero(w.Z, n * 4, st));
   double t = 1.0;
   FistaBatch p;
   std::memset(&p, 0, sizeof(p));
   for (int k = 1; k <= niter; ++k) {
-    PAT_TRY(run_A(op, w.Z, w.R, 1, d, w, st));  // R = A z - d
-    if (trace) PAT_TRY(dot_f32(w.R, w.R, nd, w.part32, trace + (k - 1), 0.5f, st));
-    PAT_TRY(run_AT(op, w.R, w.U, 1, w, st));    // U = A^T (A z - d)
+    // gradient A^T (A z - d) = A^T A z - A^T d, per frequency: G z^ - b^
+    PAT_TRY(fft2_r2c(w.Z, w.T, w.Xs, g.nx, g.ny, g.nz, op->rowmap, st));
+    PAT_TRY(run_gram(op, w.Xs, w.Gs, w.Bs, 1, st));
+    PAT_TRY(fft2_c2r(w.Gs, w.T, w.U, g.nx, g.ny, g.nz, inv, nullptr, op->rowmap, st));
+    if (trace) {
+      // 1/2 ||A z - d||^2 = 1/2 (<z, g> - <z, b> + ||d||^2), float64 sums
+      PAT_TRY(dot_f64(w.Z, w.U, n, w.part64, w.s64 + 0, st));
+      PAT_TRY(dot_f64(w.Z, w.V, n, w.part64, w.s64 + 1, st));
+      PAT_TRY(trace_combine(trace + (k - 1), w.s64, st));
+    }
     double beta = 0.0;
     if (momentum) {
       const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;

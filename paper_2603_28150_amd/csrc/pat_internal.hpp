@@ -55,6 +55,7 @@ struct ContractArgs {
   float2* out;               // [nitem*G][out_rs]
   const float* in_scale;   // [ni] or null
   const float* out_scale;  // [nj] or null
+  const float2* out_sub;   // null, or rows like out: out = result - out_sub
   int ni, nj, s_row;
   long long slab_elems;    // ni * s_row
   int in_rs, out_rs;
@@ -93,6 +94,14 @@ struct HBuildArgs {
   int hdtype;
 };
 pat_status hbuild(const HBuildArgs& a, hipStream_t st);
+struct GramArgs {
+  const void* slabA;        // stored library, [l][n] rows (FP32) or fragments (16-bit)
+  const float* inv_scale;   // [nz]
+  float* gram;              // [nslab][nz][sG_row]
+  int nslab, nz, nt, sA_row, ntA, ksA, sG_row, hdtype;
+};
+pat_status gram_build(const GramArgs& a, hipStream_t st);
+
 pat_status hexport(const void* slabA, int hdtype, const int32_t* kclass, const float* inv_scale,
                    int k0, int nk, int nz, int nt, int sA_row, int ntA, int ksA, float* out,
                    hipStream_t st);
@@ -104,6 +113,8 @@ pat_status dot_f32(const float* a, const float* b, long long n, float* part, flo
                    float post_scale, hipStream_t st);
 pat_status dot_f64(const float* a, const float* b, long long n, double* part, double* result,
                    hipStream_t st);
+// out[0] = (s[0] - s[1] + s[2]) / 2
+pat_status trace_combine(float* out, const double* s, hipStream_t st);
 // dst = src / sqrt(*nrm2)
 pat_status scale_rsqrt(float* dst, const float* src, long long n, const float* nrm2, hipStream_t st);
 

@@ -94,6 +94,16 @@ pat_status scale_rsqrt(float* dst, const float* src, long long n, const float* n
   return PAT_OK;
 }
 
+__global__ void k_trace_combine(float* out, const double* s) {
+  out[0] = (float)(0.5 * (s[0] - s[1] + s[2]));
+}
+
+pat_status trace_combine(float* out, const double* s, hipStream_t st) {
+  k_trace_combine<<<1, 1, 0, st>>>(out, s);
+  PAT_LAUNCHED("trace");
+  return PAT_OK;
+}
+
 // x_old = x; v = z - tau g; x = prox(v); z = x + beta (x - x_old)
 __global__ __launch_bounds__(256) void k_fista_update(float* __restrict__ x, float* __restrict__ z,
                                                       const float* __restrict__ g,
