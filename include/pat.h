@@ -212,6 +212,17 @@ pat_status pat_fista_step(pat_op* op, int32_t B, const float* d, float* x, float
                           const int32_t* nonneg, int32_t* nonfinite,
                           void* ws, size_t ws_bytes, void* stream);
 
+/* The same iteration with the gradient formed per frequency through the Gram
+ * blocks of the library (see pat_recon_fista): atd [B][nz][ny][nx] holds
+ * A^T d of each object (one pat_apply_AT when the problem is set up), so the
+ * data themselves are not needed; x, z, beta, tau, lambda, nonneg and
+ * nonfinite as in pat_fista_step.  Per iteration: one spectrum of z, one
+ * nz x nz contraction, one inverse spectrum and the update. */
+pat_status pat_fista_step_normal(pat_op* op, int32_t B, const float* atd, float* x, float* z,
+                                 const double* beta, const float* tau, const float* lambda,
+                                 const int32_t* nonneg, int32_t* nonfinite,
+                                 void* ws, size_t ws_bytes, void* stream);
+
 /* Adjoint check with float64 dot products on the GPU (synchronises):
  * *rel_out = |<A x, y> - <x, A^T y>| / (||A x|| ||y||).
  * x: device [nz][ny][nx], y: device [nt][ny][nx]. */

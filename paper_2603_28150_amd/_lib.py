@@ -61,6 +61,8 @@ SIGNATURES = {
     "pat_recon_fista": [_vp, _vp, _vp, _i32, _f32, _f32, _i32, _i32, _vp, _vp, _sz, _vp],
     "pat_fista_step": [_vp, _i32, _vp, _vp, _vp, C.POINTER(_f64), C.POINTER(_f32),
                        C.POINTER(_f32), C.POINTER(_i32), _vp, _vp, _sz, _vp],
+    "pat_fista_step_normal": [_vp, _i32, _vp, _vp, _vp, C.POINTER(_f64), C.POINTER(_f32),
+                              C.POINTER(_f32), C.POINTER(_i32), _vp, _vp, _sz, _vp],
     "pat_adjoint_check": [_vp, _vp, _vp, C.POINTER(_f64), _vp, _sz, _vp],
     "pat_spectrum": [_vp, _vp, _vp, _i32, _vp, _sz, _vp],
     "pat_inverse_spectrum": [_vp, _vp, _vp, _i32, _vp, _vp, _sz, _vp],

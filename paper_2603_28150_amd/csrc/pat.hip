@@ -759,6 +759,36 @@ pat_status pat_fista_step(pat_op* op, int32_t B, const float* d, float* x, float
   return fista_update(x, z, w.U, n, B, p, nonfinite, st);
 }
 
+pat_status pat_fista_step_normal(pat_op* op, int32_t B, const float* atd, float* x, float* z,
+                                 const double* beta, const float* tau, const float* lambda,
+                                 const int32_t* nonneg, int32_t* nonfinite, void* ws,
+                                 size_t ws_bytes, void* stream) {
+  Work w;
+  PAT_TRY(check_op_call(op, B, ws, ws_bytes, &w));
+  if (B > 32) return fail(PAT_EINVAL, "B must be <= 32");
+  PAT_TRY(check_ptr(atd, "atd"));
+  PAT_TRY(check_ptr(x, "x"));
+  PAT_TRY(check_ptr(z, "z"));
+  if (!beta || !tau || !lambda || !nonneg) return fail(PAT_EINVAL, "per-object parameters are null");
+  hipStream_t st = (hipStream_t)stream;
+  const pat_geometry& g = op->g;
+  const long long n = (long long)g.nz * g.nx * g.ny;
+  FistaBatch p;
+  std::memset(&p, 0, sizeof(p));
+  for (int b = 0; b < B; ++b) {
+    if (!(tau[b] > 0.f) || !(lambda[b] >= 0.f)) return fail(PAT_EINVAL, "tau must be > 0 and lambda >= 0");
+    p.o[b].tau = tau[b];
+    p.o[b].thr = tau[b] * lambda[b];
+    p.o[b].beta = (float)beta[b];
+    p.o[b].nonneg = nonneg[b] ? 1 : 0;
+  }
+  PAT_TRY(fft2_r2c(z, w.T, w.Xs, g.nx, g.ny, B * g.nz, op->rowmap, st));
+  PAT_TRY(run_gram(op, w.Xs, w.Gs, nullptr, B, st));
+  PAT_TRY(fft2_c2r(w.Gs, w.T, w.U, g.nx, g.ny, B * g.nz, 1.0f / (float)(g.nx * g.ny), atd,
+                   op->rowmap, st));  // U = A^T A z - A^T d
+  return fista_update(x, z, w.U, n, B, p, nonfinite, st);
+}
+
 pat_status pat_adjoint_check(pat_op* op, const float* x, const float* y, double* rel_out, void* ws,
                              size_t ws_bytes, void* stream) {
   Work w;

@@ -239,6 +239,23 @@ class Operator:
                   _ptr(nonfinite) if nonfinite is not None else None, _ptr(ws), ws.numel(),
                   _stream(self.device))
 
+    def fista_step_normal(self, atd, x, z, beta, tau, lam, nonneg, nonfinite=None, ws=None) -> None:
+        """One batched FISTA iteration with the per-frequency normal operator;
+        atd = A^T d of every object ([B, nz, ny, nx])."""
+        B = x.shape[0]
+        self._check(atd, self.x_shape, "atd")
+        self._check(x, self.x_shape, "x")
+        self._check(z, self.x_shape, "z")
+        cb = (C.c_double * B)(*[float(b) for b in beta])
+        ct = (C.c_float * B)(*[float(t) for t in tau])
+        cl = (C.c_float * B)(*[float(v) for v in lam])
+        cn = (C.c_int32 * B)(*[int(bool(v)) for v in nonneg])
+        if ws is None:
+            ws = self.workspace(B)
+        _lib.call("pat_fista_step_normal", self.handle, B, _ptr(atd), _ptr(x), _ptr(z), cb, ct, cl, cn,
+                  _ptr(nonfinite) if nonfinite is not None else None, _ptr(ws), ws.numel(),
+                  _stream(self.device))
+
     def adjoint_check(self, x: torch.Tensor, y: torch.Tensor) -> float:
         self._check(x, self.x_shape, "x")
         self._check(y, self.d_shape, "y")

@@ -76,10 +76,16 @@ class _Class:
 
 
 class HipBackend:
-    """GPU backend: libpat operators, torch-owned buffers, one stream per class."""
+    """GPU backend: libpat operators, torch-owned buffers, one stream per class.
 
-    def __init__(self, device: int = 0):
+    normal=True (default) steps requests with the per-frequency normal
+    operator: a slot keeps A^T d (formed once at admission) instead of d, and
+    an iteration costs one z-spectrum, one nz x nz contraction and one inverse
+    spectrum; normal=False takes the explicit A then A^T every iteration."""
+
+    def __init__(self, device: int = 0, normal: bool = True):
         self.device = torch.device("cuda", device)
+        self.normal = normal
 
     def library_bytes(self, geom, h_dtype) -> int:
         from .op import h_bytes
@@ -99,6 +105,8 @@ class HipBackend:
 
     def slot_bytes(self, op) -> int:
         g = op.geom
+        if self.normal:
+            return 4 * g.nx * g.ny * 3 * g.nz + 4
         return 4 * g.nx * g.ny * (2 * g.nz + g.nt) + 4
 
     def workspace_bytes(self, op, cap) -> int:
@@ -109,34 +117,43 @@ class HipBackend:
 
     def alloc_pool(self, op, cap, stream):
         g = op.geom
+        data = "b" if self.normal else "d"
+        dshape = op.x_shape if self.normal else op.d_shape
         with torch.cuda.stream(stream):
             return {"x": torch.zeros((cap,) + op.x_shape, device=self.device),
                     "z": torch.zeros((cap,) + op.x_shape, device=self.device),
-                    "d": torch.zeros((cap,) + op.d_shape, device=self.device),
+                    data: torch.zeros((cap,) + dshape, device=self.device),
                     "bad": torch.zeros(cap, dtype=torch.int32, device=self.device)}, \
                 torch.empty(op.workspace_bytes(cap), dtype=torch.uint8, device=self.device)
 
-    def load_row(self, pool, i, d, stream):
+    def load_row(self, pool, i, d, stream, op=None):
         with torch.cuda.stream(stream):
-            pool["d"][i].copy_(d, non_blocking=True)
+            if self.normal:
+                op.apply_AT(d.to(self.device, non_blocking=True), out=pool["b"][i])
+            else:
+                pool["d"][i].copy_(d, non_blocking=True)
             pool["x"][i].zero_()
             pool["z"][i].zero_()
             pool["bad"][i].zero_()
 
     def move_row(self, pool, src, dst, stream):
         with torch.cuda.stream(stream):
-            for name in ("x", "z", "d", "bad"):
+            for name in pool:
                 pool[name][dst].copy_(pool[name][src])
 
     def copy_rows(self, old, new, n, stream):
         with torch.cuda.stream(stream):
-            for name in ("x", "z", "d", "bad"):
+            for name in old:
                 new[name][:n].copy_(old[name][:n])
 
     def step(self, op, pool, ws, n, betas, taus, lams, nonnegs, stream):
         with torch.cuda.stream(stream):
-            op.fista_step(pool["d"][:n], pool["x"][:n], pool["z"][:n], betas, taus, lams, nonnegs,
-                          nonfinite=pool["bad"][:n], ws=ws)
+            if self.normal:
+                op.fista_step_normal(pool["b"][:n], pool["x"][:n], pool["z"][:n], betas, taus, lams,
+                                     nonnegs, nonfinite=pool["bad"][:n], ws=ws)
+            else:
+                op.fista_step(pool["d"][:n], pool["x"][:n], pool["z"][:n], betas, taus, lams, nonnegs,
+                              nonfinite=pool["bad"][:n], ws=ws)
             ev = torch.cuda.Event()
             ev.record(stream)
         return ev
@@ -253,7 +270,7 @@ class Server:
                 continue
             i = len(cls.active)
             st = self._stream(cls.key)
-            self.be.load_row(cls.pool, i, req.d, st)
+            self.be.load_row(cls.pool, i, req.d, st, op=cls.op)
             cls.active.append(_Slot(req))
             req.status = "running"
             req.t_admit = self.clock()

@@ -337,3 +337,25 @@ def test_gram_fista_matches_oracle(name, kind):
     xs = solvers.fista(A, AT, d, (g.nz, g.ny, g.nx), 15, tau, 2e-3, nonneg=True)
     for k in (3, 15):
         assert rel(host(op.recon_fista(dev(d), k, tau, 2e-3, nonneg=True)), xs[k - 1]) < 1e-5, k
+
+
+def test_normal_step_matches_explicit_step_and_oracle():
+    # batched FISTA steps through the Gram blocks (A^T d given) against the
+    # explicit A then A^T step and against the oracle, three objects
+    g, op, Hh = setup("mid")
+    ds = np.stack([_problem("mid", seed_obj=700 + b, seed_noise=710 + b)[3] for b in range(3)])
+    atd = op.apply_AT(dev(ds))
+    taus = [float(np.float32(f / solvers.norm_exact(Hh))) for f in (0.5, 0.8, 1.0)]
+    lams, nn = [0.0, 1e-3, 0.0], [True, True, False]
+    xe = torch.zeros((3, g.nz, g.ny, g.nx), device="cuda")
+    ze, xn, zn = torch.zeros_like(xe), torch.zeros_like(xe), torch.zeros_like(xe)
+    betas = solvers.momentum_weights(6)
+    for k in range(6):
+        op.fista_step(dev(ds), xe, ze, [betas[k]] * 3, taus, lams, nn)
+        op.fista_step_normal(atd, xn, zn, [betas[k]] * 3, taus, lams, nn)
+    A = lambda v: ops.A_fft(Hh, v)
+    AT = lambda v: ops.AT_fft(Hh, v)
+    for b in range(3):
+        xo = solvers.fista(A, AT, ds[b], (g.nz, g.ny, g.nx), 6, taus[b], lams[b], nonneg=nn[b])[-1]
+        assert rel(host(xn[b]), xo) < 1e-5, b
+        assert rel(host(xn[b]), host(xe[b])) < 1e-5, b

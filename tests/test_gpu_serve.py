@@ -29,11 +29,12 @@ def rel(a, b):
     return float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
 
 
-def test_results_alone_equal_results_in_the_mix():
+@pytest.mark.parametrize("normal", [True, False])
+def test_results_alone_equal_results_in_the_mix(normal):
     plan = [(GA, "f32", 12), (GB, "f32", 20), (GA, "bf16", 9), (GA, "f32", 15), (GB, "f32", 7),
             (GA, "bf16", 11), (GA, "f32", 5), (GB, "bf16", 8)]
     datas = [_data(g, 500 + 7 * i)[0] for i, (g, _, _) in enumerate(plan)]
-    srv = Server(HipBackend(), hbm_budget=8 << 30, max_batch=4)
+    srv = Server(HipBackend(normal=normal), hbm_budget=8 << 30, max_batch=4)
     reqs = []
     for i, ((g, kind, n), d) in enumerate(zip(plan, datas)):
         r = Request(geom=g, d=d, niter=n, h_dtype=kind, lam=1e-3 * (i % 3))
@@ -48,7 +49,7 @@ def test_results_alone_equal_results_in_the_mix():
     assert max(st["batch_hist"]) > 1
     for r, d in zip(reqs, datas):
         assert r.status == "done"
-        alone = Server(HipBackend(), hbm_budget=8 << 30, max_batch=4)
+        alone = Server(HipBackend(normal=normal), hbm_budget=8 << 30, max_batch=4)
         a = alone.submit(Request(geom=r.geom, d=d, niter=r.niter, h_dtype=r.h_dtype, lam=r.lam))
         alone.run_until_idle()
         torch.cuda.synchronize()

@@ -58,7 +58,7 @@ class CpuBackend:
         return {"x": np.zeros((cap,) + op.x_shape), "z": np.zeros((cap,) + op.x_shape),
                 "d": np.zeros((cap,) + op.d_shape), "bad": np.zeros(cap, dtype=int)}, None
 
-    def load_row(self, pool, i, d, stream):
+    def load_row(self, pool, i, d, stream, op=None):
         pool["d"][i] = d
         pool["x"][i] = 0
         pool["z"][i] = 0
