@@ -48,7 +48,7 @@ template <int N, int DIR>
 __global__ __launch_bounds__(256) void k_fft_cols(const float2* __restrict__ in,
                                                   float2* __restrict__ out, int nh, int S,
                                                   int rs, const int32_t* __restrict__ imap,
-                                                  const int32_t* __restrict__ omap) {
+                                                  const int32_t* __restrict__ omap, int sfast) {
   constexpr int N1 = Split<N>::N1, N2 = Split<N>::N2;
   constexpr int SB = 16;       // slices per block
   constexpr int PAD = N + 1;   // LDS stride per slice (complex)
@@ -58,8 +58,10 @@ __global__ __launch_bounds__(256) void k_fft_cols(const float2* __restrict__ in,
   __shared__ int rin[N], rout[N];
   const int tid = threadIdx.x;
   const int s = tid % SB, t = tid / SB;
-  const int m = blockIdx.y;
-  const int sg = blockIdx.x * SB + s;
+  // grid order: slice blocks fastest for very wide rows (adjacent workgroups
+  // share rows), frequency columns fastest otherwise (spreads channels)
+  const int m = sfast ? blockIdx.y : blockIdx.x;
+  const int sg = (sfast ? blockIdx.x : blockIdx.y) * SB + s;
   const bool live = sg < S;
   load_twiddles<N, DIR>(tw, tid, NT);
   for (int y = tid; y < N; y += NT) {
@@ -94,15 +96,14 @@ __global__ __launch_bounds__(256) void k_fft_cols(const float2* __restrict__ in,
 
 // ---------------------------------------------------------- rows, r2c (x)
 // T[(j*nh + m)*rs + s] = sum_i exp(-2 pi i m i / N) f[s][j][i],  m = 0..N/2
-// The 32 rows of a block are read with 16-byte loads into LDS, packed in
+// The 2Q rows of a block are read with 16-byte loads into LDS, packed in
 // pairs as z = f[2q] + i f[2q+1]; after the transform the two real spectra are
 // separated and written slice-fastest (contiguous across threads).
-template <int N>
+template <int N, int Q>  // Q packed complex sequences = 2Q real slices per block
 __global__ __launch_bounds__(256) void k_fft_rows_r2c(const float* __restrict__ f,
                                                       float2* __restrict__ T, int ny, int S,
                                                       int rs) {
   constexpr int N1 = Split<N>::N1, N2 = Split<N>::N2;
-  constexpr int Q = 16;        // packed complex sequences = 32 real slices
   constexpr int PAD = N + 1;
   constexpr int NT = Q * N1;
   constexpr int NH = N / 2 + 1;
@@ -178,13 +179,12 @@ __global__ __launch_bounds__(256) void k_fft_rows_r2c(const float* __restrict__ 
 // ---------------------------------------------------------- rows, c2r (x)
 // f[s][j][i] = scale * sum_{m=0}^{N-1} exp(+2 pi i m i / N) F[m] - sub[s][j][i],
 // F Hermitian-extended from m = 0..N/2 (imaginary parts of m = 0, N/2 dropped)
-template <int N>
+template <int N, int Q>
 __global__ __launch_bounds__(256) void k_fft_rows_c2r(const float2* __restrict__ T,
                                                       float* __restrict__ f, int ny, int S,
                                                       int rs, float scale,
                                                       const float* __restrict__ sub) {
   constexpr int N1 = Split<N>::N1, N2 = Split<N>::N2;
-  constexpr int Q = 16;
   constexpr int PAD = N + 1;
   constexpr int NT = Q * N1;
   constexpr int NH = N / 2 + 1;
@@ -289,8 +289,9 @@ __global__ __launch_bounds__(256) void k_fft_rows_c2r(const float2* __restrict__
 template <int N, int DIR>
 static void launch_cols(const float2* in, float2* out, int nh, int S, int rs, const int32_t* imap,
                         const int32_t* omap, hipStream_t st) {
-  dim3 grid((S + 15) / 16, nh);
-  k_fft_cols<N, DIR><<<grid, 16 * Split<N>::N1, 0, st>>>(in, out, nh, S, rs, imap, omap);
+  const int sfast = S >= 2048;
+  dim3 grid = sfast ? dim3((S + 15) / 16, nh) : dim3(nh, (S + 15) / 16);
+  k_fft_cols<N, DIR><<<grid, 16 * Split<N>::N1, 0, st>>>(in, out, nh, S, rs, imap, omap, sfast);
 }
 
 template <int DIR>
@@ -308,17 +309,34 @@ static pat_status cols(const float2* in, float2* out, int ny, int nh, int S, int
   return PAT_OK;
 }
 
+template <int N, int Q>
+static void rows_r2c(const float* f, float2* T, int ny, int S, hipStream_t st) {
+  dim3 grid(ny, (S + 2 * Q - 1) / (2 * Q));
+  k_fft_rows_r2c<N, Q><<<grid, Q * Split<N>::N1, 0, st>>>(f, T, ny, S, S);
+}
+
+template <int N, int Q>
+static void rows_c2r(const float2* T, float* f, int ny, int S, float scale, const float* sub,
+                     hipStream_t st) {
+  dim3 grid(ny, (S + 2 * Q - 1) / (2 * Q));
+  k_fft_rows_c2r<N, Q><<<grid, Q * Split<N>::N1, 0, st>>>(T, f, ny, S, S, scale, sub);
+}
+
+// 8 packed sequences (16 real slices) per row block: small enough for several
+// resident workgroups per CU, large enough for full 16-byte row loads
+constexpr int kRowQ = 8;
+#define PAT_ROWS(fn, N, ...) (fn<N, kRowQ>(__VA_ARGS__))
+
 pat_status fft2_r2c(const float* f, float2* T, float2* X, int nx, int ny, int S,
                     const int32_t* rowmap, hipStream_t st) {
   if (S <= 0) return PAT_OK;
   const int nh = nx / 2 + 1;
-  dim3 grid(ny, (S + 31) / 32);
   switch (nx) {
-    case 16: k_fft_rows_r2c<16><<<grid, 16 * Split<16>::N1, 0, st>>>(f, T, ny, S, S); break;
-    case 32: k_fft_rows_r2c<32><<<grid, 16 * Split<32>::N1, 0, st>>>(f, T, ny, S, S); break;
-    case 64: k_fft_rows_r2c<64><<<grid, 16 * Split<64>::N1, 0, st>>>(f, T, ny, S, S); break;
-    case 128: k_fft_rows_r2c<128><<<grid, 16 * Split<128>::N1, 0, st>>>(f, T, ny, S, S); break;
-    case 256: k_fft_rows_r2c<256><<<grid, 16 * Split<256>::N1, 0, st>>>(f, T, ny, S, S); break;
+    case 16: PAT_ROWS(rows_r2c, 16, f, T, ny, S, st); break;
+    case 32: PAT_ROWS(rows_r2c, 32, f, T, ny, S, st); break;
+    case 64: PAT_ROWS(rows_r2c, 64, f, T, ny, S, st); break;
+    case 128: PAT_ROWS(rows_r2c, 128, f, T, ny, S, st); break;
+    case 256: PAT_ROWS(rows_r2c, 256, f, T, ny, S, st); break;
     default: return fail(PAT_EUNSUPPORTED, "nx must be a power of two in [16, 256]");
   }
   PAT_LAUNCHED("fft rows r2c");
@@ -330,13 +348,12 @@ pat_status fft2_c2r(const float2* X, float2* T, float* f, int nx, int ny, int S,
   if (S <= 0) return PAT_OK;
   const int nh = nx / 2 + 1;
   PAT_TRY(cols<+1>(X, T, ny, nh, S, S, rowmap, nullptr, st));
-  dim3 grid(ny, (S + 31) / 32);
   switch (nx) {
-    case 16: k_fft_rows_c2r<16><<<grid, 16 * Split<16>::N1, 0, st>>>(T, f, ny, S, S, scale, sub); break;
-    case 32: k_fft_rows_c2r<32><<<grid, 16 * Split<32>::N1, 0, st>>>(T, f, ny, S, S, scale, sub); break;
-    case 64: k_fft_rows_c2r<64><<<grid, 16 * Split<64>::N1, 0, st>>>(T, f, ny, S, S, scale, sub); break;
-    case 128: k_fft_rows_c2r<128><<<grid, 16 * Split<128>::N1, 0, st>>>(T, f, ny, S, S, scale, sub); break;
-    case 256: k_fft_rows_c2r<256><<<grid, 16 * Split<256>::N1, 0, st>>>(T, f, ny, S, S, scale, sub); break;
+    case 16: PAT_ROWS(rows_c2r, 16, T, f, ny, S, scale, sub, st); break;
+    case 32: PAT_ROWS(rows_c2r, 32, T, f, ny, S, scale, sub, st); break;
+    case 64: PAT_ROWS(rows_c2r, 64, T, f, ny, S, scale, sub, st); break;
+    case 128: PAT_ROWS(rows_c2r, 128, T, f, ny, S, scale, sub, st); break;
+    case 256: PAT_ROWS(rows_c2r, 256, T, f, ny, S, scale, sub, st); break;
     default: return fail(PAT_EUNSUPPORTED, "nx must be a power of two in [16, 256]");
   }
   PAT_LAUNCHED("fft rows c2r");
