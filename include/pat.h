@@ -135,6 +135,13 @@ pat_status pat_get_info(const pat_op* op, pat_op_info* info);
  * rows no frequency maps to.  Host only. */
 pat_status pat_spectrum_rows(const pat_op* op, int32_t* k_of_row);
 
+/* Row stride, in complex elements, of a spectrum array holding S slices
+ * (see pat_spectrum): S rounded up to a multiple of 64, plus 32 (an odd
+ * multiple of 256 bytes).  The padding keeps rows from being a power of two
+ * long, which would put the rows the transforms touch together on the same
+ * HBM channels.  EINVAL for S outside [1, 2^30].  Host only. */
+pat_status pat_spectrum_stride(int32_t S, int32_t* stride);
+
 /* Workspace bytes every call below needs for a batch of B objects. */
 pat_status pat_workspace_bytes(const pat_op* op, int32_t B, size_t* bytes);
 
@@ -151,8 +158,10 @@ pat_status pat_apply_AT(pat_op* op, const float* y, float* x, int32_t B,
 /* The three steps of an apply (Sec. 3.2), for callers that work in the
  * transverse Fourier domain.  Spectra are complex64 (interleaved re, im
  * float pairs), one row per r2c half-spectrum frequency, slice index fastest:
- *     spec[r][s],  r = 0 .. spec_rows-1,  s = b*n + i
- * (n = nz for object spectra, nt for data spectra).  Rows are ordered by
+ *     spec[r*rs + s],  r = 0 .. spec_rows-1,  s = b*n + i < S,
+ * rs = pat_spectrum_stride(S), S = B*n (n = nz for object spectra, nt for
+ * data spectra); a spectrum array holds spec_rows*rs complex values and the
+ * padding s >= S of each row is neither read nor written.  Rows are ordered by
  * symmetry class, members of a class adjacent, so that the contraction
  * streams contiguous rows; row r holds frequency k = k_of_row[r] from
  * pat_spectrum_rows (k = p*(nx/2+1) + m; -1 marks an unused row, whose
@@ -165,7 +174,8 @@ pat_status pat_apply_AT(pat_op* op, const float* y, float* x, int32_t B,
  * slices (step (iii); sub may be NULL, else it has the layout of f).  Both need
  * a workspace sized by pat_workspace_bytes for some B with S <= B*max(nz, nt).
  * pat_contract (step (ii)): adjoint == 0: out[k][b*nt+n] = sum_l H^[k,l,n] in[k][b*nz+l];
- * adjoint != 0: out[k][b*nz+l] = sum_n conj(H^[k,l,n]) in[k][b*nt+n]; no workspace. */
+ * adjoint != 0: out[k][b*nz+l] = sum_n conj(H^[k,l,n]) in[k][b*nt+n]; rows of
+ * in and out have the strides of B*nz and B*nt slices; no workspace. */
 pat_status pat_spectrum(pat_op* op, const float* f, float* spec, int32_t S, void* ws,
                         size_t ws_bytes, void* stream);
 pat_status pat_inverse_spectrum(pat_op* op, const float* spec, float* f, int32_t S, const float* sub,

@@ -55,6 +55,7 @@ SIGNATURES = {
     "pat_workspace_bytes": [_vp, _i32, C.POINTER(_sz)],
     "pat_get_info": [_vp, C.POINTER(OpInfo)],
     "pat_spectrum_rows": [_vp, C.POINTER(_i32)],
+    "pat_spectrum_stride": [_i32, C.POINTER(_i32)],
     "pat_apply_A": [_vp, _vp, _vp, _i32, _vp, _sz, _vp],
     "pat_apply_AT": [_vp, _vp, _vp, _i32, _vp, _sz, _vp],
     "pat_power_norm": [_vp, _vp, _i32, C.POINTER(_f64), C.POINTER(_f64), _vp, _sz, _vp],

@@ -310,16 +310,16 @@ static pat_status cols(const float2* in, float2* out, int ny, int nh, int S, int
 }
 
 template <int N, int Q>
-static void rows_r2c(const float* f, float2* T, int ny, int S, hipStream_t st) {
+static void rows_r2c(const float* f, float2* T, int ny, int S, int rs, hipStream_t st) {
   dim3 grid(ny, (S + 2 * Q - 1) / (2 * Q));
-  k_fft_rows_r2c<N, Q><<<grid, Q * Split<N>::N1, 0, st>>>(f, T, ny, S, S);
+  k_fft_rows_r2c<N, Q><<<grid, Q * Split<N>::N1, 0, st>>>(f, T, ny, S, rs);
 }
 
 template <int N, int Q>
-static void rows_c2r(const float2* T, float* f, int ny, int S, float scale, const float* sub,
+static void rows_c2r(const float2* T, float* f, int ny, int S, int rs, float scale, const float* sub,
                      hipStream_t st) {
   dim3 grid(ny, (S + 2 * Q - 1) / (2 * Q));
-  k_fft_rows_c2r<N, Q><<<grid, Q * Split<N>::N1, 0, st>>>(T, f, ny, S, S, scale, sub);
+  k_fft_rows_c2r<N, Q><<<grid, Q * Split<N>::N1, 0, st>>>(T, f, ny, S, rs, scale, sub);
 }
 
 // 8 packed sequences (16 real slices) per row block: small enough for several
@@ -331,29 +331,31 @@ pat_status fft2_r2c(const float* f, float2* T, float2* X, int nx, int ny, int S,
                     const int32_t* rowmap, hipStream_t st) {
   if (S <= 0) return PAT_OK;
   const int nh = nx / 2 + 1;
+  const int rs = spec_stride(S);
   switch (nx) {
-    case 16: PAT_ROWS(rows_r2c, 16, f, T, ny, S, st); break;
-    case 32: PAT_ROWS(rows_r2c, 32, f, T, ny, S, st); break;
-    case 64: PAT_ROWS(rows_r2c, 64, f, T, ny, S, st); break;
-    case 128: PAT_ROWS(rows_r2c, 128, f, T, ny, S, st); break;
-    case 256: PAT_ROWS(rows_r2c, 256, f, T, ny, S, st); break;
+    case 16: PAT_ROWS(rows_r2c, 16, f, T, ny, S, rs, st); break;
+    case 32: PAT_ROWS(rows_r2c, 32, f, T, ny, S, rs, st); break;
+    case 64: PAT_ROWS(rows_r2c, 64, f, T, ny, S, rs, st); break;
+    case 128: PAT_ROWS(rows_r2c, 128, f, T, ny, S, rs, st); break;
+    case 256: PAT_ROWS(rows_r2c, 256, f, T, ny, S, rs, st); break;
     default: return fail(PAT_EUNSUPPORTED, "nx must be a power of two in [16, 256]");
   }
   PAT_LAUNCHED("fft rows r2c");
-  return cols<-1>(T, X, ny, nh, S, S, nullptr, rowmap, st);
+  return cols<-1>(T, X, ny, nh, S, rs, nullptr, rowmap, st);
 }
 
 pat_status fft2_c2r(const float2* X, float2* T, float* f, int nx, int ny, int S, float scale,
                     const float* sub, const int32_t* rowmap, hipStream_t st) {
   if (S <= 0) return PAT_OK;
   const int nh = nx / 2 + 1;
-  PAT_TRY(cols<+1>(X, T, ny, nh, S, S, rowmap, nullptr, st));
+  const int rs = spec_stride(S);
+  PAT_TRY(cols<+1>(X, T, ny, nh, S, rs, rowmap, nullptr, st));
   switch (nx) {
-    case 16: PAT_ROWS(rows_c2r, 16, T, f, ny, S, scale, sub, st); break;
-    case 32: PAT_ROWS(rows_c2r, 32, T, f, ny, S, scale, sub, st); break;
-    case 64: PAT_ROWS(rows_c2r, 64, T, f, ny, S, scale, sub, st); break;
-    case 128: PAT_ROWS(rows_c2r, 128, T, f, ny, S, scale, sub, st); break;
-    case 256: PAT_ROWS(rows_c2r, 256, T, f, ny, S, scale, sub, st); break;
+    case 16: PAT_ROWS(rows_c2r, 16, T, f, ny, S, rs, scale, sub, st); break;
+    case 32: PAT_ROWS(rows_c2r, 32, T, f, ny, S, rs, scale, sub, st); break;
+    case 64: PAT_ROWS(rows_c2r, 64, T, f, ny, S, rs, scale, sub, st); break;
+    case 128: PAT_ROWS(rows_c2r, 128, T, f, ny, S, rs, scale, sub, st); break;
+    case 256: PAT_ROWS(rows_c2r, 256, T, f, ny, S, rs, scale, sub, st); break;
     default: return fail(PAT_EUNSUPPORTED, "nx must be a power of two in [16, 256]");
   }
   PAT_LAUNCHED("fft rows c2r");

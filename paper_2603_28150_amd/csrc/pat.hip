@@ -238,11 +238,12 @@ static Work work_layout(const pat_op* op, int B, char* base) {
     o = align_up(o + bytes, 256);
     return p;
   };
-  w.Xs = (float2*)take((size_t)op->nrows * Sz * 8);  // nrows = nitem * G
-  w.Ds = (float2*)take((size_t)op->nrows * St * 8);
-  w.T = (float2*)take((size_t)g.ny * op->nh * std::max(Sz, St) * 8);
-  w.Bs = (float2*)take((size_t)op->nrows * Sz * 8);
-  w.Gs = (float2*)take((size_t)op->nrows * Sz * 8);
+  const size_t rz = spec_stride((int)Sz), rt = spec_stride((int)St);
+  w.Xs = (float2*)take((size_t)op->nrows * rz * 8);  // nrows = nitem * G
+  w.Ds = (float2*)take((size_t)op->nrows * rt * 8);
+  w.T = (float2*)take((size_t)g.ny * op->nh * std::max(rz, rt) * 8);
+  w.Bs = (float2*)take((size_t)op->nrows * rz * 8);
+  w.Gs = (float2*)take((size_t)op->nrows * rz * 8);
   w.V = (float*)take(Sz * nxy * 4);
   w.U = (float*)take(Sz * nxy * 4);
   w.Z = (float*)take(Sz * nxy * 4);
@@ -312,8 +313,8 @@ static pat_status run_contract(pat_op* op, bool adjoint, const float2* in, float
       m.in_scale = nullptr;
       m.out_scale = sc;
     }
-    m.in_rs = B * m.K;
-    m.out_rs = B * m.N;
+    m.in_rs = spec_stride(B * m.K);
+    m.out_rs = spec_stride(B * m.N);
     return contract_mfma(m, g.h_dtype, st);
   }
   if (!adjoint) {
@@ -332,8 +333,8 @@ static pat_status run_contract(pat_op* op, bool adjoint, const float2* in, float
     a.s_row = op->sT_row;
   }
   a.slab_elems = (long long)a.ni * a.s_row;
-  a.in_rs = B * a.ni;
-  a.out_rs = B * a.nj;
+  a.in_rs = spec_stride(B * a.ni);
+  a.out_rs = spec_stride(B * a.nj);
   return contract(a, g.h_dtype, op->G, B, st);
 }
 
@@ -354,8 +355,8 @@ static pat_status run_gram(pat_op* op, const float2* in, float2* out, const floa
   a.nj = g.nz;
   a.s_row = op->sG_row;
   a.slab_elems = (long long)g.nz * op->sG_row;
-  a.in_rs = B * g.nz;
-  a.out_rs = B * g.nz;
+  a.in_rs = spec_stride(B * g.nz);
+  a.out_rs = spec_stride(B * g.nz);
   a.nitem = op->nitem;
   return contract(a, PAT_H_F32, op->G, B, st);
 }
@@ -583,6 +584,13 @@ pat_status pat_get_info(const pat_op* op, pat_op_info* info) {
 pat_status pat_spectrum_rows(const pat_op* op, int32_t* k_of_row) {
   if (!op || !k_of_row) return fail(PAT_EINVAL, "null argument");
   for (int r = 0; r < op->nrows; ++r) k_of_row[r] = op->h_members[r];
+  return PAT_OK;
+}
+
+pat_status pat_spectrum_stride(int32_t S, int32_t* stride) {
+  if (!stride) return fail(PAT_EINVAL, "null argument");
+  if (S < 1 || S > (1 << 30)) return fail(PAT_EINVAL, "S must be in [1, 2^30]");
+  *stride = spec_stride(S);
   return PAT_OK;
 }
 

@@ -29,12 +29,19 @@ pat_status hip_check(hipError_t e, const char* what);
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // --------------------------------------------------------------- 2D FFTs
-// Slice layouts (S slices, element type float / float2):
+// Row stride (complex elements) of frequency-major arrays holding S slices:
+// S rounded up to 64, plus 32, i.e. an odd multiple of 256 bytes and never a
+// power of two.  Power-of-two strides (4 KB .. 64 KB at the usual slice
+// counts) map the rows read or written together onto the same few HBM
+// channels and halve the column pass's bandwidth.
+inline int spec_stride(int S) { return (S + 63) / 64 * 64 + 32; }
+
+// Slice layouts (S slices, element type float / float2, rs = spec_stride(S)):
 //   real slices      f[s][ny][nx]
-//   half spectrum    X[row(p*nh + m) * S + s] (frequency rows, slice fastest;
+//   half spectrum    X[row(p*nh + m) * rs + s] (frequency rows, slice fastest;
 //                    nh = nx/2 + 1; row() is the class-major row map, or the
 //                    identity when rowmap is null)
-//   row-transformed  T[(j*nh + m) * S + s]   (y not yet transformed)
+//   row-transformed  T[(j*nh + m) * rs + s]   (y not yet transformed)
 // Forward transforms are unnormalised; the inverse multiplies by `scale`.
 pat_status fft_init_device();  // uploads the twiddle table to the current device
 pat_status fft2_r2c(const float* f, float2* T, float2* X, int nx, int ny, int S,

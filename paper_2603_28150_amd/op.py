@@ -121,7 +121,8 @@ class Operator:
 
     # ---------------------------------------------------- stage-level calls
     def spectrum(self, f: torch.Tensor, S: int, out: torch.Tensor, B_ws: int = 1) -> torch.Tensor:
-        """Step (i): half spectrum [nk][S] (complex64 as float pairs) of S real slices."""
+        """Step (i): half spectrum (rows of spectrum_stride(S) complex64 values
+        as float pairs, see spectrum_rows) of S real slices."""
         ws = self.workspace(B_ws)
         _lib.call("pat_spectrum", self.handle, _ptr(f), _ptr(out), S, _ptr(ws), ws.numel(),
                   _stream(self.device))
@@ -149,8 +150,18 @@ class Operator:
         _lib.call("pat_spectrum_rows", self.handle, arr)
         return list(arr)
 
+    @staticmethod
+    def spectrum_stride(S: int) -> int:
+        """Row stride (complex elements) of a spectrum array of S slices."""
+        n = C.c_int32()
+        _lib.call("pat_spectrum_stride", S, C.byref(n))
+        return n.value
+
     def spectrum_buffer(self, S: int) -> torch.Tensor:
-        return torch.empty((self.info()["spec_rows"], S, 2), dtype=torch.float32, device=self.device)
+        """Spectrum array [spec_rows][stride][2] for S slices; entries s >= S
+        of a row are padding."""
+        rs = self.spectrum_stride(S)
+        return torch.empty((self.info()["spec_rows"], rs, 2), dtype=torch.float32, device=self.device)
 
     def workspace_bytes(self, B: int = 1) -> int:
         n = C.c_size_t()

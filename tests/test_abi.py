@@ -61,3 +61,17 @@ def test_host_only_calls(lib):
     assert L.pat_H_bytes(ctypes.byref(neg), ctypes.byref(hb), ctypes.byref(sb)) == -1
     small = _lib.Geometry(32, 32, 16, 64, 1e-4, 1e-4, 1e-4, 2e-8, 1500.0, 8, 0)
     assert L.pat_H_bytes(ctypes.byref(small), ctypes.byref(hb), ctypes.byref(sb)) == -1
+
+
+def test_spectrum_stride(lib):
+    # rows of a spectrum array: at least S, an odd multiple of 32 complex
+    # values (256 bytes), hence never a power of two
+    from paper_2603_28150_amd import _lib
+    L = _lib.load()
+    rs = ctypes.c_int32()
+    for S in [1, 13, 32, 37, 128, 512, 2048, 8192, 3 * 512]:
+        assert L.pat_spectrum_stride(S, ctypes.byref(rs)) == 0
+        assert rs.value >= S + 1 and rs.value % 64 == 32 and rs.value - S <= 95
+        assert rs.value & (rs.value - 1) != 0
+    assert L.pat_spectrum_stride(0, ctypes.byref(rs)) == -1
+    assert L.pat_spectrum_stride(8, None) == -1
