@@ -62,32 +62,13 @@ __device__ __forceinline__ void contract_item(const ContractArgs& a, int lr_log2
   typedef Slab<HT> SL;
   typedef typename SL::raw_t raw_t;
   constexpr int VEC = SL::VEC;
-  constexpr int U = 8 / JPT;                // rows in flight per thread
+  constexpr int U = 4 / JPT;                // rows per register buffer
   constexpr int NS = JPT * VEC * GG * 2;    // accumulators per thread
   float2* xin = reinterpret_cast<float2*>(smem_raw);
   float* red = reinterpret_cast<float*>(smem_raw);
   const int tid = threadIdx.x;
   const int Lr = 1 << lr_log2, R = 256 >> lr_log2;
   const int lr = tid & (Lr - 1), rg = tid >> lr_log2;
-
-  // member input vectors, [i][g], with the optional per-row scale applied
-  for (int idx = tid; idx < a.ni * GG; idx += 256) {
-    const int i = idx / GG, g = idx % GG;
-    int k = -1;
-#pragma unroll
-    for (int gg = 0; gg < GG; ++gg) k = (gg == g) ? kg[gg] : k;
-    float2 v = make_float2(0.f, 0.f);
-    if (k >= 0) {
-      v = a.in[(size_t)(t * G + g) * a.in_rs + (size_t)b * a.ni + i];
-      if (a.in_scale) v = cscale(v, a.in_scale[i]);
-    }
-    xin[idx] = v;
-  }
-  __syncthreads();
-
-  float acc[NS];
-#pragma unroll
-  for (int s = 0; s < NS; ++s) acc[s] = 0.f;
 
   const HT* slab = reinterpret_cast<const HT*>(a.slab) + (size_t)a.item_slab[t] * a.slab_elems;
   const int nchunks = (a.nj + VEC - 1) / VEC;
@@ -97,24 +78,71 @@ __device__ __forceinline__ void contract_item(const ContractArgs& a, int lr_log2
   for (int jj = 0; jj < JPT; ++jj) {
     const int ch = lr + jj * Lr;
     cl[jj] = ch < nchunks;
-    colp[jj] = slab + (size_t)ch * VEC;
+    colp[jj] = slab + (size_t)min(ch, nchunks - 1) * VEC;  // clamped: always a valid address
   }
 
-  for (int i0 = rg; i0 < a.ni; i0 += R * U) {
-    raw_t raw[U][JPT];
+  // Rows in flight: the loads of the next U rows are issued before the FMAs
+  // of the current ones (two register buffers), so that every wave keeps
+  // memory requests outstanding while it computes.  Loads are unconditional
+  // (rows and chunks clamped into the slab, the value zeroed by a select) so
+  // that no branch hides them from the wait counter.
+  auto load_rows = [&](raw_t (&raw)[U][JPT], int i0) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int i = i0 + u * R;
+      const int ic = min(i, a.ni - 1);
 #pragma unroll
       for (int jj = 0; jj < JPT; ++jj) {
-        if (i < a.ni && cl[jj]) {
-          raw[u][jj] = __builtin_nontemporal_load(
-              reinterpret_cast<const raw_t*>(colp[jj] + (size_t)i * a.s_row));
-        } else {
-          raw[u][jj] = raw_t(0);
-        }
+        const raw_t v = __builtin_nontemporal_load(
+            reinterpret_cast<const raw_t*>(colp[jj] + (size_t)ic * a.s_row));
+        raw[u][jj] = (i < a.ni && cl[jj]) ? v : raw_t(0);
       }
     }
+  };
+  raw_t ra[U][JPT], rb[U][JPT];
+  load_rows(ra, rg);  // the first rows travel while the member vectors are staged
+
+  // member input vectors -> LDS xin[i][g], with the optional per-row scale;
+  // 16-byte loads along each member row when the row length is even
+  if ((a.ni & 1) == 0) {
+    const int h = a.ni >> 1;
+    for (int idx = tid; idx < GG * h; idx += 256) {
+      const int g = idx / h, i = 2 * (idx - g * h);
+      int k = -1;
+#pragma unroll
+      for (int gg = 0; gg < GG; ++gg) k = (gg == g) ? kg[gg] : k;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (k >= 0) {
+        v = *reinterpret_cast<const float4*>(a.in + (size_t)(t * G + g) * a.in_rs + (size_t)b * a.ni + i);
+        if (a.in_scale) {
+          const float s0 = a.in_scale[i], s1 = a.in_scale[i + 1];
+          v = make_float4(v.x * s0, v.y * s0, v.z * s1, v.w * s1);
+        }
+      }
+      xin[i * GG + g] = make_float2(v.x, v.y);
+      xin[(i + 1) * GG + g] = make_float2(v.z, v.w);
+    }
+  } else {
+    for (int idx = tid; idx < a.ni * GG; idx += 256) {
+      const int i = idx / GG, g = idx % GG;
+      int k = -1;
+#pragma unroll
+      for (int gg = 0; gg < GG; ++gg) k = (gg == g) ? kg[gg] : k;
+      float2 v = make_float2(0.f, 0.f);
+      if (k >= 0) {
+        v = a.in[(size_t)(t * G + g) * a.in_rs + (size_t)b * a.ni + i];
+        if (a.in_scale) v = cscale(v, a.in_scale[i]);
+      }
+      xin[idx] = v;
+    }
+  }
+  __syncthreads();
+
+  float acc[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) acc[s] = 0.f;
+
+  auto fma_rows = [&](const raw_t (&raw)[U][JPT], int i0) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int i = i0 + u * R;
@@ -136,6 +164,13 @@ __device__ __forceinline__ void contract_item(const ContractArgs& a, int lr_log2
         }
       }
     }
+  };
+  for (int i0 = rg; i0 < a.ni; i0 += 2 * R * U) {
+    load_rows(rb, i0 + R * U);
+    fma_rows(ra, i0);
+    if (i0 + R * U >= a.ni) break;
+    load_rows(ra, i0 + 2 * R * U);
+    fma_rows(rb, i0 + R * U);
   }
 
   // add the partial sums of the R row groups (fixed order: deterministic)
@@ -176,14 +211,35 @@ __device__ __forceinline__ void contract_item(const ContractArgs& a, int lr_log2
     }
   }
   __syncthreads();
-  for (int e = tid; e < GG * a.nj; e += 256) {
-    const int g = e / a.nj, j = e - g * a.nj;
-    int k = -1;
+  if ((a.nj & 1) == 0) {
+    // two complex values (16 bytes) per store, non-temporal: the rows are
+    // not read again by this kernel
+    const int h = a.nj >> 1;
+    for (int e = tid; e < GG * h; e += 256) {
+      const int g = e / h, j = 2 * (e - g * h);
+      int k = -1;
 #pragma unroll
-    for (int gg = 0; gg < GG; ++gg) k = (gg == g) ? kg[gg] : k;
-    if (k >= 0) {
-      const size_t o = (size_t)(t * G + g) * a.out_rs + (size_t)b * a.nj + j;
-      a.out[o] = a.out_sub ? csub(ob[e], a.out_sub[o]) : ob[e];
+      for (int gg = 0; gg < GG; ++gg) k = (gg == g) ? kg[gg] : k;
+      if (k >= 0) {
+        const size_t o = (size_t)(t * G + g) * a.out_rs + (size_t)b * a.nj + j;
+        float4 v = *reinterpret_cast<const float4*>(ob + g * a.nj + j);
+        if (a.out_sub) {
+          const float4 s = *reinterpret_cast<const float4*>(a.out_sub + o);
+          v = make_float4(v.x - s.x, v.y - s.y, v.z - s.z, v.w - s.w);
+        }
+        __builtin_nontemporal_store(v4f{v.x, v.y, v.z, v.w}, reinterpret_cast<v4f*>(a.out + o));
+      }
+    }
+  } else {
+    for (int e = tid; e < GG * a.nj; e += 256) {
+      const int g = e / a.nj, j = e - g * a.nj;
+      int k = -1;
+#pragma unroll
+      for (int gg = 0; gg < GG; ++gg) k = (gg == g) ? kg[gg] : k;
+      if (k >= 0) {
+        const size_t o = (size_t)(t * G + g) * a.out_rs + (size_t)b * a.nj + j;
+        a.out[o] = a.out_sub ? csub(ob[e], a.out_sub[o]) : ob[e];
+      }
     }
   }
 }
