@@ -14,6 +14,7 @@ Prints ONE JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import platform
@@ -118,16 +119,28 @@ def cpu_baseline(x64: np.ndarray, budget_s: float = 12.0) -> dict:
             "cpu": platform.processor() or platform.machine()}
 
 
+CONTRACT_SRC = os.path.join(ROOT, "paper_2603_28150_amd", "csrc", "contract.hip")
+
+
+def source_sha256(path: str) -> str:
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
 def profile_traffic(kernel_bytes: int):
-    """HBM traffic of the contraction from committed rocprofv3 PMC summaries, if present."""
+    """HBM traffic of the contraction from the committed rocprofv3 PMC summary,
+    or None when there is none or it was taken on a different kernel source."""
     p = os.path.join(ROOT, "profiles", "contract_fp32_256x256x128x512_traffic.json")
     if not os.path.exists(p):
         return None
     try:
         with open(p) as f:
-            return json.load(f).get("traffic_bytes_per_launch")
+            d = json.load(f)
     except (OSError, ValueError):
         return None
+    if d.get("source_sha256") != source_sha256(CONTRACT_SRC):
+        return None
+    return d.get("traffic_bytes_per_launch")
 
 
 def main():
