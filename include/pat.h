@@ -118,10 +118,12 @@ pat_status pat_H_export(pat_op* op, int32_t k0, int32_t nk, float* out, void* st
 
 /* Shape of the stored library: nk half-spectrum frequencies, nclass stored
  * slabs (symmetry classes: frequencies with equal kx^2 + ky^2 share one), the
- * z-period used, and the bytes of one stored layout (the library keeps two,
- * rows along n for A and along l for A^T).  The contraction runs over
- * nitems work items of up to members_max frequencies; each streams one slab,
- * so one apply reads read_bytes_A (or read_bytes_AT) of library. */
+ * z-period used, and the bytes of one stored row layout (the library keeps
+ * two, rows along n for A and along l for A^T; a 16-bit library also keeps
+ * both as matrix-core operand tiles, padded to 32 x 16, for batches).  The
+ * contraction runs over nitems work items of up to members_max frequencies;
+ * each streams one slab, so one apply of one object reads read_bytes_A (or
+ * read_bytes_AT) of library. */
 typedef struct {
   int32_t nk, nclass, members_max, nz_sim;
   size_t slab_bytes_A, slab_bytes_AT;

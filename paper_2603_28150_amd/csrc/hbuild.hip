@@ -119,43 +119,9 @@ __global__ __launch_bounds__(256) void k_hbuild(HBuildArgs a) {
         if (nl == 0 && l < a.nz)
           atomicMax(&a.amax[l], (unsigned long long)__double_as_longlong(m));
       }
-    } else if (a.hdtype != PAT_H_F32) {
-      // 16-bit library: MFMA fragments for both directions, through the LDS tile
-      __syncthreads();
-#pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int ll = lg + 4 * u, l = l0 + ll;
-        tile[nl * (kLP + 1) + ll] = (l < a.nz) ? (float)(acc[u] * depth_scale(a.amax, l, a.hdtype)) : 0.f;
-      }
-      __syncthreads();
-      const int n0 = blockIdx.x * kNT;
-      for (int dir = 0; dir < 2; ++dir) {
-        // dir 0: rows n, k = l (forward);  dir 1: rows l, k = n (adjoint)
-        const int nt = dir == 0 ? a.ntA : a.ntT, ks = dir == 0 ? a.ksA : a.ksT;
-        const int rt0 = (dir == 0 ? n0 : l0) / 32, kt0 = (dir == 0 ? l0 : n0) / 16;
-        unsigned short* dst = reinterpret_cast<unsigned short*>(dir == 0 ? a.slabA : a.slabT);
-        for (int unit = tid; unit < 8 * 64; unit += 256) {
-          const int f = unit >> 6, L = unit & 63;
-          const int rt = f >> 2, kt = f & 3;
-          if (rt0 + rt >= nt || kt0 + kt >= ks) continue;
-          const int r = rt * 32 + (L & 31), k = kt * 16 + 8 * (L >> 5);
-          unsigned short v[8];
-#pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            const float x = dir == 0 ? tile[r * (kLP + 1) + k + e] : tile[(k + e) * (kLP + 1) + r];
-            v[e] = a.hdtype == PAT_H_BF16 ? to_bf16(x) : to_f16(x);
-          }
-          uint4 pk;
-          pk.x = v[0] | ((unsigned)v[1] << 16);
-          pk.y = v[2] | ((unsigned)v[3] << 16);
-          pk.z = v[4] | ((unsigned)v[5] << 16);
-          pk.w = v[6] | ((unsigned)v[7] << 16);
-          const size_t o = (((size_t)c * nt + rt0 + rt) * ks + kt0 + kt) * 64 + L;
-          reinterpret_cast<uint4*>(dst)[o] = pk;
-        }
-      }
     } else {
-      // [l][n] slab: lanes along n, coalesced
+      // [l][n] rows: lanes along n, coalesced; the scaled values also go to
+      // the LDS tile for the transposed and the fragment layouts
       __syncthreads();
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
@@ -165,22 +131,51 @@ __global__ __launch_bounds__(256) void k_hbuild(HBuildArgs a) {
         tile[nl * (kLP + 1) + ll] = f;
         if (l < a.nz && n < a.nt) {
           const size_t o = ((size_t)c * a.nz + l) * a.sA_row + n;
-          if (a.hdtype == PAT_H_F32) reinterpret_cast<float*>(a.slabA)[o] = f;
-          else if (a.hdtype == PAT_H_BF16) reinterpret_cast<unsigned short*>(a.slabA)[o] = to_bf16(f);
-          else reinterpret_cast<unsigned short*>(a.slabA)[o] = to_f16(f);
+          if (a.hdtype == PAT_H_F32) reinterpret_cast<float*>(a.rowA)[o] = f;
+          else if (a.hdtype == PAT_H_BF16) reinterpret_cast<unsigned short*>(a.rowA)[o] = to_bf16(f);
+          else reinterpret_cast<unsigned short*>(a.rowA)[o] = to_f16(f);
         }
       }
       __syncthreads();
-      // [n][l] slab: transpose through LDS so that lanes run along l
+      // [n][l] rows: transpose through LDS so that lanes run along l
       for (int e = tid; e < kNT * kLP; e += 256) {
         const int nn = e / kLP, ll = e % kLP;
         const int ng = blockIdx.x * kNT + nn, l = l0 + ll;
         if (ng >= a.nt || l >= a.nz) continue;
         const float f = tile[nn * (kLP + 1) + ll];
         const size_t o = ((size_t)c * a.nt + ng) * a.sT_row + l;
-        if (a.hdtype == PAT_H_F32) reinterpret_cast<float*>(a.slabT)[o] = f;
-        else if (a.hdtype == PAT_H_BF16) reinterpret_cast<unsigned short*>(a.slabT)[o] = to_bf16(f);
-        else reinterpret_cast<unsigned short*>(a.slabT)[o] = to_f16(f);
+        if (a.hdtype == PAT_H_F32) reinterpret_cast<float*>(a.rowT)[o] = f;
+        else if (a.hdtype == PAT_H_BF16) reinterpret_cast<unsigned short*>(a.rowT)[o] = to_bf16(f);
+        else reinterpret_cast<unsigned short*>(a.rowT)[o] = to_f16(f);
+      }
+      if (a.hdtype != PAT_H_F32) {
+        // 16-bit library: MFMA fragments for both directions, from the tile
+        const int n0 = blockIdx.x * kNT;
+        for (int dir = 0; dir < 2; ++dir) {
+          // dir 0: rows n, k = l (forward);  dir 1: rows l, k = n (adjoint)
+          const int nt = dir == 0 ? a.ntA : a.ntT, ks = dir == 0 ? a.ksA : a.ksT;
+          const int rt0 = (dir == 0 ? n0 : l0) / 32, kt0 = (dir == 0 ? l0 : n0) / 16;
+          unsigned short* dst = reinterpret_cast<unsigned short*>(dir == 0 ? a.slabA : a.slabT);
+          for (int unit = tid; unit < 8 * 64; unit += 256) {
+            const int f = unit >> 6, L = unit & 63;
+            const int rt = f >> 2, kt = f & 3;
+            if (rt0 + rt >= nt || kt0 + kt >= ks) continue;
+            const int r = rt * 32 + (L & 31), k = kt * 16 + 8 * (L >> 5);
+            unsigned short v[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              const float x = dir == 0 ? tile[r * (kLP + 1) + k + e] : tile[(k + e) * (kLP + 1) + r];
+              v[e] = a.hdtype == PAT_H_BF16 ? to_bf16(x) : to_f16(x);
+            }
+            uint4 pk;
+            pk.x = v[0] | ((unsigned)v[1] << 16);
+            pk.y = v[2] | ((unsigned)v[3] << 16);
+            pk.z = v[4] | ((unsigned)v[5] << 16);
+            pk.w = v[6] | ((unsigned)v[7] << 16);
+            const size_t o = (((size_t)c * nt + rt0 + rt) * ks + kt0 + kt) * 64 + L;
+            reinterpret_cast<uint4*>(dst)[o] = pk;
+          }
+        }
       }
     }
   }

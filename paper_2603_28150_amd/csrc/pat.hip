@@ -34,8 +34,10 @@ struct pat_op {
   int32_t* cls_freq;  // [nclass][2]
   float* inv_scale;   // [nz]
   unsigned long long* amax;  // [nz]
-  void* slabA;        // [nclass][nz][sA_row]
-  void* slabT;        // [nclass][nt][sT_row]
+  void* slabA;        // FP32: [nclass][nz][sA_row]; 16-bit: MFMA fragments (n, k = l)
+  void* slabT;        // FP32: [nclass][nt][sT_row]; 16-bit: MFMA fragments (l, k = n)
+  void* rowA;         // [nclass][nz][sA_row] rows of the storage type (= slabA for FP32)
+  void* rowT;         // [nclass][nt][sT_row] rows of the storage type (= slabT for FP32)
   float* gram;        // [nclass][nz][sG_row]  Gram blocks of the library
   int sG_row;
   std::vector<int32_t> h_members, h_kclass, h_cls_freq, h_rowmap, h_item_slab;
@@ -169,8 +171,8 @@ static Classes make_classes(const pat_geometry& g) {
 
 struct HLayout {
   size_t off_members, off_items, off_kclass, off_rowmap, off_freq, off_inv, off_amax, off_A, off_T,
-      off_G, total;
-  size_t bytes_A, bytes_T, bytes_G;
+      off_Ar, off_Tr, off_G, total;
+  size_t bytes_A, bytes_T, bytes_Ar, bytes_Tr, bytes_G;
   int sG_row;
   int nclass, nitem, G, vec, sA_row, sT_row;
   int ntA, ksA, ntT, ksT;
@@ -190,9 +192,14 @@ static HLayout h_layout(const pat_geometry& g, const Classes& C) {
   L.ksA = (g.nz + 15) / 16;
   L.ntT = (g.nz + 31) / 32;
   L.ksT = (g.nt + 15) / 16;
+  // rows [slab][l][n] and [slab][n][l] of the storage type, for the VALU
+  // contraction; 16-bit libraries add both layouts as MFMA fragments for
+  // batches (the FP32 rows serve every batch size)
+  L.bytes_Ar = (size_t)L.nclass * g.nz * L.sA_row * esz;
+  L.bytes_Tr = (size_t)L.nclass * g.nt * L.sT_row * esz;
   if (g.h_dtype == PAT_H_F32) {
-    L.bytes_A = (size_t)L.nclass * g.nz * L.sA_row * esz;
-    L.bytes_T = (size_t)L.nclass * g.nt * L.sT_row * esz;
+    L.bytes_A = 0;
+    L.bytes_T = 0;
   } else {
     L.bytes_A = (size_t)L.nclass * L.ntA * L.ksA * 1024;
     L.bytes_T = (size_t)L.nclass * L.ntT * L.ksT * 1024;
@@ -208,6 +215,8 @@ static HLayout h_layout(const pat_geometry& g, const Classes& C) {
   L.off_amax = o;    o = align_up(o + (size_t)g.nz * 8, 256);
   L.sG_row = (int)align_up((size_t)g.nz, 4);
   L.bytes_G = (size_t)L.nclass * g.nz * L.sG_row * 4;
+  L.off_Ar = o;      o = align_up(o + L.bytes_Ar, 256);
+  L.off_Tr = o;      o = align_up(o + L.bytes_Tr, 256);
   L.off_A = o;       o = align_up(o + L.bytes_A, 256);
   L.off_T = o;       o = align_up(o + L.bytes_T, 256);
   L.off_G = o;       o = align_up(o + L.bytes_G, 256);
@@ -287,7 +296,10 @@ static pat_status run_contract(pat_op* op, bool adjoint, const float2* in, float
   a.out_sub = nullptr;
   a.nitem = op->nitem;
   const float* sc = g.h_dtype == PAT_H_F32 ? nullptr : op->inv_scale;
-  if (g.h_dtype != PAT_H_F32) {
+  // one object: the VALU kernel on the row layouts streams the library at
+  // the FP32 kernel's rate; batches go to the matrix cores (one slab read
+  // serves every object)
+  if (g.h_dtype != PAT_H_F32 && B > 1) {
     MfmaArgs m;
     m.members = op->members;
     m.item_slab = op->item_slab;
@@ -318,14 +330,14 @@ static pat_status run_contract(pat_op* op, bool adjoint, const float2* in, float
     return contract_mfma(m, g.h_dtype, st);
   }
   if (!adjoint) {
-    a.slab = op->slabA;
+    a.slab = op->rowA;
     a.in_scale = sc;
     a.out_scale = nullptr;
     a.ni = g.nz;
     a.nj = g.nt;
     a.s_row = op->sA_row;
   } else {
-    a.slab = op->slabT;
+    a.slab = op->rowT;
     a.in_scale = nullptr;
     a.out_scale = sc;
     a.ni = g.nt;
@@ -475,8 +487,11 @@ pat_status pat_H_build(pat_ctx* ctx, const pat_geometry* geom, void* h_buf, size
   op->cls_freq = (int32_t*)(op->hbuf + L.off_freq);
   op->inv_scale = (float*)(op->hbuf + L.off_inv);
   op->amax = (unsigned long long*)(op->hbuf + L.off_amax);
-  op->slabA = op->hbuf + L.off_A;
-  op->slabT = op->hbuf + L.off_T;
+  op->rowA = op->hbuf + L.off_Ar;
+  op->rowT = op->hbuf + L.off_Tr;
+  const bool f32 = geom->h_dtype == PAT_H_F32;
+  op->slabA = f32 ? op->rowA : op->hbuf + L.off_A;
+  op->slabT = f32 ? op->rowT : op->hbuf + L.off_T;
   op->gram = (float*)(op->hbuf + L.off_G);
   op->sG_row = L.sG_row;
   op->h_members = std::move(C.members);
@@ -522,6 +537,8 @@ pat_status pat_H_build(pat_ctx* ctx, const pat_geometry* geom, void* h_buf, size
   a.c = geom->c;
   a.slabA = op->slabA;
   a.slabT = op->slabT;
+  a.rowA = op->rowA;
+  a.rowT = op->rowT;
   a.sA_row = op->sA_row;
   a.sT_row = op->sT_row;
   a.ntA = op->ntA;
@@ -572,11 +589,11 @@ pat_status pat_get_info(const pat_op* op, pat_op_info* info) {
   info->nclass = op->nclass;
   info->members_max = op->G;
   info->nz_sim = op->nq;
-  info->slab_bytes_A = L.bytes_A;
-  info->slab_bytes_AT = L.bytes_T;
+  info->slab_bytes_A = L.bytes_Ar;
+  info->slab_bytes_AT = L.bytes_Tr;
   info->nitems = op->nitem;
-  info->read_bytes_A = L.bytes_A / op->nclass * op->nitem;
-  info->read_bytes_AT = L.bytes_T / op->nclass * op->nitem;
+  info->read_bytes_A = L.bytes_Ar / op->nclass * op->nitem;
+  info->read_bytes_AT = L.bytes_Tr / op->nclass * op->nitem;
   info->spec_rows = op->nrows;
   return PAT_OK;
 }

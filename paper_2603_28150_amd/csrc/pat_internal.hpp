@@ -94,6 +94,8 @@ struct HBuildArgs {
   double dx, dy, dz, dt, c;
   void* slabA;              // FP32: [C][nz][sA_row] (n fastest); 16-bit: fragments (n, k=l)
   void* slabT;              // FP32: [C][nt][sT_row] (l fastest); 16-bit: fragments (l, k=n)
+  void* rowA;               // [C][nz][sA_row] rows of the storage type (= slabA for FP32)
+  void* rowT;               // [C][nt][sT_row] rows of the storage type (= slabT for FP32)
   int sA_row, sT_row;
   int ntA, ksA, ntT, ksT;   // fragment tiling of the 16-bit layouts
   unsigned long long* amax; // [nz] bit patterns of max |H^| per depth

@@ -296,9 +296,11 @@ def test_stage_calls_compose_apply_and_row_map(name):
 @pytest.mark.parametrize("kind", ["bf16", "f16"])
 @pytest.mark.parametrize("name,B", [("tiny", 16), ("ragged", 3), ("mid", 2)])
 def test_quantised_batched_matrix_core_path(kind, name, B):
-    # 16-bit libraries run on the matrix cores; every object of a batch must
-    # match the oracle applying the same quantised library (2e-5) and the
-    # exact oracle (5e-3), and equal its own single-object apply
+    # 16-bit libraries run batches on the matrix cores; every object of a
+    # batch must match the oracle applying the same quantised library (2e-5)
+    # and the exact oracle (5e-3), and agree with its own single-object apply
+    # (the VALU kernel on float32 spectra) to the hi + lo bf16 split of the
+    # spectra that the matrix-core path makes: 2^-17 relative per element
     g = GEOMS[name]
     op = Operator(g, kind)
     Hh = setup(name)[2]
@@ -313,8 +315,8 @@ def test_quantised_batched_matrix_core_path(kind, name, B):
         assert rel(gs[b], ops.AT_fft(Hq, ds[b])) < 2e-5, b
         assert rel(gs[b], ops.AT_fft(Hh, ds[b])) < 5e-3, b
     for b in (0, B - 1):
-        assert rel(ys[b], host(op.apply_A(dev(xs[b])))) < 1e-6
-        assert rel(gs[b], host(op.apply_AT(dev(ds[b])))) < 1e-6
+        assert rel(ys[b], host(op.apply_A(dev(xs[b])))) < 1e-5
+        assert rel(gs[b], host(op.apply_AT(dev(ds[b])))) < 1e-5
     assert op.adjoint_check(dev(xs[0]), dev(ds[0])) < 1e-5
 
 
