@@ -244,10 +244,28 @@ __device__ __forceinline__ void contract_item(const ContractArgs& a, int lr_log2
   }
 }
 
+// Workgroups -> (item t, object b).  Workgroups are dealt to the eight XCDs
+// round-robin by index, so for a batch the B objects of one item get indices
+// that are equal modulo 8 and close together: they run on the same XCD at
+// about the same time and share the slab through its L2 instead of each
+// streaming it from HBM.
+__device__ __forceinline__ bool item_of_block(int nitem, int B, int& t, int& b) {
+  if (B == 1) {
+    t = blockIdx.x;
+    b = 0;
+    return true;
+  }
+  const int x = blockIdx.x & 7, r = blockIdx.x >> 3;
+  b = r % B;
+  t = (r / B) * 8 + x;
+  return t < nitem;
+}
+
 template <typename HT, int G, int JPT>
-__global__ __launch_bounds__(256) void k_contract(ContractArgs a, int lr_log2) {
+__global__ __launch_bounds__(256) void k_contract(ContractArgs a, int lr_log2, int B) {
   extern __shared__ float4 smem_raw[];
-  const int t = blockIdx.x, b = blockIdx.y;
+  int t, b;
+  if (!item_of_block(a.nitem, B, t, b)) return;  // whole workgroup: padding of the last XCD round
   int kg[G];
 #pragma unroll
   for (int g = 0; g < G; ++g) kg[g] = a.members[t * G + g];
@@ -276,11 +294,13 @@ static pat_status launch_t(const ContractArgs& a, int B, hipStream_t st) {
   size_t lds = red_bytes > in_bytes ? red_bytes : in_bytes;
   lds = lds > out_bytes ? lds : out_bytes;
   if (lds > 160 * 1024) return fail(PAT_EUNSUPPORTED, "contraction input vector does not fit in LDS");
-  dim3 grid(a.nitem, B);
+  const long long nblk = B == 1 ? a.nitem : (long long)(a.nitem + 7) / 8 * 8 * B;
+  if (nblk > 0x7fffffffLL) return fail(PAT_EUNSUPPORTED, "contraction grid too large");
+  dim3 grid((unsigned)nblk);
   if (jpt == 1)
-    k_contract<HT, G, 1><<<grid, 256, lds, st>>>(a, lr_log2);
+    k_contract<HT, G, 1><<<grid, 256, lds, st>>>(a, lr_log2, B);
   else
-    k_contract<HT, G, 2><<<grid, 256, lds, st>>>(a, lr_log2);
+    k_contract<HT, G, 2><<<grid, 256, lds, st>>>(a, lr_log2, B);
   PAT_LAUNCHED("contraction");
   return PAT_OK;
 }
