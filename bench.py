@@ -79,10 +79,47 @@ def time_pairs(op, x, steps, warmup, B=1):
         pair(evs[k])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    el = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(6)] for e in evs]).mean(axis=0)
+    per = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(6)] for e in evs])
+    el = per.mean(axis=0)
     log("  stage ms (spec_z, contract_A, ispec_t, spec_t, contract_AT, ispec_z): "
         + ", ".join(f"{v:.3f}" for v in el))
+    time_pairs.last = {"pair_ms": per.sum(axis=1), "stage_ms": el}
     return t1 - t0, float(el[1]), float(el[4])
+
+
+# transverse frequencies (m, p) where GPU outputs are compared with the oracle:
+# DC, axes, Nyquist corners, multi-member classes and random ones
+SAMPLE_M = np.array([0, 128, 0, 128, 3, 7, 100, 41, 128, 17])
+SAMPLE_P = np.array([0, 0, 128, 128, 250, 3, 9, 200, 77, 17])
+
+
+def spectra_at(y, M=SAMPLE_M, P=SAMPLE_P) -> np.ndarray:
+    """2D DFT over (x, y) of GPU output slices at the sampled frequencies,
+    float64: [B, K, n] (y: [B, n, ny, nx] device tensor)."""
+    import torch
+    out = []
+    for b in range(y.shape[0]):
+        F = torch.fft.rfft2(y[b].double())            # [n, ny, nx/2+1]
+        out.append(F[:, torch.as_tensor(P), torch.as_tensor(M)].T.cpu().numpy())
+    return np.stack(out)
+
+
+def oracle_accuracy(samples: dict) -> dict:
+    """Relative error per object of GPU outputs against the float64 oracle at
+    the sampled frequencies (|| D_gpu - D_oracle || / || D_oracle || over
+    those frequencies and all time samples)."""
+    from oracle import hlib, operators as ops
+    from oracle.geometry import paper_like
+    g = paper_like(**BIG)
+    Hk = hlib.H_hat(g, SAMPLE_M, SAMPLE_P)
+    out = {}
+    for name, (x64s, D) in samples.items():
+        errs = []
+        for b in range(len(x64s)):
+            Do = ops.A_at_freqs(Hk, x64s[b], SAMPLE_M, SAMPLE_P)
+            errs.append(float(np.linalg.norm(D[b] - Do) / np.linalg.norm(Do)))
+        out[name] = {"max": max(errs), "median": float(np.median(errs)), "per_object": errs}
+    return out
 
 
 def cpu_baseline(x64: np.ndarray, budget_s: float = 12.0) -> dict:
@@ -99,12 +136,14 @@ def cpu_baseline(x64: np.ndarray, budget_s: float = 12.0) -> dict:
     rng = np.random.default_rng(7)
     ks = rng.permutation(nk)
     r64 = inputs.gaussian_random((g.nt, g.ny, g.nx), seed=8)
-    done, spent = 0, 0.0
+    done, spent, spent_h = 0, 0.0, 0.0
     chunk = 4
     while spent < budget_s and done < nk:
         kk = ks[done:done + chunk]
         m, p = kk % nh, kk // nh
-        Hk = hlib.H_hat(g, m, p)            # library for the sample, outside the timing
+        t0 = time.perf_counter()
+        Hk = hlib.H_hat(g, m, p)            # library for the sample, timed apart
+        spent_h += time.perf_counter() - t0
         t0 = time.perf_counter()
         ops.A_at_freqs(Hk, x64, m, p)
         ops.AT_at_freqs(Hk, r64, m, p)
@@ -116,7 +155,8 @@ def cpu_baseline(x64: np.ndarray, budget_s: float = 12.0) -> dict:
             "sample": f"oracle forward+adjoint (direct DFT sums + per-frequency contraction, FP64) "
                       f"on {done} of {nk} transverse frequencies of the 256x256x128x512 operator, "
                       f"{spent:.1f} s, scaled by {nk}/{done}; library build and inverse DFT not timed",
-            "cpu": platform.processor() or platform.machine()}
+            "cpu": platform.processor() or platform.machine(),
+            "oracle_library_build_s_estimate": spent_h / done * nk}
 
 
 CONTRACT_SRC = os.path.join(ROOT, "paper_2603_28150_amd", "csrc", "contract.hip")
@@ -143,6 +183,24 @@ def profile_traffic(kernel_bytes: int):
     return d.get("traffic_bytes_per_launch")
 
 
+def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 10) -> float:
+    """Device-to-device copy rate (bytes read + written per second, GB/s): the
+    achievable denominator next to the 8 TB/s specification."""
+    import torch
+    a = torch.ones(nbytes // 4, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -151,7 +209,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-forms", action="store_true", help="skip the BF16/FP16/batch/FISTA forms")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
-    ap.add_argument("--serve-requests", type=int, default=120)
+    ap.add_argument("--serve-requests", type=int, default=400,
+                    help="measured requests per serving run (after 20 warm-up requests)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a device copy of 1 GiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -182,7 +241,9 @@ def main():
     x = torch.from_numpy(x64.astype(np.float32)).cuda()
 
     secs, tA, tAT = time_pairs(op, x, args.steps, args.warmup)
+    tp = time_pairs.last
     ms_step = secs / args.steps * 1e3
+    copy_gbs = copy_bandwidth()
     value = args.steps / secs
     bA = contraction_bytes(info, op.nk, geom.nz, geom.nt, False)
     bAT = contraction_bytes(info, op.nk, geom.nz, geom.nt, True)
@@ -210,11 +271,18 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": profile_traffic(bA),
                      "kernel": "k_contract (A and A^T, mean of both)",
                      "algorithmic_bytes_per_launch": (bA + bAT) / 2,
-                     "ms_per_launch": (tA + tAT) / 2},
+                     "ms_per_launch": (tA + tAT) / 2,
+                     "copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
+        "timing": {"median_ms_per_pair": float(np.median(tp["pair_ms"])),
+                   "min_ms_per_pair": float(np.min(tp["pair_ms"])),
+                   "stage_ms": dict(zip(["spectrum_z", "contract_A", "inverse_spectrum_t",
+                                         "spectrum_t", "contract_AT", "inverse_spectrum_z"],
+                                        [float(v) for v in tp["stage_ms"]]))},
     }
 
+    samples = {}
     if not args.no_forms:
-        out["forms"] = forms(op, x, x64, args)
+        out["forms"] = forms(op, x, x64, args, samples)
     if not args.no_serve:
         del op
         torch.cuda.empty_cache()
@@ -222,18 +290,25 @@ def main():
     if not args.no_cpu:
         log("cpu baseline (oracle sample) ...")
         out["cpu_baseline"] = cpu_baseline(x64)
+        if samples:
+            out["accuracy_vs_oracle"] = oracle_accuracy(samples)
+            log(f"accuracy: { {k: v['max'] for k, v in out['accuracy_vs_oracle'].items()} }")
     print(json.dumps(out), flush=True)
 
 
-def forms(op, x, x64, args) -> dict:
-    """Secondary numbers on the same GPU: FISTA, 16-bit library, batch 16."""
+def forms(op, x, x64, args, samples: dict) -> dict:
+    """Secondary numbers on the same GPU: FISTA (Gram and explicit gradient),
+    16-bit libraries, batches of 16, the autograd fit.  GPU output spectra at
+    the sampled frequencies go to `samples` for the oracle comparison."""
+    import math
     import torch
-    from paper_2603_28150_amd import inputs
-    from paper_2603_28150_amd.op import Operator
+    from paper_2603_28150_amd import autograd, inputs
+    from paper_2603_28150_amd.op import Geometry, Operator
     res = {}
     g = op.geom
     # 100-iteration FISTA with the step from 30 power iterations, 20 dB noise
     clean = op.apply_A(x)
+    samples["f32_b1"] = ([x64], spectra_at(clean[None]))
     sig = float(torch.sqrt(torch.mean(clean * clean)))
     noise = torch.from_numpy(inputs.noise_like(op.d_shape, seed=1501).astype(np.float32)).cuda()
     d = clean + inputs.NOISE_20DB * sig * noise
@@ -249,7 +324,22 @@ def forms(op, x, x64, args) -> dict:
     t_f = time.perf_counter() - t0
     res["fista100_fp32_s"] = t_f
     res["power30_s"] = t_pow
-    log(f"FISTA 100 it: {t_f:.3f} s; power 30 it {t_pow:.3f} s")
+    # the same iterations with the explicit gradient A^T (A z - d): two applies each
+    xs = torch.zeros((1,) + op.x_shape, device="cuda")
+    zs = torch.zeros_like(xs)
+    ws = op.workspace(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tk = 1.0
+    for _ in range(100):
+        tn = (1.0 + math.sqrt(1.0 + 4.0 * tk * tk)) / 2.0
+        op.fista_step(d[None], xs, zs, [(tk - 1.0) / tn], [1.0 / L], [0.0], [True], ws=ws)
+        tk = tn
+    torch.cuda.synchronize()
+    res["fista100_explicit_fp32_s"] = time.perf_counter() - t0
+    log(f"FISTA 100 it: {t_f:.3f} s (Gram), {res['fista100_explicit_fp32_s']:.3f} s (explicit); "
+        f"power 30 it {t_pow:.3f} s")
+    del xs, zs, d, noise, clean
     # 16-bit libraries, batch 1
     for kind in ("bf16", "f16"):
         o = Operator(g, kind)
@@ -258,31 +348,52 @@ def forms(op, x, x64, args) -> dict:
         b = contraction_bytes(inf, o.nk, g.nz, g.nt, False) + contraction_bytes(inf, o.nk, g.nz, g.nt, True)
         res[f"{kind}_pairs_per_s"] = max(5, args.steps // 2) / secs
         res[f"{kind}_contract_GBs"] = b / ((tA + tAT) * 1e-3) / 1e9
+        samples[f"{kind}_b1"] = ([x64], spectra_at(o.apply_A(x)[None]))
         log(f"{kind}: {res[f'{kind}_pairs_per_s']:.1f} pairs/s, contraction {res[f'{kind}_contract_GBs']:.0f} GB/s")
         del o
         torch.cuda.empty_cache()
     # batch of 16 objects, FP32 and BF16 libraries
-    xb = torch.from_numpy(np.stack([inputs.vascular_phantom(op.x_shape, seed=2001 + b)
-                                    for b in range(16)]).astype(np.float32)).cuda()
+    xb64 = [inputs.vascular_phantom(op.x_shape, seed=2001 + b) for b in range(16)]
+    xb = torch.from_numpy(np.stack(xb64).astype(np.float32)).cuda()
     for kind in ("f32", "bf16"):
         o = op if kind == "f32" else Operator(g, kind)
         secs, tA, tAT = time_pairs(o, xb, 3, 1, B=16)
         res[f"batch16_{kind}_object_pairs_per_s"] = 16 * 3 / secs
+        samples[f"{kind}_b16"] = (xb64, spectra_at(o.apply_A(xb)))
         log(f"batch16 {kind}: {res[f'batch16_{kind}_object_pairs_per_s']:.1f} object-pairs/s")
         if o is not op:
             del o
         torch.cuda.empty_cache()
+    del xb
+    # differentiable form: 200 Adam steps on 1/2 ||A x - y||^2 + 1e-3 TV(x), 128^2 x 64 x 256
+    ga = Geometry.paper_like(128, 128, 64, 256)
+    oa = Operator(ga, "f32")
+    xa = torch.from_numpy(inputs.vascular_phantom(oa.x_shape, seed=3001).astype(np.float32)).cuda()
+    ya = oa.apply_A(xa)
+    autograd.fit_adam_tv(oa, ya, steps=2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, losses = autograd.fit_adam_tv(oa, ya, steps=200)
+    torch.cuda.synchronize()
+    res["autograd_adam200_128x128x64x256_s"] = time.perf_counter() - t0
+    res["autograd_loss_first_last"] = [losses[0], losses[-1]]
+    log(f"autograd 200 Adam steps: {res['autograd_adam200_128x128x64x256_s']:.2f} s, "
+        f"loss {losses[0]:.4g} -> {losses[-1]:.4g}")
+    del oa, xa, ya
+    torch.cuda.empty_cache()
     return res
 
 
 def serving(args) -> dict:
     """Poisson streams of 50-iteration FISTA reconstructions over three
     geometries x {FP32, BF16} libraries (seeded vascular phantoms, 20 dB
-    noise).  The same stream is served by (i) the plain FIFO: one request at a
-    time, no batching, explicit A then A^T each iteration; (ii) continuous
-    batching with the per-frequency normal operator.  A saturating stream
-    (400 req/s) compares batching with a FIFO of the same step.  Libraries are
-    pre-built (cache warm); latency = completion - arrival."""
+    noise): 20 warm-up requests, then the measured ones.  The same stream is
+    served by (i) the plain FIFO: one request at a time, no batching, explicit
+    A then A^T each iteration; (ii) continuous batching with the
+    per-frequency normal operator; (iii) the same with a 24 GiB HBM budget so
+    that admission binds.  A saturating stream (400 req/s) compares batching
+    with a FIFO of the same step.  Libraries are pre-built (cache warm; the
+    cold build time is reported apart); latency = completion - arrival."""
     import torch
     from paper_2603_28150_amd import inputs
     from paper_2603_28150_amd.op import Geometry
@@ -291,7 +402,8 @@ def serving(args) -> dict:
              Geometry.paper_like(256, 256, 128, 512)]
     classes = [(g, k) for g in geoms for k in ("f32", "bf16")]
     rng = np.random.default_rng(4001)
-    n = args.serve_requests
+    n_warm = 20
+    n = n_warm + args.serve_requests
     which = rng.integers(0, len(classes), n)
     be_n, be_x = HipBackend(normal=True), HipBackend(normal=False)
     warm = Server(be_n, hbm_budget=200 << 30, max_batch=16)
@@ -319,8 +431,8 @@ def serving(args) -> dict:
         reqs_data.append((g, k, c + inputs.NOISE_20DB * sig * noise))
     torch.cuda.synchronize()
 
-    def fresh(backend, max_batch):
-        srv = Server(backend, hbm_budget=200 << 30, max_batch=max_batch)
+    def fresh(backend, max_batch, budget=200 << 30):
+        srv = Server(backend, hbm_budget=budget, max_batch=max_batch)
         for key, cls in warm.classes.items():   # warm library cache, empty slots
             cls.cap, cls.pool, cls.ws, cls.active, cls.inflight, cls.bytes_pool = 0, {}, None, [], None, 0
             srv.classes[key] = cls
@@ -346,21 +458,32 @@ def serving(args) -> dict:
                 time.sleep(max(0.0, min(1e-3, reqs[i].t_arrival - time.perf_counter())))
         torch.cuda.synchronize()
         st = srv.stats()
-        out = {k: (float(v) if v is not None else None) for k, v in st.items() if k in ("p50_s", "p99_s", "recon_per_s")}
-        out["completed"] = st["completed"]
+        meas = [r for r in reqs[n_warm:] if r.latency is not None]
+        lat = sorted(r.latency for r in meas)
+        span = max(r.t_done for r in meas) - min(r.t_arrival for r in reqs[n_warm:]) if meas else 0.0
+        out = {"p50_s": float(np.percentile(lat, 50)) if lat else None,
+               "p99_s": float(np.percentile(lat, 99)) if lat else None,
+               "recon_per_s": len(meas) / span if span > 0 else None,
+               "completed": len(meas),
+               "rejected": sum(r.status == "rejected" for r in reqs[n_warm:]),
+               "hbm_peak_GiB": st["hbm_peak_bytes"] / 2**30}
         if not fifo:
             out["batch_hist"] = {str(b): c for b, c in sorted(st["batch_hist"].items())}
         for r in reqs:
             r.x = None
         return out
 
-    out = {"library_cache_cold_build_s": t_cold, "requests": n, "iterations": 50,
-           "classes": [f"{g.nx}x{g.ny}x{g.nz}x{g.nt}/{k}" for g, k in classes]}
+    out = {"library_cache_cold_build_s": t_cold, "requests_measured": n - n_warm,
+           "requests_warmup": n_warm, "iterations": 50,
+           "classes": [f"{g.nx}x{g.ny}x{g.nz}x{g.nt}/{k}" for g, k in classes],
+           "library_cache_GiB": sum(c.bytes_lib for c in warm.classes.values()) / 2**30}
     out["rate_20"] = {"fifo_plain": run(fresh(be_x, 1), 20.0, True),
-                      "batching": run(fresh(be_n, 16), 20.0, False)}
+                      "batching": run(fresh(be_n, 16), 20.0, False),
+                      "batching_budget_24GiB": run(fresh(be_n, 16, 24 << 30), 20.0, False)}
     log(f"serving at 20 req/s: {out['rate_20']}")
     out["rate_400"] = {"fifo_normal": run(fresh(be_n, 1), 400.0, True),
-                       "batching": run(fresh(be_n, 16), 400.0, False)}
+                       "batching": run(fresh(be_n, 16), 400.0, False),
+                       "batching_budget_24GiB": run(fresh(be_n, 16, 24 << 30), 400.0, False)}
     log(f"serving at 400 req/s: {out['rate_400']}")
     return out
 
