@@ -7,7 +7,9 @@ The object lives on G_rho = G_xy x G_z and the data on G_d = G_xy x T
 
 * the sensor plane is depth index l = 0 (z_l = l*dz), and the time grid is
   t_n = n*dt for n = 0..Nt-1 (it includes t = 0);
-* the transverse boundary is periodic at Nx x Ny (circular convolution);
+* the transverse boundary is periodic at Nx x Ny (circular convolution), or,
+  for the zero-padded linear convolution, periodic at 2Nx x 2Ny with the
+  object padded and the data cropped (``doubled``);
 * the simulated medium is periodic in z with period nz_sim >= Nz; by default
   nz_sim is the smallest power of two >= Nz + ceil(c*dt*(Nt-1)/dz) + 1, so
   that the wrapped image of the object cannot reach the sensor within the
@@ -63,6 +65,13 @@ def ky_full(g: Geometry) -> np.ndarray:
 def kz_full(g: Geometry) -> np.ndarray:
     """k_z for every index q = 0..nz_sim-1 of the periodic z-grid (rad/m)."""
     return 2.0 * np.pi * np.fft.fftfreq(g.nq, d=g.dz)
+
+
+def doubled(g: Geometry) -> Geometry:
+    """The 2Nx x 2Ny periodic grid on which the zero-padded linear
+    convolution of the Nx x Ny window is taken (same physics and z-period)."""
+    from dataclasses import replace
+    return replace(g, nx=2 * g.nx, ny=2 * g.ny, nz_sim=g.nq)
 
 
 def time_axis(g: Geometry) -> np.ndarray:

@@ -20,6 +20,10 @@ Three independent realisations of the same discrete operator:
   the half spectrum, the only form fast enough for long iterations on large
   grids.
 
+For the zero-padded linear convolution of Sec. 2.3, ``A_direct_linear``
+writes the sum over signed source-sensor offsets out, and ``A_linear`` /
+``AT_linear`` pad, apply the periodic operator of the doubled grid and crop.
+
 The inner products are the unweighted Euclidean ones of eq. 10, so A^T is the
 plain matrix transpose.
 """
@@ -99,6 +103,48 @@ def AT_fft(Hh: np.ndarray, d: np.ndarray) -> np.ndarray:
     R = np.fft.rfft2(d, axes=(1, 2))                       # [nt, ny, nh]
     G = np.einsum("pmln,npm->lpm", np.conj(Hh), R, optimize=True)
     return np.fft.irfft2(G, s=(ny, nx), axes=(1, 2))
+
+
+# ------------------------------------ zero-padded linear convolution (Sec. 2.3)
+# The object and the data live on the Ny x Nx window; the kernels are those of
+# the doubled periodic grid (2Ny x 2Nx), indexed by the signed offset between
+# sensor and source, which stays inside (-Ny, Ny) x (-Nx, Nx).
+def pad2(f: np.ndarray, py: int, px: int) -> np.ndarray:
+    """Zero-pad the last two axes of f to (py, px) (data at the low indices)."""
+    out = np.zeros(f.shape[:-2] + (py, px))
+    out[..., :f.shape[-2], :f.shape[-1]] = f
+    return out
+
+
+def A_direct_linear(h2: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """d[n, j, i] = sum_l sum_{j', i' in window} h2[l, j-j', i-i', n] x[l, j', i']
+    with negative offsets read from the doubled grid's kernel at +2N.
+    h2: [nz, 2Ny, 2Nx, nt]; tiny grids only."""
+    nz, py, px, nt = h2.shape
+    _, ny, nx = x.shape
+    d = np.zeros((nt, ny, nx))
+    for b in range(-(ny - 1), ny):
+        for a in range(-(nx - 1), nx):
+            hb = h2[:, b % py, a % px, :]                     # [nz, nt]
+            js, je = max(0, -b), min(ny, ny - b)              # source rows j' with j'+b in window
+            is_, ie = max(0, -a), min(nx, nx - a)
+            d[:, js + b:je + b, is_ + a:ie + a] += np.tensordot(hb, x[:, js:je, is_:ie], axes=([0], [0]))
+    return d
+
+
+def A_linear(Hh2: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """A with the zero-padded linear convolution: pad, A on the doubled grid
+    (Hh2 = H^ of the doubled grid, half spectrum), crop."""
+    py, nh2 = Hh2.shape[:2]
+    _, ny, nx = x.shape
+    return A_fft(Hh2, pad2(x, py, 2 * (nh2 - 1)))[:, :ny, :nx]
+
+
+def AT_linear(Hh2: np.ndarray, d: np.ndarray) -> np.ndarray:
+    """A^T of A_linear: pad the data, A^T on the doubled grid, crop."""
+    py, nh2 = Hh2.shape[:2]
+    _, ny, nx = d.shape
+    return AT_fft(Hh2, pad2(d, py, 2 * (nh2 - 1)))[:, :ny, :nx]
 
 
 # ----------------------------------------- single frequencies of large grids
