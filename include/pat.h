@@ -56,7 +56,7 @@ typedef struct pat_op pat_op;   /* one geometry + its kernel library */
 typedef enum {
   PAT_OK = 0,
   PAT_EINVAL = -1,       /* bad argument: null/misaligned pointer, buffer too small, B < 1, ... */
-  PAT_EUNSUPPORTED = -2, /* valid but unsupported: nx or ny not a power of two in [16, 256], ... */
+  PAT_EUNSUPPORTED = -2, /* valid but unsupported: nx or ny outside the supported sizes, ... */
   PAT_ENOMEM = -3,       /* host allocation failed */
   PAT_EHIP = -4,         /* a HIP runtime call or kernel launch failed */
   PAT_ENONFINITE = -5    /* a non-finite value was detected where a check was requested */
@@ -70,14 +70,26 @@ typedef enum {
  * A^T post-scales it, so both use the same dequantised H^ and stay adjoint. */
 typedef enum { PAT_H_F32 = 0, PAT_H_BF16 = 1, PAT_H_F16 = 2 } pat_hdtype;
 
+/* Transverse boundary of the convolution.  PERIODIC: circular at nx x ny.
+ * LINEAR: the zero-padded linear convolution of Sec. 2.3 (the object and the
+ * data live on nx x ny; the transforms and the library are taken on the
+ * 2nx x 2ny periodic grid, the object is zero-padded and the data cropped,
+ * so that A^T stays the exact adjoint).  The library of the doubled grid is
+ * the free-space response on the nx x ny window as long as the wavefront does
+ * not travel round the doubled period within the record,
+ * c*dt*(nt-1) < (nx+1)*dx and (ny+1)*dy. */
+typedef enum { PAT_BOUNDARY_PERIODIC = 0, PAT_BOUNDARY_LINEAR = 1 } pat_boundary;
+
 typedef struct {
-  int32_t nx, ny;  /* transverse grid (x fastest); powers of two in [16, 256] */
+  int32_t nx, ny;  /* transverse grid (x fastest); powers of two, in [16, 512]
+                      (periodic) or [8, 256] (linear) */
   int32_t nz, nt;  /* depths and time samples, >= 1 */
   double dx, dy, dz, dt, c; /* spacings [m], time step [s], sound speed [m/s]; all > 0 */
   int32_t nz_sim;  /* z-period of the simulated medium in grid points: 0 selects
                       the smallest power of two >= nz + ceil(c*dt*(nt-1)/dz) + 1,
                       otherwise it must be >= nz */
   int32_t h_dtype; /* pat_hdtype */
+  int32_t boundary; /* pat_boundary */
 } pat_geometry;
 
 /* ---------------------------------------------------------------- context */
@@ -198,15 +210,17 @@ pat_status pat_power_norm(pat_op* op, const float* v0, int32_t niter, double* L_
  *     t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2   (beta_k = 0 if momentum == 0),
  * with prox(v) = max(v - tau*lambda, 0) if nonneg, else soft-thresholding.
  * d: device [nt][ny][nx]; x: device [nz][ny][nx], receives x_niter.
- * The gradient A^T (A z - d) = A^T A z - A^T d (eq. 15) is formed per
- * transverse frequency with the Gram blocks H^_k^T H^_k of the library (built
- * with it, float64 sums of the stored values): one spectrum of z, one
- * nz x nz contraction and one inverse spectrum per iteration, A^T d once.
+ * Periodic boundary: the gradient A^T (A z - d) = A^T A z - A^T d (eq. 15)
+ * is formed per transverse frequency with the Gram blocks H^_k^T H^_k of the
+ * library (built with it, float64 sums of the stored values): one spectrum
+ * of z, one nz x nz contraction and one inverse spectrum per iteration,
+ * A^T d once.  Linear boundary: the cropping between A and A^T couples the
+ * frequencies, so the gradient is A^T r with r = A z - d, two applies.
  * trace: NULL or a device float array [niter] that receives
  * 1/2 ||A z_k - d||^2, the data term at the point where the gradient of
- * step k is taken, as 1/2 (<z, g> - <z, A^T d> + ||d||^2) with float64 sums
- * (absolute error of order 1e-7 * ||d||^2).  The momentum weights are
- * computed on the host in float64.  Asynchronous. */
+ * step k is taken (periodic: as 1/2 (<z, g> - <z, A^T d> + ||d||^2) with
+ * float64 sums, absolute error of order 1e-7 * ||d||^2; linear: 1/2 <r, r>).
+ * The momentum weights are computed on the host in float64.  Asynchronous. */
 pat_status pat_recon_fista(pat_op* op, const float* d, float* x, int32_t niter,
                            float tau, float lambda, int32_t nonneg, int32_t momentum,
                            float* trace, void* ws, size_t ws_bytes, void* stream);
@@ -229,7 +243,9 @@ pat_status pat_fista_step(pat_op* op, int32_t B, const float* d, float* x, float
  * A^T d of each object (one pat_apply_AT when the problem is set up), so the
  * data themselves are not needed; x, z, beta, tau, lambda, nonneg and
  * nonfinite as in pat_fista_step.  Per iteration: one spectrum of z, one
- * nz x nz contraction, one inverse spectrum and the update. */
+ * nz x nz contraction, one inverse spectrum and the update.  Periodic
+ * boundary only (EUNSUPPORTED for the linear one, whose library has no
+ * Gram blocks). */
 pat_status pat_fista_step_normal(pat_op* op, int32_t B, const float* atd, float* x, float* z,
                                  const double* beta, const float* tau, const float* lambda,
                                  const int32_t* nonneg, int32_t* nonfinite,

@@ -25,11 +25,12 @@ class Geometry(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("nt", C.c_int32),
                 ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
                 ("dt", C.c_double), ("c", C.c_double),
-                ("nz_sim", C.c_int32), ("h_dtype", C.c_int32)]
+                ("nz_sim", C.c_int32), ("h_dtype", C.c_int32), ("boundary", C.c_int32)]
 
 
 H_F32, H_BF16, H_F16 = 0, 1, 2
 HDTYPES = {"f32": H_F32, "bf16": H_BF16, "f16": H_F16}
+BOUNDARIES = {"periodic": 0, "linear": 1}
 
 STATUS = {0: "PAT_OK", -1: "PAT_EINVAL", -2: "PAT_EUNSUPPORTED", -3: "PAT_ENOMEM",
           -4: "PAT_EHIP", -5: "PAT_ENONFINITE"}

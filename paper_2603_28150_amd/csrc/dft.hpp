@@ -20,6 +20,26 @@ __device__ __forceinline__ float2 rot90(float2 a) {
   return DIR < 0 ? make_float2(a.y, -a.x) : make_float2(-a.y, a.x);
 }
 
+// exp(DIR * 2 pi i e / 32) for 0 <= e < 16, from exact constants.
+template <int DIR>
+__device__ __forceinline__ float2 w32(int e) {
+  const float cs[16] = {1.f,
+                        0.98078528040323044913f, 0.92387953251128675613f, 0.83146961230254523708f,
+                        0.70710678118654752440f, 0.55557023301960222474f, 0.38268343236508977173f,
+                        0.19509032201612826785f, 0.f,
+                        -0.19509032201612826785f, -0.38268343236508977173f, -0.55557023301960222474f,
+                        -0.70710678118654752440f, -0.83146961230254523708f, -0.92387953251128675613f,
+                        -0.98078528040323044913f};
+  const float sn[16] = {0.f,
+                        0.19509032201612826785f, 0.38268343236508977173f, 0.55557023301960222474f,
+                        0.70710678118654752440f, 0.83146961230254523708f, 0.92387953251128675613f,
+                        0.98078528040323044913f, 1.f,
+                        0.98078528040323044913f, 0.92387953251128675613f, 0.83146961230254523708f,
+                        0.70710678118654752440f, 0.55557023301960222474f, 0.38268343236508977173f,
+                        0.19509032201612826785f};
+  return make_float2(cs[e & 15], DIR < 0 ? -sn[e & 15] : sn[e & 15]);
+}
+
 // exp(DIR * 2 pi i e / 16) for 0 <= e < 16, from exact constants.
 template <int DIR>
 __device__ __forceinline__ float2 w16(int e) {
@@ -87,6 +107,22 @@ __device__ __forceinline__ void dft(float2* v) {
 #pragma unroll
       for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[k2];
     }
+  } else if constexpr (R == 32) {
+    // radix 2 x 16: even/odd halves, then combine with exp(DIR 2 pi i k / 32)
+    float2 e[16], o[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      e[k] = v[2 * k];
+      o[k] = v[2 * k + 1];
+    }
+    dft<16, DIR>(e);
+    dft<16, DIR>(o);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const float2 t = k == 0 ? o[k] : cmul(o[k], w32<DIR>(k));
+      v[k] = cadd(e[k], t);
+      v[k + 16] = csub(e[k], t);
+    }
   }
 }
 
@@ -97,5 +133,6 @@ template <> struct Split<32> { static constexpr int N1 = 8, N2 = 4; };
 template <> struct Split<64> { static constexpr int N1 = 8, N2 = 8; };
 template <> struct Split<128> { static constexpr int N1 = 16, N2 = 8; };
 template <> struct Split<256> { static constexpr int N1 = 16, N2 = 16; };
+template <> struct Split<512> { static constexpr int N1 = 32, N2 = 16; };
 
 }  // namespace pat

@@ -10,8 +10,14 @@
 //            complex transform;
 //   columns: complex transforms along y on the frequency-major layout, slices
 //            fastest, so that loads and stores are contiguous across threads.
-// Twiddles exp(-2 pi i e / 256) are tabulated on the host in float64 and
+// Twiddles exp(-2 pi i e / 512) are tabulated on the host in float64 and
 // rounded once to float32.
+//
+// Transform sizes and data extents are separate: slices hold nx_d x ny_d
+// values and are transformed on an fx x fy grid (nx_d <= fx, ny_d <= fy).
+// Missing rows and columns are zeros that are never read (forward) and
+// rows and columns beyond the data are never written (inverse), so the
+// zero-padded linear convolution costs no extra HBM traffic.
 #include <cmath>
 
 #include "dft.hpp"
@@ -19,38 +25,43 @@
 
 namespace pat {
 
-__device__ float2 g_tw256[256];
+constexpr int kTwN = 512;  // largest transform size
+__device__ float2 g_tw[kTwN];
 
 pat_status fft_init_device() {
-  float2 host[256];
+  float2 host[kTwN];
   const double two_pi = 6.283185307179586476925286766559;
-  for (int e = 0; e < 256; ++e) {
-    double a = two_pi * e / 256.0;
+  for (int e = 0; e < kTwN; ++e) {
+    double a = two_pi * e / (double)kTwN;
     host[e] = make_float2((float)std::cos(a), (float)-std::sin(a));
   }
-  PAT_HIP(hipMemcpyToSymbol(HIP_SYMBOL(g_tw256), host, sizeof(host), 0, hipMemcpyHostToDevice));
+  PAT_HIP(hipMemcpyToSymbol(HIP_SYMBOL(g_tw), host, sizeof(host), 0, hipMemcpyHostToDevice));
   return PAT_OK;
 }
 
 template <int N, int DIR>
 __device__ __forceinline__ void load_twiddles(float2* tw, int tid, int nthreads) {
   for (int e = tid; e < N; e += nthreads) {
-    float2 w = g_tw256[e * (256 / N)];
+    float2 w = g_tw[e * (kTwN / N)];
     tw[e] = DIR < 0 ? w : cconj(w);
   }
 }
 
 // ------------------------------------------------------------- columns (y)
-// out[orow(p*nh + m)*rs + s] = sum_j exp(DIR 2 pi i p j / N) in[irow(j*nh + m)*rs + s]
-// irow / orow: row maps (null = identity); the spectrum side uses the
-// class-major map so that the contraction reads and writes contiguous rows.
+// out[orow(p*nh + m)*rs + s] = sum_{j < nin} exp(DIR 2 pi i p j / N) in[irow(j*nh + m)*rs + s]
+// for p < nout (rows j >= nin are zeros); irow / orow: row maps (null =
+// identity); the spectrum side uses the class-major map so that the
+// contraction reads and writes contiguous rows.
+template <int N> struct ColSB { static constexpr int value = N <= 256 ? 16 : 8; };  // slices per block
+
 template <int N, int DIR>
 __global__ __launch_bounds__(256) void k_fft_cols(const float2* __restrict__ in,
                                                   float2* __restrict__ out, int nh, int S,
                                                   int rs, const int32_t* __restrict__ imap,
-                                                  const int32_t* __restrict__ omap, int sfast) {
+                                                  const int32_t* __restrict__ omap, int sfast,
+                                                  int nin, int nout) {
   constexpr int N1 = Split<N>::N1, N2 = Split<N>::N2;
-  constexpr int SB = 16;       // slices per block
+  constexpr int SB = ColSB<N>::value;
   constexpr int PAD = N + 1;   // LDS stride per slice (complex)
   constexpr int NT = SB * N1;  // threads
   __shared__ float2 tw[N];
@@ -74,7 +85,7 @@ __global__ __launch_bounds__(256) void k_fft_cols(const float2* __restrict__ in,
 #pragma unroll
     for (int n1 = 0; n1 < N1; ++n1) {
       const int y = t + N2 * n1;
-      v[n1] = live ? in[(size_t)rin[y] * rs + sg] : make_float2(0.f, 0.f);
+      v[n1] = (live && y < nin) ? in[(size_t)rin[y] * rs + sg] : make_float2(0.f, 0.f);
     }
     dft<N1, DIR>(v);
 #pragma unroll
@@ -89,20 +100,21 @@ __global__ __launch_bounds__(256) void k_fft_cols(const float2* __restrict__ in,
 #pragma unroll
     for (int k2 = 0; k2 < N2; ++k2) {
       const int p = t + N1 * k2;
-      out[(size_t)rout[p] * rs + sg] = v[k2];
+      if (p < nout) out[(size_t)rout[p] * rs + sg] = v[k2];
     }
   }
 }
 
 // ---------------------------------------------------------- rows, r2c (x)
-// T[(j*nh + m)*rs + s] = sum_i exp(-2 pi i m i / N) f[s][j][i],  m = 0..N/2
+// T[(j*nh + m)*rs + s] = sum_{i < nxd} exp(-2 pi i m i / N) f[s][j][i],  m = 0..N/2,
+// for the ny_d rows j of slices f[s][ny_d][nxd] (zero-padded to N along x)
 // The 2Q rows of a block are read with 16-byte loads into LDS, packed in
 // pairs as z = f[2q] + i f[2q+1]; after the transform the two real spectra are
 // separated and written slice-fastest (contiguous across threads).
 template <int N, int Q>  // Q packed complex sequences = 2Q real slices per block
 __global__ __launch_bounds__(256) void k_fft_rows_r2c(const float* __restrict__ f,
-                                                      float2* __restrict__ T, int ny, int S,
-                                                      int rs) {
+                                                      float2* __restrict__ T, int ny, int nxd,
+                                                      int S, int rs) {
   constexpr int N1 = Split<N>::N1, N2 = Split<N>::N2;
   constexpr int PAD = N + 1;
   constexpr int NT = Q * N1;
@@ -123,7 +135,8 @@ __global__ __launch_bounds__(256) void k_fft_rows_r2c(const float* __restrict__ 
     const int row = u / (N / 4), c4 = u % (N / 4);
     const int s = s0 + row;
     ld[it] = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (u < 2 * Q * (N / 4) && s < S) ld[it] = reinterpret_cast<const float4*>(f + ((size_t)s * ny + j) * N)[c4];
+    if (u < 2 * Q * (N / 4) && s < S && 4 * c4 < nxd)
+      ld[it] = reinterpret_cast<const float4*>(f + ((size_t)s * ny + j) * nxd)[c4];
   }
 #pragma unroll
   for (int it = 0; it < LIT; ++it) {
@@ -178,11 +191,12 @@ __global__ __launch_bounds__(256) void k_fft_rows_r2c(const float* __restrict__ 
 
 // ---------------------------------------------------------- rows, c2r (x)
 // f[s][j][i] = scale * sum_{m=0}^{N-1} exp(+2 pi i m i / N) F[m] - sub[s][j][i],
-// F Hermitian-extended from m = 0..N/2 (imaginary parts of m = 0, N/2 dropped)
+// F Hermitian-extended from m = 0..N/2 (imaginary parts of m = 0, N/2 dropped),
+// for i < nxd (slices f[s][ny][nxd]; the rest of the period is not stored)
 template <int N, int Q>
 __global__ __launch_bounds__(256) void k_fft_rows_c2r(const float2* __restrict__ T,
-                                                      float* __restrict__ f, int ny, int S,
-                                                      int rs, float scale,
+                                                      float* __restrict__ f, int ny, int nxd,
+                                                      int S, int rs, float scale,
                                                       const float* __restrict__ sub) {
   constexpr int N1 = Split<N>::N1, N2 = Split<N>::N2;
   constexpr int PAD = N + 1;
@@ -264,7 +278,8 @@ __global__ __launch_bounds__(256) void k_fft_rows_c2r(const float2* __restrict__
       const int row = u / (N / 4), c4 = u % (N / 4);
       const int s = s0 + row;
       sb4[it] = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (u < 2 * Q * (N / 4) && s < S) sb4[it] = reinterpret_cast<const float4*>(sub + ((size_t)s * ny + j) * N)[c4];
+      if (u < 2 * Q * (N / 4) && s < S && 4 * c4 < nxd)
+        sb4[it] = reinterpret_cast<const float4*>(sub + ((size_t)s * ny + j) * nxd)[c4];
     }
   }
 #pragma unroll
@@ -272,7 +287,7 @@ __global__ __launch_bounds__(256) void k_fft_rows_c2r(const float2* __restrict__
     const int u = tid + it * NT;
     const int row = u / (N / 4), c4 = u % (N / 4);
     const int s = s0 + row;
-    if (u >= 2 * Q * (N / 4) || s >= S) continue;
+    if (u >= 2 * Q * (N / 4) || s >= S || 4 * c4 >= nxd) continue;
     const float4 r = *reinterpret_cast<const float4*>(rows + row * (N + 4) + 4 * c4);
     float4 v = make_float4(r.x * scale, r.y * scale, r.z * scale, r.w * scale);
     if (sub) {
@@ -281,45 +296,50 @@ __global__ __launch_bounds__(256) void k_fft_rows_c2r(const float2* __restrict__
       v.z -= sb4[it].z;
       v.w -= sb4[it].w;
     }
-    reinterpret_cast<float4*>(f + ((size_t)s * ny + j) * N)[c4] = v;
+    reinterpret_cast<float4*>(f + ((size_t)s * ny + j) * nxd)[c4] = v;
   }
 }
 
 // ------------------------------------------------------------- launchers
 template <int N, int DIR>
 static void launch_cols(const float2* in, float2* out, int nh, int S, int rs, const int32_t* imap,
-                        const int32_t* omap, hipStream_t st) {
+                        const int32_t* omap, int nin, int nout, hipStream_t st) {
+  constexpr int SB = ColSB<N>::value;
   const int sfast = S >= 2048;
-  dim3 grid = sfast ? dim3((S + 15) / 16, nh) : dim3(nh, (S + 15) / 16);
-  k_fft_cols<N, DIR><<<grid, 16 * Split<N>::N1, 0, st>>>(in, out, nh, S, rs, imap, omap, sfast);
+  const int nsb = (S + SB - 1) / SB;
+  dim3 grid = sfast ? dim3(nsb, nh) : dim3(nh, nsb);
+  k_fft_cols<N, DIR><<<grid, SB * Split<N>::N1, 0, st>>>(in, out, nh, S, rs, imap, omap, sfast,
+                                                         nin, nout);
 }
 
 template <int DIR>
-static pat_status cols(const float2* in, float2* out, int ny, int nh, int S, int rs,
-                       const int32_t* imap, const int32_t* omap, hipStream_t st) {
-  switch (ny) {
-    case 16: launch_cols<16, DIR>(in, out, nh, S, rs, imap, omap, st); break;
-    case 32: launch_cols<32, DIR>(in, out, nh, S, rs, imap, omap, st); break;
-    case 64: launch_cols<64, DIR>(in, out, nh, S, rs, imap, omap, st); break;
-    case 128: launch_cols<128, DIR>(in, out, nh, S, rs, imap, omap, st); break;
-    case 256: launch_cols<256, DIR>(in, out, nh, S, rs, imap, omap, st); break;
-    default: return fail(PAT_EUNSUPPORTED, "ny must be a power of two in [16, 256]");
+static pat_status cols(const float2* in, float2* out, int fy, int nh, int S, int rs,
+                       const int32_t* imap, const int32_t* omap, int nin, int nout,
+                       hipStream_t st) {
+  switch (fy) {
+    case 16: launch_cols<16, DIR>(in, out, nh, S, rs, imap, omap, nin, nout, st); break;
+    case 32: launch_cols<32, DIR>(in, out, nh, S, rs, imap, omap, nin, nout, st); break;
+    case 64: launch_cols<64, DIR>(in, out, nh, S, rs, imap, omap, nin, nout, st); break;
+    case 128: launch_cols<128, DIR>(in, out, nh, S, rs, imap, omap, nin, nout, st); break;
+    case 256: launch_cols<256, DIR>(in, out, nh, S, rs, imap, omap, nin, nout, st); break;
+    case 512: launch_cols<512, DIR>(in, out, nh, S, rs, imap, omap, nin, nout, st); break;
+    default: return fail(PAT_EUNSUPPORTED, "transform size along y must be a power of two in [16, 512]");
   }
   PAT_LAUNCHED("fft columns");
   return PAT_OK;
 }
 
 template <int N, int Q>
-static void rows_r2c(const float* f, float2* T, int ny, int S, int rs, hipStream_t st) {
-  dim3 grid(ny, (S + 2 * Q - 1) / (2 * Q));
-  k_fft_rows_r2c<N, Q><<<grid, Q * Split<N>::N1, 0, st>>>(f, T, ny, S, rs);
+static void rows_r2c(const float* f, float2* T, int nyd, int nxd, int S, int rs, hipStream_t st) {
+  dim3 grid(nyd, (S + 2 * Q - 1) / (2 * Q));
+  k_fft_rows_r2c<N, Q><<<grid, Q * Split<N>::N1, 0, st>>>(f, T, nyd, nxd, S, rs);
 }
 
 template <int N, int Q>
-static void rows_c2r(const float2* T, float* f, int ny, int S, int rs, float scale, const float* sub,
-                     hipStream_t st) {
-  dim3 grid(ny, (S + 2 * Q - 1) / (2 * Q));
-  k_fft_rows_c2r<N, Q><<<grid, Q * Split<N>::N1, 0, st>>>(T, f, ny, S, rs, scale, sub);
+static void rows_c2r(const float2* T, float* f, int nyd, int nxd, int S, int rs, float scale,
+                     const float* sub, hipStream_t st) {
+  dim3 grid(nyd, (S + 2 * Q - 1) / (2 * Q));
+  k_fft_rows_c2r<N, Q><<<grid, Q * Split<N>::N1, 0, st>>>(T, f, nyd, nxd, S, rs, scale, sub);
 }
 
 // 8 packed sequences (16 real slices) per row block: small enough for several
@@ -327,36 +347,44 @@ static void rows_c2r(const float2* T, float* f, int ny, int S, int rs, float sca
 constexpr int kRowQ = 8;
 #define PAT_ROWS(fn, N, ...) (fn<N, kRowQ>(__VA_ARGS__))
 
-pat_status fft2_r2c(const float* f, float2* T, float2* X, int nx, int ny, int S,
-                    const int32_t* rowmap, hipStream_t st) {
-  if (S <= 0) return PAT_OK;
-  const int nh = nx / 2 + 1;
-  const int rs = spec_stride(S);
-  switch (nx) {
-    case 16: PAT_ROWS(rows_r2c, 16, f, T, ny, S, rs, st); break;
-    case 32: PAT_ROWS(rows_r2c, 32, f, T, ny, S, rs, st); break;
-    case 64: PAT_ROWS(rows_r2c, 64, f, T, ny, S, rs, st); break;
-    case 128: PAT_ROWS(rows_r2c, 128, f, T, ny, S, rs, st); break;
-    case 256: PAT_ROWS(rows_r2c, 256, f, T, ny, S, rs, st); break;
-    default: return fail(PAT_EUNSUPPORTED, "nx must be a power of two in [16, 256]");
-  }
-  PAT_LAUNCHED("fft rows r2c");
-  return cols<-1>(T, X, ny, nh, S, rs, nullptr, rowmap, st);
+static bool extents_ok(int fx, int fy, int nxd, int nyd) {
+  return nxd >= 4 && nyd >= 1 && nxd <= fx && nyd <= fy && (nxd & 3) == 0;
 }
 
-pat_status fft2_c2r(const float2* X, float2* T, float* f, int nx, int ny, int S, float scale,
-                    const float* sub, const int32_t* rowmap, hipStream_t st) {
+pat_status fft2_r2c(const float* f, float2* T, float2* X, int fx, int fy, int nxd, int nyd, int S,
+                    const int32_t* rowmap, hipStream_t st) {
   if (S <= 0) return PAT_OK;
-  const int nh = nx / 2 + 1;
+  if (!extents_ok(fx, fy, nxd, nyd)) return fail(PAT_EINVAL, "fft: data extent does not fit the transform");
+  const int nh = fx / 2 + 1;
   const int rs = spec_stride(S);
-  PAT_TRY(cols<+1>(X, T, ny, nh, S, rs, rowmap, nullptr, st));
-  switch (nx) {
-    case 16: PAT_ROWS(rows_c2r, 16, T, f, ny, S, rs, scale, sub, st); break;
-    case 32: PAT_ROWS(rows_c2r, 32, T, f, ny, S, rs, scale, sub, st); break;
-    case 64: PAT_ROWS(rows_c2r, 64, T, f, ny, S, rs, scale, sub, st); break;
-    case 128: PAT_ROWS(rows_c2r, 128, T, f, ny, S, rs, scale, sub, st); break;
-    case 256: PAT_ROWS(rows_c2r, 256, T, f, ny, S, rs, scale, sub, st); break;
-    default: return fail(PAT_EUNSUPPORTED, "nx must be a power of two in [16, 256]");
+  switch (fx) {
+    case 16: PAT_ROWS(rows_r2c, 16, f, T, nyd, nxd, S, rs, st); break;
+    case 32: PAT_ROWS(rows_r2c, 32, f, T, nyd, nxd, S, rs, st); break;
+    case 64: PAT_ROWS(rows_r2c, 64, f, T, nyd, nxd, S, rs, st); break;
+    case 128: PAT_ROWS(rows_r2c, 128, f, T, nyd, nxd, S, rs, st); break;
+    case 256: PAT_ROWS(rows_r2c, 256, f, T, nyd, nxd, S, rs, st); break;
+    case 512: PAT_ROWS(rows_r2c, 512, f, T, nyd, nxd, S, rs, st); break;
+    default: return fail(PAT_EUNSUPPORTED, "transform size along x must be a power of two in [16, 512]");
+  }
+  PAT_LAUNCHED("fft rows r2c");
+  return cols<-1>(T, X, fy, nh, S, rs, nullptr, rowmap, nyd, fy, st);
+}
+
+pat_status fft2_c2r(const float2* X, float2* T, float* f, int fx, int fy, int nxd, int nyd, int S,
+                    float scale, const float* sub, const int32_t* rowmap, hipStream_t st) {
+  if (S <= 0) return PAT_OK;
+  if (!extents_ok(fx, fy, nxd, nyd)) return fail(PAT_EINVAL, "fft: data extent does not fit the transform");
+  const int nh = fx / 2 + 1;
+  const int rs = spec_stride(S);
+  PAT_TRY(cols<+1>(X, T, fy, nh, S, rs, rowmap, nullptr, fy, nyd, st));
+  switch (fx) {
+    case 16: PAT_ROWS(rows_c2r, 16, T, f, nyd, nxd, S, rs, scale, sub, st); break;
+    case 32: PAT_ROWS(rows_c2r, 32, T, f, nyd, nxd, S, rs, scale, sub, st); break;
+    case 64: PAT_ROWS(rows_c2r, 64, T, f, nyd, nxd, S, rs, scale, sub, st); break;
+    case 128: PAT_ROWS(rows_c2r, 128, T, f, nyd, nxd, S, rs, scale, sub, st); break;
+    case 256: PAT_ROWS(rows_c2r, 256, T, f, nyd, nxd, S, rs, scale, sub, st); break;
+    case 512: PAT_ROWS(rows_c2r, 512, T, f, nyd, nxd, S, rs, scale, sub, st); break;
+    default: return fail(PAT_EUNSUPPORTED, "transform size along x must be a power of two in [16, 512]");
   }
   PAT_LAUNCHED("fft rows c2r");
   return PAT_OK;

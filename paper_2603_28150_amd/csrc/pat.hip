@@ -18,7 +18,8 @@ struct pat_op {
   pat_ctx* ctx;
   pat_geometry g;
   int nq;
-  int nh, nk;
+  int fx, fy;   // transform grid (2 nx x 2 ny for the linear boundary)
+  int nh, nk;   // half-spectrum columns fx/2+1 and frequencies fy*nh
   int G;        // member slots per work item (8: radial, 4: octant, 2: quadrant fold)
   int nclass;   // stored slabs
   int nitem;    // contraction work items (each reads one slab)
@@ -70,6 +71,16 @@ static int default_nq(const pat_geometry& g) {
   return nq;
 }
 
+// the periodic grid the transforms and the library live on
+static pat_geometry transform_geometry(const pat_geometry& g) {
+  pat_geometry t = g;
+  if (g.boundary == PAT_BOUNDARY_LINEAR) {
+    t.nx = 2 * g.nx;
+    t.ny = 2 * g.ny;
+  }
+  return t;
+}
+
 static pat_status check_geometry(const pat_geometry* g) {
   if (!g) return fail(PAT_EINVAL, "geometry is null");
   if (g->nz < 1 || g->nt < 1) return fail(PAT_EINVAL, "nz and nt must be >= 1");
@@ -77,8 +88,12 @@ static pat_status check_geometry(const pat_geometry* g) {
     return fail(PAT_EINVAL, "dx, dy, dz, dt and c must be > 0");
   if (g->nz_sim != 0 && g->nz_sim < g->nz) return fail(PAT_EINVAL, "nz_sim must be 0 or >= nz");
   if (g->h_dtype < PAT_H_F32 || g->h_dtype > PAT_H_F16) return fail(PAT_EINVAL, "unknown h_dtype");
-  if (!pow2_in(g->nx, 16, 256) || !pow2_in(g->ny, 16, 256))
-    return fail(PAT_EUNSUPPORTED, "nx and ny must be powers of two in [16, 256]");
+  if (g->boundary != PAT_BOUNDARY_PERIODIC && g->boundary != PAT_BOUNDARY_LINEAR)
+    return fail(PAT_EINVAL, "unknown boundary");
+  if (g->boundary == PAT_BOUNDARY_PERIODIC && (!pow2_in(g->nx, 16, 512) || !pow2_in(g->ny, 16, 512)))
+    return fail(PAT_EUNSUPPORTED, "periodic: nx and ny must be powers of two in [16, 512]");
+  if (g->boundary == PAT_BOUNDARY_LINEAR && (!pow2_in(g->nx, 8, 256) || !pow2_in(g->ny, 8, 256)))
+    return fail(PAT_EUNSUPPORTED, "linear: nx and ny must be powers of two in [8, 256]");
   if (g->nz > 2048 || g->nt > 2048) return fail(PAT_EUNSUPPORTED, "nz and nt must be <= 2048");
   return PAT_OK;
 }
@@ -214,7 +229,9 @@ static HLayout h_layout(const pat_geometry& g, const Classes& C) {
   L.off_inv = o;     o = align_up(o + (size_t)g.nz * 4, 256);
   L.off_amax = o;    o = align_up(o + (size_t)g.nz * 8, 256);
   L.sG_row = (int)align_up((size_t)g.nz, 4);
-  L.bytes_G = (size_t)L.nclass * g.nz * L.sG_row * 4;
+  // Gram blocks serve the normal-operator gradient, which only the periodic
+  // boundary has (see pat_recon_fista)
+  L.bytes_G = g.boundary == PAT_BOUNDARY_PERIODIC ? (size_t)L.nclass * g.nz * L.sG_row * 4 : 0;
   L.off_Ar = o;      o = align_up(o + L.bytes_Ar, 256);
   L.off_Tr = o;      o = align_up(o + L.bytes_Tr, 256);
   L.off_A = o;       o = align_up(o + L.bytes_A, 256);
@@ -283,6 +300,9 @@ static pat_status check_ptr(const void* p, const char* name) {
   if (misaligned(p)) return fail(PAT_EINVAL, std::string(name) + " is not 16-byte aligned");
   return PAT_OK;
 }
+
+// 1 / (points of the transform grid): the inverse DFT normalisation
+static float inv_area(const pat_op* op) { return 1.0f / (float)((long long)op->fx * op->fy); }
 
 // step (ii): per-frequency contraction of B spectra
 static pat_status run_contract(pat_op* op, bool adjoint, const float2* in, float2* out, int B,
@@ -377,18 +397,18 @@ static pat_status run_gram(pat_op* op, const float2* in, float2* out, const floa
 static pat_status run_A(pat_op* op, const float* x, float* y, int B, const float* sub, const Work& w,
                         hipStream_t st) {
   const pat_geometry& g = op->g;
-  PAT_TRY(fft2_r2c(x, w.T, w.Xs, g.nx, g.ny, B * g.nz, op->rowmap, st));
+  PAT_TRY(fft2_r2c(x, w.T, w.Xs, op->fx, op->fy, g.nx, g.ny, B * g.nz, op->rowmap, st));
   PAT_TRY(run_contract(op, false, w.Xs, w.Ds, B, st));
-  return fft2_c2r(w.Ds, w.T, y, g.nx, g.ny, B * g.nt, 1.0f / (float)(g.nx * g.ny), sub,
+  return fft2_c2r(w.Ds, w.T, y, op->fx, op->fy, g.nx, g.ny, B * g.nt, inv_area(op), sub,
                   op->rowmap, st);
 }
 
 // x = A^T y, B data sets
 static pat_status run_AT(pat_op* op, const float* y, float* x, int B, const Work& w, hipStream_t st) {
   const pat_geometry& g = op->g;
-  PAT_TRY(fft2_r2c(y, w.T, w.Ds, g.nx, g.ny, B * g.nt, op->rowmap, st));
+  PAT_TRY(fft2_r2c(y, w.T, w.Ds, op->fx, op->fy, g.nx, g.ny, B * g.nt, op->rowmap, st));
   PAT_TRY(run_contract(op, true, w.Ds, w.Xs, B, st));
-  return fft2_c2r(w.Xs, w.T, x, g.nx, g.ny, B * g.nz, 1.0f / (float)(g.nx * g.ny), nullptr,
+  return fft2_c2r(w.Xs, w.T, x, op->fx, op->fy, g.nx, g.ny, B * g.nz, inv_area(op), nullptr,
                   op->rowmap, st);
 }
 
@@ -437,8 +457,9 @@ void pat_ctx_destroy(pat_ctx* ctx) { delete ctx; }
 pat_status pat_H_bytes(const pat_geometry* geom, size_t* h_bytes, size_t* scratch_bytes) {
   PAT_TRY(check_geometry(geom));
   if (!h_bytes) return fail(PAT_EINVAL, "h_bytes is null");
-  Classes C = make_classes(*geom);
-  *h_bytes = h_layout(*geom, C).total;
+  const pat_geometry tg = transform_geometry(*geom);
+  Classes C = make_classes(tg);
+  *h_bytes = h_layout(tg, C).total;
   if (scratch_bytes) *scratch_bytes = 0;
   return PAT_OK;
 }
@@ -451,8 +472,9 @@ pat_status pat_H_build(pat_ctx* ctx, const pat_geometry* geom, void* h_buf, size
   *out = nullptr;
   PAT_TRY(check_geometry(geom));
   PAT_TRY(check_ptr(h_buf, "h_buf"));
-  Classes C = make_classes(*geom);
-  HLayout L = h_layout(*geom, C);
+  const pat_geometry tg = transform_geometry(*geom);
+  Classes C = make_classes(tg);
+  HLayout L = h_layout(tg, C);
   if (h_bytes < L.total)
     return fail(PAT_EINVAL, "h_buf too small: need " + std::to_string(L.total) + " bytes");
   for (int32_t kc : C.kclass)
@@ -466,8 +488,10 @@ pat_status pat_H_build(pat_ctx* ctx, const pat_geometry* geom, void* h_buf, size
   op->g = *geom;
   op->nq = geom->nz_sim ? geom->nz_sim : default_nq(*geom);
   op->g.nz_sim = op->nq;
-  op->nh = geom->nx / 2 + 1;
-  op->nk = geom->ny * op->nh;
+  op->fx = tg.nx;
+  op->fy = tg.ny;
+  op->nh = op->fx / 2 + 1;
+  op->nk = op->fy * op->nh;
   op->G = L.G;
   op->nclass = L.nclass;
   op->nitem = L.nitem;
@@ -492,7 +516,7 @@ pat_status pat_H_build(pat_ctx* ctx, const pat_geometry* geom, void* h_buf, size
   const bool f32 = geom->h_dtype == PAT_H_F32;
   op->slabA = f32 ? op->rowA : op->hbuf + L.off_A;
   op->slabT = f32 ? op->rowT : op->hbuf + L.off_T;
-  op->gram = (float*)(op->hbuf + L.off_G);
+  op->gram = L.bytes_G ? (float*)(op->hbuf + L.off_G) : nullptr;
   op->sG_row = L.sG_row;
   op->h_members = std::move(C.members);
   op->h_kclass = std::move(C.kclass);
@@ -525,8 +549,8 @@ pat_status pat_H_build(pat_ctx* ctx, const pat_geometry* geom, void* h_buf, size
   HBuildArgs a;
   a.cls_freq = op->cls_freq;
   a.nclass = op->nclass;
-  a.nx = geom->nx;
-  a.ny = geom->ny;
+  a.nx = op->fx;
+  a.ny = op->fy;
   a.nz = geom->nz;
   a.nt = geom->nt;
   a.nq = op->nq;
@@ -561,7 +585,7 @@ pat_status pat_H_build(pat_ctx* ctx, const pat_geometry* geom, void* h_buf, size
   ga.ksA = op->ksA;
   ga.sG_row = op->sG_row;
   ga.hdtype = geom->h_dtype;
-  if ((s = gram_build(ga, st)) != PAT_OK) return bail(s);
+  if (op->gram && (s = gram_build(ga, st)) != PAT_OK) return bail(s);
   *out = op;
   return PAT_OK;
 }
@@ -583,8 +607,9 @@ pat_status pat_H_export(pat_op* op, int32_t k0, int32_t nk, float* out, void* st
 
 pat_status pat_get_info(const pat_op* op, pat_op_info* info) {
   if (!op || !info) return fail(PAT_EINVAL, "null argument");
-  Classes C = make_classes(op->g);
-  const HLayout L = h_layout(op->g, C);
+  const pat_geometry tg = transform_geometry(op->g);
+  Classes C = make_classes(tg);
+  const HLayout L = h_layout(tg, C);
   info->nk = op->nk;
   info->nclass = op->nclass;
   info->members_max = op->G;
@@ -651,7 +676,8 @@ pat_status pat_spectrum(pat_op* op, const float* f, float* spec, int32_t S, void
   PAT_TRY(check_stage(op, S, ws, ws_bytes, &w));
   PAT_TRY(check_ptr(f, "f"));
   PAT_TRY(check_ptr(spec, "spec"));
-  return fft2_r2c(f, w.T, (float2*)spec, op->g.nx, op->g.ny, S, op->rowmap, (hipStream_t)stream);
+  return fft2_r2c(f, w.T, (float2*)spec, op->fx, op->fy, op->g.nx, op->g.ny, S, op->rowmap,
+                  (hipStream_t)stream);
 }
 
 pat_status pat_inverse_spectrum(pat_op* op, const float* spec, float* f, int32_t S, const float* sub,
@@ -661,8 +687,8 @@ pat_status pat_inverse_spectrum(pat_op* op, const float* spec, float* f, int32_t
   PAT_TRY(check_ptr(f, "f"));
   PAT_TRY(check_ptr(spec, "spec"));
   if (sub) PAT_TRY(check_ptr(sub, "sub"));
-  return fft2_c2r((const float2*)spec, w.T, f, op->g.nx, op->g.ny, S,
-                  1.0f / (float)(op->g.nx * op->g.ny), sub, op->rowmap, (hipStream_t)stream);
+  return fft2_c2r((const float2*)spec, w.T, f, op->fx, op->fy, op->g.nx, op->g.ny, S,
+                  inv_area(op), sub, op->rowmap, (hipStream_t)stream);
 }
 
 pat_status pat_contract(pat_op* op, int32_t adjoint, const float* in, float* out, int32_t B,
@@ -717,13 +743,22 @@ pat_status pat_recon_fista(pat_op* op, const float* d, float* x, int32_t niter, 
   const pat_geometry& g = op->g;
   const long long n = (long long)g.nz * g.nx * g.ny;
   const long long nd = (long long)g.nt * g.nx * g.ny;
-  const float inv = 1.0f / (float)(g.nx * g.ny);
-  // b^ = spectrum of A^T d (the adjoint up to its inverse transform), once
-  PAT_TRY(fft2_r2c(d, w.T, w.Ds, g.nx, g.ny, g.nt, op->rowmap, st));
-  PAT_TRY(run_contract(op, true, w.Ds, w.Bs, 1, st));
-  if (trace) {
-    PAT_TRY(fft2_c2r(w.Bs, w.T, w.V, g.nx, g.ny, g.nz, inv, nullptr, op->rowmap, st));  // b = A^T d
-    PAT_TRY(dot_f64(d, d, nd, w.part64, w.s64 + 2, st));
+  const float inv = inv_area(op);
+  // The periodic operator is block diagonal in the transverse frequency, so
+  // A^T A is too and the gradient is formed per frequency with the Gram
+  // blocks.  The linear boundary crops the data between A and A^T, which
+  // couples frequencies: its gradient is taken explicitly, A then A^T.
+  const bool normal = op->gram != nullptr;
+  if (normal) {
+    // b^ = spectrum of A^T d (the adjoint up to its inverse transform), once
+    PAT_TRY(fft2_r2c(d, w.T, w.Ds, op->fx, op->fy, g.nx, g.ny, g.nt, op->rowmap, st));
+    PAT_TRY(run_contract(op, true, w.Ds, w.Bs, 1, st));
+    if (trace) {
+      PAT_TRY(fft2_c2r(w.Bs, w.T, w.V, op->fx, op->fy, g.nx, g.ny, g.nz, inv, nullptr, op->rowmap, st));  // b = A^T d
+      PAT_TRY(dot_f64(d, d, nd, w.part64, w.s64 + 2, st));
+    }
+  } else if (trace) {
+    PAT_TRY(fill_zero(w.s64, 3 * sizeof(double), st));  // the trace is 1/2 <r, r> alone
   }
   PAT_TRY(fill_zero(x, n * 4, st));
   PAT_TRY(fill_zero(w.Z, n * 4, st));
@@ -731,15 +766,25 @@ pat_status pat_recon_fista(pat_op* op, const float* d, float* x, int32_t niter, 
   FistaBatch p;
   std::memset(&p, 0, sizeof(p));
   for (int k = 1; k <= niter; ++k) {
-    // gradient A^T (A z - d) = A^T A z - A^T d, per frequency: G z^ - b^
-    PAT_TRY(fft2_r2c(w.Z, w.T, w.Xs, g.nx, g.ny, g.nz, op->rowmap, st));
-    PAT_TRY(run_gram(op, w.Xs, w.Gs, w.Bs, 1, st));
-    PAT_TRY(fft2_c2r(w.Gs, w.T, w.U, g.nx, g.ny, g.nz, inv, nullptr, op->rowmap, st));
-    if (trace) {
-      // 1/2 ||A z - d||^2 = 1/2 (<z, g> - <z, b> + ||d||^2), float64 sums
-      PAT_TRY(dot_f64(w.Z, w.U, n, w.part64, w.s64 + 0, st));
-      PAT_TRY(dot_f64(w.Z, w.V, n, w.part64, w.s64 + 1, st));
-      PAT_TRY(trace_combine(trace + (k - 1), w.s64, st));
+    if (normal) {
+      // gradient A^T (A z - d) = A^T A z - A^T d, per frequency: G z^ - b^
+      PAT_TRY(fft2_r2c(w.Z, w.T, w.Xs, op->fx, op->fy, g.nx, g.ny, g.nz, op->rowmap, st));
+      PAT_TRY(run_gram(op, w.Xs, w.Gs, w.Bs, 1, st));
+      PAT_TRY(fft2_c2r(w.Gs, w.T, w.U, op->fx, op->fy, g.nx, g.ny, g.nz, inv, nullptr, op->rowmap, st));
+      if (trace) {
+        // 1/2 ||A z - d||^2 = 1/2 (<z, g> - <z, b> + ||d||^2), float64 sums
+        PAT_TRY(dot_f64(w.Z, w.U, n, w.part64, w.s64 + 0, st));
+        PAT_TRY(dot_f64(w.Z, w.V, n, w.part64, w.s64 + 1, st));
+        PAT_TRY(trace_combine(trace + (k - 1), w.s64, st));
+      }
+    } else {
+      // explicit: residual r = A z - d (fused into the inverse transform), g = A^T r
+      PAT_TRY(run_A(op, w.Z, w.R, 1, d, w, st));
+      if (trace) {
+        PAT_TRY(dot_f64(w.R, w.R, nd, w.part64, w.s64 + 0, st));
+        PAT_TRY(trace_combine(trace + (k - 1), w.s64, st));
+      }
+      PAT_TRY(run_AT(op, w.R, w.U, 1, w, st));
     }
     double beta = 0.0;
     if (momentum) {
@@ -788,6 +833,8 @@ pat_status pat_fista_step_normal(pat_op* op, int32_t B, const float* atd, float*
                                  const double* beta, const float* tau, const float* lambda,
                                  const int32_t* nonneg, int32_t* nonfinite, void* ws,
                                  size_t ws_bytes, void* stream) {
+  if (op && !op->gram)
+    return fail(PAT_EUNSUPPORTED, "the normal-operator step needs the periodic boundary (no Gram blocks)");
   Work w;
   PAT_TRY(check_op_call(op, B, ws, ws_bytes, &w));
   if (B > 32) return fail(PAT_EINVAL, "B must be <= 32");
@@ -807,9 +854,9 @@ pat_status pat_fista_step_normal(pat_op* op, int32_t B, const float* atd, float*
     p.o[b].beta = (float)beta[b];
     p.o[b].nonneg = nonneg[b] ? 1 : 0;
   }
-  PAT_TRY(fft2_r2c(z, w.T, w.Xs, g.nx, g.ny, B * g.nz, op->rowmap, st));
+  PAT_TRY(fft2_r2c(z, w.T, w.Xs, op->fx, op->fy, g.nx, g.ny, B * g.nz, op->rowmap, st));
   PAT_TRY(run_gram(op, w.Xs, w.Gs, nullptr, B, st));
-  PAT_TRY(fft2_c2r(w.Gs, w.T, w.U, g.nx, g.ny, B * g.nz, 1.0f / (float)(g.nx * g.ny), atd,
+  PAT_TRY(fft2_c2r(w.Gs, w.T, w.U, op->fx, op->fy, g.nx, g.ny, B * g.nz, inv_area(op), atd,
                    op->rowmap, st));  // U = A^T A z - A^T d
   return fista_update(x, z, w.U, n, B, p, nonfinite, st);
 }

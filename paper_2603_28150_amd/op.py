@@ -26,15 +26,18 @@ class Geometry:
     dt: float
     c: float
     nz_sim: int = 0
+    boundary: str = "periodic"     # "periodic" or "linear" (zero-padded, Sec. 2.3)
 
     @staticmethod
-    def paper_like(nx, ny, nz, nt, dx=100e-6, c=1500.0, cfl=0.3, nz_sim=0) -> "Geometry":
+    def paper_like(nx, ny, nz, nt, dx=100e-6, c=1500.0, cfl=0.3, nz_sim=0,
+                   boundary="periodic") -> "Geometry":
         """dx = dy = dz, dt = cfl * dx / c (the physics of the synthetic workloads)."""
-        return Geometry(nx, ny, nz, nt, dx, dx, dx, cfl * dx / c, c, nz_sim)
+        return Geometry(nx, ny, nz, nt, dx, dx, dx, cfl * dx / c, c, nz_sim, boundary)
 
     def to_c(self, h_dtype: str) -> _lib.Geometry:
         return _lib.Geometry(self.nx, self.ny, self.nz, self.nt, self.dx, self.dy, self.dz,
-                             self.dt, self.c, self.nz_sim, _lib.HDTYPES[h_dtype])
+                             self.dt, self.c, self.nz_sim, _lib.HDTYPES[h_dtype],
+                             _lib.BOUNDARIES[self.boundary])
 
 
 def _stream(device: torch.device) -> int:
@@ -111,7 +114,10 @@ class Operator:
 
     @property
     def nk(self) -> int:
-        return self.geom.ny * (self.geom.nx // 2 + 1)
+        """Half-spectrum frequencies of the transform grid (doubled for the
+        linear boundary)."""
+        f = 2 if self.geom.boundary == "linear" else 1
+        return f * self.geom.ny * (f * self.geom.nx // 2 + 1)
 
     def info(self) -> dict:
         """Stored-library shape: nk, nclass, members_max, nz_sim, slab bytes per layout."""

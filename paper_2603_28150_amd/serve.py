@@ -81,7 +81,10 @@ class HipBackend:
     normal=True (default) steps requests with the per-frequency normal
     operator: a slot keeps A^T d (formed once at admission) instead of d, and
     an iteration costs one z-spectrum, one nz x nz contraction and one inverse
-    spectrum; normal=False takes the explicit A then A^T every iteration."""
+    spectrum; normal=False takes the explicit A then A^T every iteration.
+    Geometries with the linear (zero-padded) boundary always take the explicit
+    step: cropping the data between A and A^T breaks the per-frequency
+    structure of A^T A."""
 
     def __init__(self, device: int = 0, normal: bool = True):
         self.device = torch.device("cuda", device)
@@ -103,9 +106,12 @@ class HipBackend:
             L, _ = op.power_norm(v0, 30)
         return 1.0 / L
 
+    def uses_normal(self, op) -> bool:
+        return self.normal and op.geom.boundary == "periodic"
+
     def slot_bytes(self, op) -> int:
         g = op.geom
-        if self.normal:
+        if self.uses_normal(op):
             return 4 * g.nx * g.ny * 3 * g.nz + 4
         return 4 * g.nx * g.ny * (2 * g.nz + g.nt) + 4
 
@@ -117,8 +123,8 @@ class HipBackend:
 
     def alloc_pool(self, op, cap, stream):
         g = op.geom
-        data = "b" if self.normal else "d"
-        dshape = op.x_shape if self.normal else op.d_shape
+        data = "b" if self.uses_normal(op) else "d"
+        dshape = op.x_shape if self.uses_normal(op) else op.d_shape
         with torch.cuda.stream(stream):
             return {"x": torch.zeros((cap,) + op.x_shape, device=self.device),
                     "z": torch.zeros((cap,) + op.x_shape, device=self.device),
@@ -128,7 +134,7 @@ class HipBackend:
 
     def load_row(self, pool, i, d, stream, op=None):
         with torch.cuda.stream(stream):
-            if self.normal:
+            if "b" in pool:
                 op.apply_AT(d.to(self.device, non_blocking=True), out=pool["b"][i])
             else:
                 pool["d"][i].copy_(d, non_blocking=True)
@@ -148,7 +154,7 @@ class HipBackend:
 
     def step(self, op, pool, ws, n, betas, taus, lams, nonnegs, stream):
         with torch.cuda.stream(stream):
-            if self.normal:
+            if "b" in pool:
                 op.fista_step_normal(pool["b"][:n], pool["x"][:n], pool["z"][:n], betas, taus, lams,
                                      nonnegs, nonfinite=pool["bad"][:n], ws=ws)
             else:
