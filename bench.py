@@ -365,6 +365,23 @@ def forms(op, x, x64, args, samples: dict) -> dict:
             del o
         torch.cuda.empty_cache()
     del xb
+    # zero-padded linear convolution (Sec. 2.3): same object and data grids,
+    # transforms and library on the doubled 512^2 grid
+    gl = Geometry.paper_like(g.nx, g.ny, g.nz, g.nt, boundary="linear")
+    t0 = time.perf_counter()
+    ol = Operator(gl, "f32")
+    torch.cuda.synchronize()
+    res["linear_library_build_s"] = time.perf_counter() - t0
+    infl = ol.info()
+    secs, tA, tAT = time_pairs(ol, x, max(5, args.steps // 2), 2)
+    bl = contraction_bytes(infl, ol.nk, g.nz, g.nt, False) + contraction_bytes(infl, ol.nk, g.nz, g.nt, True)
+    res["linear_pairs_per_s"] = max(5, args.steps // 2) / secs
+    res["linear_contract_GBs"] = bl / ((tA + tAT) * 1e-3) / 1e9
+    res["linear_library_GiB"] = (infl["slab_bytes_A"] + infl["slab_bytes_AT"]) / 2**30
+    log(f"linear (512^2 transforms): {res['linear_pairs_per_s']:.1f} pairs/s, "
+        f"contraction {res['linear_contract_GBs']:.0f} GB/s, library {res['linear_library_GiB']:.1f} GiB")
+    del ol
+    torch.cuda.empty_cache()
     # differentiable form: 200 Adam steps on 1/2 ||A x - y||^2 + 1e-3 TV(x), 128^2 x 64 x 256
     ga = Geometry.paper_like(128, 128, 64, 256)
     oa = Operator(ga, "f32")

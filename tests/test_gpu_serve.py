@@ -1,11 +1,11 @@
 """Serving form on the GPU: every request's result is the same alone and in a
-mix of geometries and library precisions (continuous batching)."""
+mix of geometries, boundaries and library precisions (continuous batching)."""
 import numpy as np
 import pytest
 import torch
 
 from oracle import hlib, operators as ops, solvers
-from oracle.geometry import Geometry as OGeom
+from oracle.geometry import Geometry as OGeom, doubled
 from paper_2603_28150_amd import inputs
 from paper_2603_28150_amd.op import Geometry
 from paper_2603_28150_amd.serve import HipBackend, Request, Server
@@ -14,13 +14,22 @@ pytestmark = pytest.mark.gpu
 
 GA = Geometry.paper_like(64, 64, 64, 256)
 GB = Geometry.paper_like(32, 32, 16, 64)
+GL = Geometry.paper_like(32, 32, 16, 64, boundary="linear")    # zero-padded, explicit step
+
+
+def _ops(g):
+    o = OGeom(g.nx, g.ny, g.nz, g.nt, g.dx, g.dy, g.dz, g.dt, g.c)
+    if g.boundary == "linear":
+        Hh = hlib.H_half(doubled(o))
+        return Hh, (lambda v: ops.A_linear(Hh, v)), (lambda v: ops.AT_linear(Hh, v))
+    Hh = hlib.H_half(o)
+    return Hh, (lambda v: ops.A_fft(Hh, v)), (lambda v: ops.AT_fft(Hh, v))
 
 
 def _data(g, seed):
-    o = OGeom(g.nx, g.ny, g.nz, g.nt, g.dx, g.dy, g.dz, g.dt, g.c)
-    Hh = hlib.H_half(o)
+    Hh, A, _ = _ops(g)
     p0 = inputs.vascular_phantom((g.nz, g.ny, g.nx), seed=seed, n_tubes=6)
-    clean = ops.A_fft(Hh, p0)
+    clean = A(p0)
     d = clean + inputs.NOISE_20DB * np.sqrt(np.mean(clean ** 2)) * inputs.noise_like(clean.shape, seed=seed + 1)
     return torch.from_numpy(d.astype(np.float32)).cuda(), Hh, d
 
@@ -31,8 +40,9 @@ def rel(a, b):
 
 @pytest.mark.parametrize("normal", [True, False])
 def test_results_alone_equal_results_in_the_mix(normal):
-    plan = [(GA, "f32", 12), (GB, "f32", 20), (GA, "bf16", 9), (GA, "f32", 15), (GB, "f32", 7),
-            (GA, "bf16", 11), (GA, "f32", 5), (GB, "bf16", 8)]
+    plan = [(GA, "f32", 12), (GB, "f32", 20), (GA, "bf16", 9), (GL, "f32", 10), (GA, "f32", 15),
+            (GB, "f32", 7), (GL, "bf16", 6), (GA, "bf16", 11), (GA, "f32", 5), (GL, "f32", 9),
+            (GB, "bf16", 8)]
     datas = [_data(g, 500 + 7 * i)[0] for i, (g, _, _) in enumerate(plan)]
     srv = Server(HipBackend(normal=normal), hbm_budget=8 << 30, max_batch=4)
     reqs = []
@@ -57,14 +67,14 @@ def test_results_alone_equal_results_in_the_mix(normal):
         assert rel(r.x, a.x) < 1e-5, (r.rid, r.h_dtype)
 
 
-def test_served_fista_matches_oracle():
-    d, Hh, d64 = _data(GB, 77)
+@pytest.mark.parametrize("g", [GB, GL], ids=["periodic", "linear"])
+def test_served_fista_matches_oracle(g):
+    d, Hh, d64 = _data(g, 77)
     srv = Server(HipBackend(), hbm_budget=4 << 30)
-    r = srv.submit(Request(geom=GB, d=d, niter=15))
+    r = srv.submit(Request(geom=g, d=d, niter=15))
     srv.run_until_idle()
     torch.cuda.synchronize()
-    A = lambda v: ops.A_fft(Hh, v)
-    AT = lambda v: ops.AT_fft(Hh, v)
-    xo = solvers.fista(A, AT, d.double().cpu().numpy(), (GB.nz, GB.ny, GB.nx), 15, float(np.float32(r.tau)), 0.0)[-1]
+    _, A, AT = _ops(g)
+    xo = solvers.fista(A, AT, d.double().cpu().numpy(), (g.nz, g.ny, g.nx), 15, float(np.float32(r.tau)), 0.0)[-1]
     xg = r.x.double().cpu().numpy()
     assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) < 1e-5
