@@ -89,3 +89,17 @@ def h_space(g: Geometry, Hf: np.ndarray | None = None) -> np.ndarray:
     if np.abs(h.imag).max() > 1e-12 * max(1.0, np.abs(h.real).max()):
         raise AssertionError("real-space kernels are not real")
     return np.ascontiguousarray(np.transpose(h.real, (2, 0, 1, 3)))
+
+
+def with_sensor_response(H: np.ndarray, r) -> np.ndarray:
+    """Library seen through sensors with the causal impulse response r (taps
+    at t = 0, dt, ...), folded in along the time axis (the last one):
+    H'[..., n] = sum_{j <= min(n, len(r)-1)} r[j] H[..., n-j]; nothing is
+    recorded before t = 0.  r = [1] gives the ideal point sensors."""
+    r = np.asarray(r, dtype=np.float64)
+    nt = H.shape[-1]
+    out = np.zeros(H.shape, dtype=np.result_type(H, r))
+    for j in range(min(len(r), nt)):
+        out[..., j:] += r[j] * H[..., :nt - j]
+    return out
+

@@ -147,6 +147,27 @@ def AT_linear(Hh2: np.ndarray, d: np.ndarray) -> np.ndarray:
     return AT_fft(Hh2, pad2(d, py, 2 * (nh2 - 1)))[:, :ny, :nx]
 
 
+# --------------------------------------------------- sensor response along t
+def filter_t(d: np.ndarray, r) -> np.ndarray:
+    """Causal filtering of data d[n, j, i] along time: sum_j r[j] d[n-j]."""
+    r = np.asarray(r, dtype=np.float64)
+    nt = d.shape[0]
+    out = np.zeros(d.shape)
+    for j in range(min(len(r), nt)):
+        out[j:] += r[j] * d[:nt - j]
+    return out
+
+
+def filter_t_adjoint(d: np.ndarray, r) -> np.ndarray:
+    """Adjoint of filter_t (anti-causal correlation): sum_j r[j] d[n+j]."""
+    r = np.asarray(r, dtype=np.float64)
+    nt = d.shape[0]
+    out = np.zeros(d.shape)
+    for j in range(min(len(r), nt)):
+        out[:nt - j] += r[j] * d[j:]
+    return out
+
+
 # ----------------------------------------- single frequencies of large grids
 def dft_at(f: np.ndarray, m_idx, p_idx) -> np.ndarray:
     """Forward 2D DFT of every slice of f[s, j, i] at the frequencies

@@ -122,3 +122,17 @@ def noise_like(shape, seed: int) -> np.ndarray:
 
 NOISE_1PCT = 0.01
 NOISE_20DB = 10.0 ** (-20.0 / 20.0)
+
+
+def bandpass_fir(ntaps: int, f_lo: float, f_hi: float, dt: float) -> np.ndarray:
+    """Causal band-pass impulse response for a sensor model: a Hann-windowed
+    difference of two sinc low-passes (cut-offs f_lo < f_hi in Hz, sampling
+    step dt), delayed by (ntaps-1)/2 samples and scaled to unit gain at the
+    band centre.  Filter design only; it is an input of the operator."""
+    n = np.arange(ntaps) - (ntaps - 1) / 2.0
+    w = 0.5 - 0.5 * np.cos(2.0 * np.pi * np.arange(ntaps) / (ntaps - 1))
+    h = (2 * f_hi * dt * np.sinc(2 * f_hi * dt * n) - 2 * f_lo * dt * np.sinc(2 * f_lo * dt * n)) * w
+    fc = 0.5 * (f_lo + f_hi)
+    gain = abs(np.sum(h * np.exp(-2j * np.pi * fc * dt * np.arange(ntaps))))
+    return h / gain
+
