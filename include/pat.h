@@ -90,6 +90,15 @@ typedef struct {
                       otherwise it must be >= nz */
   int32_t h_dtype; /* pat_hdtype */
   int32_t boundary; /* pat_boundary */
+  /* Temporal response of the sensors (the ideal point sensors of Sec. 2.1
+   * when n_ir = 0): a causal FIR filter of n_ir <= 64 taps ir[0..n_ir-1]
+   * (host float64, read by pat_H_bytes and pat_H_build only and copied into
+   * the library), folded into the library along t:
+   *     H^'[k, l, n] = sum_{j <= min(n, n_ir-1)} ir[j] H^[k, l, n-j],
+   * so A returns the filtered data and A^T applies the matching correlation
+   * at no cost per apply. */
+  int32_t n_ir;
+  const double* ir;
 } pat_geometry;
 
 /* ---------------------------------------------------------------- context */

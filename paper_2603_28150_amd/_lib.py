@@ -25,7 +25,8 @@ class Geometry(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("nt", C.c_int32),
                 ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
                 ("dt", C.c_double), ("c", C.c_double),
-                ("nz_sim", C.c_int32), ("h_dtype", C.c_int32), ("boundary", C.c_int32)]
+                ("nz_sim", C.c_int32), ("h_dtype", C.c_int32), ("boundary", C.c_int32),
+                ("n_ir", C.c_int32), ("ir", C.POINTER(C.c_double))]
 
 
 H_F32, H_BF16, H_F16 = 0, 1, 2

@@ -13,7 +13,8 @@
 // {q, -q} and 1 for q = 0 and the Nyquist plane; the imaginary parts cancel
 // in pairs, so H^ is real.  Phases reach several hundred radians, so the
 // whole build runs in float64 and rounds once (to float32, then to 16 bits
-// for the reduced-precision forms).
+// for the reduced-precision forms).  A sensor response r (causal FIR) is
+// folded in along t: H^'[l, n] = sum_j r_j H^[l, n - j].
 #include <cmath>
 
 #include "pat_internal.hpp"
@@ -52,11 +53,18 @@ __device__ __forceinline__ unsigned short to_f16(float f) {
   return b;
 }
 
-template <int MODE>  // 0: per-depth max |H^| only, 1: write the slabs
+// MODE 0: per-depth max |H^| only, 1: write the slabs.  FIR: fold the sensor
+// response into the time axis.  The library is linear in the time factor
+// cos(n theta_q), so the filter acts on that factor: each q-chunk also
+// evaluates it at the n_ir - 1 earlier samples (zero before t = 0) and
+// filters in LDS before the depth sum.
+template <int MODE, bool FIR>
 __global__ __launch_bounds__(256) void k_hbuild(HBuildArgs a) {
   __shared__ double ctab[kMaxNq];
   __shared__ double P[kQB * kNT];
   __shared__ float tile[kNT * (kLP + 1)];
+  __shared__ double Praw[FIR ? kQB * (kNT + kMaxIr - 1) : 1];
+  __shared__ double irs[FIR ? kMaxIr : 1];
   const int tid = threadIdx.x;
   const int nl = tid & (kNT - 1), lg = tid >> 6;
   const int c = blockIdx.y;
@@ -66,6 +74,8 @@ __global__ __launch_bounds__(256) void k_hbuild(HBuildArgs a) {
   const double two_pi = 6.283185307179586476925286766559;
 
   for (int r = tid; r < nq; r += 256) ctab[r] = cos(two_pi * (double)r / (double)nq);
+  if constexpr (FIR)
+    for (int j = tid; j < a.n_ir; j += 256) irs[j] = a.ir[j];
 
   const int fx = a.cls_freq[2 * c], fy = a.cls_freq[2 * c + 1];
   const double kx = two_pi * fx / (a.nx * a.dx);
@@ -85,17 +95,42 @@ __global__ __launch_bounds__(256) void k_hbuild(HBuildArgs a) {
     }
     for (int q0 = 0; q0 < Qn; q0 += kQB) {
       __syncthreads();
-      for (int e = tid; e < kQB * kNT; e += 256) {
-        const int qq = e / kNT, nn = e % kNT;
-        const int q = q0 + qq, ng = blockIdx.x * kNT + nn;
-        double v = 0.0;
-        if (q < Qn && ng < a.nt) {
-          const double kz = two_pi * q / (nq * a.dz);
-          const double theta = cdt * sqrt(kperp2 + kz * kz);
-          const double w = (q == 0 || 2 * q == nq) ? 1.0 : 2.0;
-          v = w * inv_nq * cos((double)ng * theta);
+      if constexpr (!FIR) {
+        for (int e = tid; e < kQB * kNT; e += 256) {
+          const int qq = e / kNT, nn = e % kNT;
+          const int q = q0 + qq, ng = blockIdx.x * kNT + nn;
+          double v = 0.0;
+          if (q < Qn && ng < a.nt) {
+            const double kz = two_pi * q / (nq * a.dz);
+            const double theta = cdt * sqrt(kperp2 + kz * kz);
+            const double w = (q == 0 || 2 * q == nq) ? 1.0 : 2.0;
+            v = w * inv_nq * cos((double)ng * theta);
+          }
+          P[e] = v;
         }
-        P[e] = v;
+      } else {
+        const int L = a.n_ir, W = kNT + L - 1;
+        const int nbase = blockIdx.x * kNT - (L - 1);
+        for (int e = tid; e < kQB * W; e += 256) {
+          const int qq = e / W, nr = e % W;
+          const int q = q0 + qq, ng = nbase + nr;
+          double v = 0.0;
+          if (q < Qn && ng >= 0 && ng < a.nt) {
+            const double kz = two_pi * q / (nq * a.dz);
+            const double theta = cdt * sqrt(kperp2 + kz * kz);
+            const double w = (q == 0 || 2 * q == nq) ? 1.0 : 2.0;
+            v = w * inv_nq * cos((double)ng * theta);
+          }
+          Praw[qq * W + nr] = v;
+        }
+        __syncthreads();
+        for (int e = tid; e < kQB * kNT; e += 256) {
+          const int qq = e / kNT, nn = e % kNT;
+          const double* pr = Praw + qq * W + nn + (L - 1);
+          double v = 0.0;
+          for (int j = 0; j < L; ++j) v = fma(irs[j], pr[-j], v);
+          P[e] = v;
+        }
       }
       __syncthreads();
       const int qe = (Qn - q0) < kQB ? (Qn - q0) : kQB;
@@ -189,13 +224,18 @@ __global__ void k_scales(const unsigned long long* amax, float* inv_scale, int n
 pat_status hbuild(const HBuildArgs& a, hipStream_t st) {
   if (a.nq > kMaxNq) return fail(PAT_EUNSUPPORTED, "nz_sim above 4096 is not supported");
   dim3 grid((a.nt + kNT - 1) / kNT, a.nclass);
+  if (a.n_ir < 0 || a.n_ir > kMaxIr || (a.n_ir > 0 && !a.ir))
+    return fail(PAT_EINVAL, "sensor response: 0..64 taps");
+  const bool fir = a.n_ir > 0;
   if (a.hdtype != PAT_H_F32) {
-    k_hbuild<0><<<grid, 256, 0, st>>>(a);
+    if (fir) k_hbuild<0, true><<<grid, 256, 0, st>>>(a);
+    else k_hbuild<0, false><<<grid, 256, 0, st>>>(a);
     PAT_LAUNCHED("H build (max pass)");
   }
   k_scales<<<(a.nz + 127) / 128, 128, 0, st>>>(a.amax, a.inv_scale, a.nz, a.hdtype);
   PAT_LAUNCHED("H build (scales)");
-  k_hbuild<1><<<grid, 256, 0, st>>>(a);
+  if (fir) k_hbuild<1, true><<<grid, 256, 0, st>>>(a);
+  else k_hbuild<1, false><<<grid, 256, 0, st>>>(a);
   PAT_LAUNCHED("H build");
   return PAT_OK;
 }

@@ -42,6 +42,7 @@ struct pat_op {
   float* gram;        // [nclass][nz][sG_row]  Gram blocks of the library
   int sG_row;
   std::vector<int32_t> h_members, h_kclass, h_cls_freq, h_rowmap, h_item_slab;
+  std::vector<double> h_ir;  // sensor response taps folded into the library
 };
 
 namespace pat {
@@ -95,6 +96,12 @@ static pat_status check_geometry(const pat_geometry* g) {
   if (g->boundary == PAT_BOUNDARY_LINEAR && (!pow2_in(g->nx, 8, 256) || !pow2_in(g->ny, 8, 256)))
     return fail(PAT_EUNSUPPORTED, "linear: nx and ny must be powers of two in [8, 256]");
   if (g->nz > 2048 || g->nt > 2048) return fail(PAT_EUNSUPPORTED, "nz and nt must be <= 2048");
+  if (g->n_ir < 0 || g->n_ir > kMaxIr) return fail(PAT_EUNSUPPORTED, "n_ir must be in [0, 64]");
+  if (g->n_ir > 0) {
+    if (!g->ir) return fail(PAT_EINVAL, "ir is null while n_ir > 0");
+    for (int j = 0; j < g->n_ir; ++j)
+      if (!std::isfinite(g->ir[j])) return fail(PAT_EINVAL, "sensor response taps must be finite");
+  }
   return PAT_OK;
 }
 
@@ -185,8 +192,8 @@ static Classes make_classes(const pat_geometry& g) {
 }
 
 struct HLayout {
-  size_t off_members, off_items, off_kclass, off_rowmap, off_freq, off_inv, off_amax, off_A, off_T,
-      off_Ar, off_Tr, off_G, total;
+  size_t off_members, off_items, off_kclass, off_rowmap, off_freq, off_inv, off_amax, off_ir, off_A,
+      off_T, off_Ar, off_Tr, off_G, total;
   size_t bytes_A, bytes_T, bytes_Ar, bytes_Tr, bytes_G;
   int sG_row;
   int nclass, nitem, G, vec, sA_row, sT_row;
@@ -228,6 +235,7 @@ static HLayout h_layout(const pat_geometry& g, const Classes& C) {
   L.off_freq = o;    o = align_up(o + (size_t)L.nclass * 8, 256);
   L.off_inv = o;     o = align_up(o + (size_t)g.nz * 4, 256);
   L.off_amax = o;    o = align_up(o + (size_t)g.nz * 8, 256);
+  L.off_ir = o;      o = align_up(o + (size_t)g.n_ir * 8, 256);
   L.sG_row = (int)align_up((size_t)g.nz, 4);
   // Gram blocks serve the normal-operator gradient, which only the periodic
   // boundary has (see pat_recon_fista)
@@ -486,6 +494,8 @@ pat_status pat_H_build(pat_ctx* ctx, const pat_geometry* geom, void* h_buf, size
   if (!op) return fail(PAT_ENOMEM, "host allocation failed");
   op->ctx = ctx;
   op->g = *geom;
+  op->h_ir.assign(geom->ir, geom->ir + geom->n_ir);
+  op->g.ir = nullptr;  // not retained: the taps live in h_ir and in the library
   op->nq = geom->nz_sim ? geom->nz_sim : default_nq(*geom);
   op->g.nz_sim = op->nq;
   op->fx = tg.nx;
@@ -546,7 +556,14 @@ pat_status pat_H_build(pat_ctx* ctx, const pat_geometry* geom, void* h_buf, size
   if ((s = hip_check(hipMemcpyAsync(op->item_slab, op->h_item_slab.data(), op->h_item_slab.size() * 4,
                                     hipMemcpyHostToDevice, st), "upload items")) != PAT_OK)
     return bail(s);
+  double* d_ir = reinterpret_cast<double*>(op->hbuf + L.off_ir);
+  if (geom->n_ir > 0 &&
+      (s = hip_check(hipMemcpyAsync(d_ir, op->h_ir.data(), op->h_ir.size() * 8, hipMemcpyHostToDevice, st),
+                     "upload sensor response")) != PAT_OK)
+    return bail(s);
   HBuildArgs a;
+  a.ir = geom->n_ir > 0 ? d_ir : nullptr;
+  a.n_ir = geom->n_ir;
   a.cls_freq = op->cls_freq;
   a.nclass = op->nclass;
   a.nx = op->fx;

@@ -104,7 +104,10 @@ struct HBuildArgs {
   unsigned long long* amax; // [nz] bit patterns of max |H^| per depth
   float* inv_scale;         // [nz] 1/s_l
   int hdtype;
+  const double* ir;         // [n_ir] sensor response taps (device), or null
+  int n_ir;                 // 0: ideal sensors
 };
+constexpr int kMaxIr = 64;  // longest sensor response folded into the library
 pat_status hbuild(const HBuildArgs& a, hipStream_t st);
 struct GramArgs {
   const void* slabA;        // stored library, [l][n] rows (FP32) or fragments (16-bit)

@@ -27,17 +27,22 @@ class Geometry:
     c: float
     nz_sim: int = 0
     boundary: str = "periodic"     # "periodic" or "linear" (zero-padded, Sec. 2.3)
+    ir: tuple = ()                 # sensor response taps (causal FIR along t), () = ideal
 
     @staticmethod
     def paper_like(nx, ny, nz, nt, dx=100e-6, c=1500.0, cfl=0.3, nz_sim=0,
-                   boundary="periodic") -> "Geometry":
+                   boundary="periodic", ir=()) -> "Geometry":
         """dx = dy = dz, dt = cfl * dx / c (the physics of the synthetic workloads)."""
-        return Geometry(nx, ny, nz, nt, dx, dx, dx, cfl * dx / c, c, nz_sim, boundary)
+        return Geometry(nx, ny, nz, nt, dx, dx, dx, cfl * dx / c, c, nz_sim, boundary,
+                        tuple(float(v) for v in ir))
 
     def to_c(self, h_dtype: str) -> _lib.Geometry:
-        return _lib.Geometry(self.nx, self.ny, self.nz, self.nt, self.dx, self.dy, self.dz,
-                             self.dt, self.c, self.nz_sim, _lib.HDTYPES[h_dtype],
-                             _lib.BOUNDARIES[self.boundary])
+        g = _lib.Geometry(self.nx, self.ny, self.nz, self.nt, self.dx, self.dy, self.dz,
+                          self.dt, self.c, self.nz_sim, _lib.HDTYPES[h_dtype],
+                          _lib.BOUNDARIES[self.boundary], len(self.ir))
+        if self.ir:
+            g.ir = (C.c_double * len(self.ir))(*self.ir)   # kept alive by the struct
+        return g
 
 
 def _stream(device: torch.device) -> int:
