@@ -168,6 +168,19 @@ def filter_t_adjoint(d: np.ndarray, r) -> np.ndarray:
     return out
 
 
+# ------------------------------------------------- scan-grid sampling operator
+def sample(d: np.ndarray, sx: int, sy: int) -> np.ndarray:
+    """S: the data at every sx-th column and sy-th row of the sensor grid."""
+    return np.ascontiguousarray(d[..., ::sy, ::sx])
+
+
+def sample_adjoint(ds: np.ndarray, sx: int, sy: int, ny: int, nx: int) -> np.ndarray:
+    """S^T: scan-grid data placed back on the sensor grid, zeros elsewhere."""
+    out = np.zeros(ds.shape[:-2] + (ny, nx))
+    out[..., ::sy, ::sx] = ds
+    return out
+
+
 # ----------------------------------------- single frequencies of large grids
 def dft_at(f: np.ndarray, m_idx, p_idx) -> np.ndarray:
     """Forward 2D DFT of every slice of f[s, j, i] at the frequencies
