@@ -99,6 +99,11 @@ typedef struct {
    * at no cost per apply. */
   int32_t n_ir;
   const double* ir;
+  /* Scan grid: the data are recorded at every sx-th column and sy-th row of
+   * the nx x ny sensor grid (a sampling operator S after A, zero-filling S^T
+   * before A^T), so data arrays are [nt][ny/sy][nx/sx].  sx must divide nx
+   * with nx/sx a multiple of 4, sy must divide ny; 0 or 1: every point. */
+  int32_t sx, sy;
 } pat_geometry;
 
 /* ---------------------------------------------------------------- context */
@@ -170,11 +175,12 @@ pat_status pat_workspace_bytes(const pat_op* op, int32_t B, size_t* bytes);
 
 /* ------------------------------------------------------------- operators */
 
-/* y = A x for B objects (eq. 7-8): x [B][nz][ny][nx] -> y [B][nt][ny][nx]. */
+/* y = A x for B objects (eq. 7-8): x [B][nz][ny][nx] -> y [B][nt][ny/sy][nx/sx]
+ * (y [B][nt][ny][nx] without scan-grid sampling; likewise everywhere below). */
 pat_status pat_apply_A(pat_op* op, const float* x, float* y, int32_t B,
                        void* ws, size_t ws_bytes, void* stream);
 
-/* x = A^T y for B data sets (eq. 11): y [B][nt][ny][nx] -> x [B][nz][ny][nx]. */
+/* x = A^T y for B data sets (eq. 11): y [B][nt][ny/sy][nx/sx] -> x [B][nz][ny][nx]. */
 pat_status pat_apply_AT(pat_op* op, const float* y, float* x, int32_t B,
                         void* ws, size_t ws_bytes, void* stream);
 
@@ -192,6 +198,8 @@ pat_status pat_apply_AT(pat_op* op, const float* y, float* x, int32_t B,
  * pat_inverse_spectrum(B*nt), and pat_apply_AT the same with nz and nt
  * swapped and pat_contract(1); the calls launch the same kernels.
  *
+ * The stage calls act on the full sensor grid: for a geometry with a scan
+ * grid, S and S^T are applied by pat_apply_A / pat_apply_AT only.
  * pat_spectrum: unnormalised 2D DFT over (x, y) of S real slices f[S][ny][nx]
  * (step (i)); pat_inverse_spectrum: f = IDFT2(spec) / (nx*ny) - sub for S
  * slices (step (iii); sub may be NULL, else it has the layout of f).  Both need

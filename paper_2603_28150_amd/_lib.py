@@ -26,7 +26,8 @@ class Geometry(C.Structure):
                 ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
                 ("dt", C.c_double), ("c", C.c_double),
                 ("nz_sim", C.c_int32), ("h_dtype", C.c_int32), ("boundary", C.c_int32),
-                ("n_ir", C.c_int32), ("ir", C.POINTER(C.c_double))]
+                ("n_ir", C.c_int32), ("ir", C.POINTER(C.c_double)),
+                ("sx", C.c_int32), ("sy", C.c_int32)]
 
 
 H_F32, H_BF16, H_F16 = 0, 1, 2

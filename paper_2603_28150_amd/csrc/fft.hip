@@ -13,11 +13,12 @@
 // Twiddles exp(-2 pi i e / 512) are tabulated on the host in float64 and
 // rounded once to float32.
 //
-// Transform sizes and data extents are separate: slices hold nx_d x ny_d
-// values and are transformed on an fx x fy grid (nx_d <= fx, ny_d <= fy).
-// Missing rows and columns are zeros that are never read (forward) and
-// rows and columns beyond the data are never written (inverse), so the
-// zero-padded linear convolution costs no extra HBM traffic.
+// Transform sizes and data extents are separate: slices cover an nx_d x ny_d
+// window of the fx x fy transform grid (nx_d <= fx, ny_d <= fy), sampled at
+// every sx-th column and sy-th row (the slices store (nx_d/sx) x (ny_d/sy)
+// values).  Points outside the window or between samples are zeros that are
+// never read (forward) and never written (inverse), so the zero-padded
+// linear convolution and the scan-grid sampling cost no extra HBM traffic.
 #include <cmath>
 
 #include "dft.hpp"
@@ -48,10 +49,12 @@ __device__ __forceinline__ void load_twiddles(float2* tw, int tid, int nthreads)
 }
 
 // ------------------------------------------------------------- columns (y)
-// out[orow(p*nh + m)*rs + s] = sum_{j < nin} exp(DIR 2 pi i p j / N) in[irow(j*nh + m)*rs + s]
-// for p < nout (rows j >= nin are zeros); irow / orow: row maps (null =
-// identity); the spectrum side uses the class-major map so that the
-// contraction reads and writes contiguous rows.
+// out[orow(p)*rs + s] = sum_j exp(DIR 2 pi i p j / N) in[irow(j)*rs + s]
+// irow / orow: the spectrum side uses the class-major row map so that the
+// contraction reads and writes contiguous rows; the other side is compact:
+// only rows j = istride*j' with j' < nin are present (the others are zeros),
+// at row j'*nh + m, and only rows p = ostride*p' with p' < nout are written,
+// at row p'*nh + m.
 template <int N> struct ColSB { static constexpr int value = N <= 256 ? 16 : 8; };  // slices per block
 
 template <int N, int DIR>
@@ -59,7 +62,7 @@ __global__ __launch_bounds__(256) void k_fft_cols(const float2* __restrict__ in,
                                                   float2* __restrict__ out, int nh, int S,
                                                   int rs, const int32_t* __restrict__ imap,
                                                   const int32_t* __restrict__ omap, int sfast,
-                                                  int nin, int nout) {
+                                                  int nin, int istride, int nout, int ostride) {
   constexpr int N1 = Split<N>::N1, N2 = Split<N>::N2;
   constexpr int SB = ColSB<N>::value;
   constexpr int PAD = N + 1;   // LDS stride per slice (complex)
@@ -76,8 +79,10 @@ __global__ __launch_bounds__(256) void k_fft_cols(const float2* __restrict__ in,
   const bool live = sg < S;
   load_twiddles<N, DIR>(tw, tid, NT);
   for (int y = tid; y < N; y += NT) {
-    rin[y] = imap ? imap[y * nh + m] : y * nh + m;
-    rout[y] = omap ? omap[y * nh + m] : y * nh + m;
+    const bool iv = imap || (y % istride == 0 && y / istride < nin);
+    const bool ov = omap || (y % ostride == 0 && y / ostride < nout);
+    rin[y] = !iv ? -1 : imap ? imap[y * nh + m] : (y / istride) * nh + m;
+    rout[y] = !ov ? -1 : omap ? omap[y * nh + m] : (y / ostride) * nh + m;
   }
   __syncthreads();
   if (t < N2) {
@@ -85,7 +90,7 @@ __global__ __launch_bounds__(256) void k_fft_cols(const float2* __restrict__ in,
 #pragma unroll
     for (int n1 = 0; n1 < N1; ++n1) {
       const int y = t + N2 * n1;
-      v[n1] = (live && y < nin) ? in[(size_t)rin[y] * rs + sg] : make_float2(0.f, 0.f);
+      v[n1] = (live && rin[y] >= 0) ? in[(size_t)rin[y] * rs + sg] : make_float2(0.f, 0.f);
     }
     dft<N1, DIR>(v);
 #pragma unroll
@@ -100,21 +105,22 @@ __global__ __launch_bounds__(256) void k_fft_cols(const float2* __restrict__ in,
 #pragma unroll
     for (int k2 = 0; k2 < N2; ++k2) {
       const int p = t + N1 * k2;
-      if (p < nout) out[(size_t)rout[p] * rs + sg] = v[k2];
+      if (rout[p] >= 0) out[(size_t)rout[p] * rs + sg] = v[k2];
     }
   }
 }
 
 // ---------------------------------------------------------- rows, r2c (x)
-// T[(j*nh + m)*rs + s] = sum_{i < nxd} exp(-2 pi i m i / N) f[s][j][i],  m = 0..N/2,
-// for the ny_d rows j of slices f[s][ny_d][nxd] (zero-padded to N along x)
+// T[(j*nh + m)*rs + s] = sum_{i < nxc} exp(-2 pi i m sx i / N) f[s][j][i],  m = 0..N/2,
+// for the ny rows j of slices f[s][ny][nxc]: sample i sits at transform
+// column sx*i, every other column of the length-N row is zero
 // The 2Q rows of a block are read with 16-byte loads into LDS, packed in
 // pairs as z = f[2q] + i f[2q+1]; after the transform the two real spectra are
 // separated and written slice-fastest (contiguous across threads).
 template <int N, int Q>  // Q packed complex sequences = 2Q real slices per block
 __global__ __launch_bounds__(256) void k_fft_rows_r2c(const float* __restrict__ f,
                                                       float2* __restrict__ T, int ny, int nxd,
-                                                      int S, int rs) {
+                                                      int sx, int S, int rs) {
   constexpr int N1 = Split<N>::N1, N2 = Split<N>::N2;
   constexpr int PAD = N + 1;
   constexpr int NT = Q * N1;
@@ -138,16 +144,29 @@ __global__ __launch_bounds__(256) void k_fft_rows_r2c(const float* __restrict__ 
     if (u < 2 * Q * (N / 4) && s < S && 4 * c4 < nxd)
       ld[it] = reinterpret_cast<const float4*>(f + ((size_t)s * ny + j) * nxd)[c4];
   }
+  if (sx > 1) {  // samples land sx columns apart: clear the row buffers first
+    for (int e = tid; e < Q * PAD; e += NT) ex[e] = make_float2(0.f, 0.f);
+    __syncthreads();
+  }
 #pragma unroll
   for (int it = 0; it < LIT; ++it) {
     const int u = tid + it * NT;
     if (u >= 2 * Q * (N / 4)) break;
     const int row = u / (N / 4), c4 = u % (N / 4);
-    float* z = reinterpret_cast<float*>(ex + (row >> 1) * PAD + 4 * c4) + (row & 1);
-    z[0] = ld[it].x;
-    z[2] = ld[it].y;
-    z[4] = ld[it].z;
-    z[6] = ld[it].w;
+    if (sx == 1) {
+      float* z = reinterpret_cast<float*>(ex + (row >> 1) * PAD + 4 * c4) + (row & 1);
+      z[0] = ld[it].x;
+      z[2] = ld[it].y;
+      z[4] = ld[it].z;
+      z[6] = ld[it].w;
+    } else if (4 * c4 < nxd) {
+      float* z = reinterpret_cast<float*>(ex + (row >> 1) * PAD) + (row & 1);
+      const int i0 = 4 * c4 * sx;
+      z[2 * i0] = ld[it].x;
+      z[2 * (i0 + sx)] = ld[it].y;
+      z[2 * (i0 + 2 * sx)] = ld[it].z;
+      z[2 * (i0 + 3 * sx)] = ld[it].w;
+    }
   }
   __syncthreads();
   float2 v[N1];
@@ -192,11 +211,12 @@ __global__ __launch_bounds__(256) void k_fft_rows_r2c(const float* __restrict__ 
 // ---------------------------------------------------------- rows, c2r (x)
 // f[s][j][i] = scale * sum_{m=0}^{N-1} exp(+2 pi i m i / N) F[m] - sub[s][j][i],
 // F Hermitian-extended from m = 0..N/2 (imaginary parts of m = 0, N/2 dropped),
-// for i < nxd (slices f[s][ny][nxd]; the rest of the period is not stored)
+// stored for the samples i = 0..nxc-1 at transform columns sx*i (slices
+// f[s][ny][nxc]; the rest of the period is not stored)
 template <int N, int Q>
 __global__ __launch_bounds__(256) void k_fft_rows_c2r(const float2* __restrict__ T,
                                                       float* __restrict__ f, int ny, int nxd,
-                                                      int S, int rs, float scale,
+                                                      int sx, int S, int rs, float scale,
                                                       const float* __restrict__ sub) {
   constexpr int N1 = Split<N>::N1, N2 = Split<N>::N2;
   constexpr int PAD = N + 1;
@@ -288,7 +308,13 @@ __global__ __launch_bounds__(256) void k_fft_rows_c2r(const float2* __restrict__
     const int row = u / (N / 4), c4 = u % (N / 4);
     const int s = s0 + row;
     if (u >= 2 * Q * (N / 4) || s >= S || 4 * c4 >= nxd) continue;
-    const float4 r = *reinterpret_cast<const float4*>(rows + row * (N + 4) + 4 * c4);
+    float4 r;
+    if (sx == 1) {
+      r = *reinterpret_cast<const float4*>(rows + row * (N + 4) + 4 * c4);
+    } else {
+      const float* rr = rows + row * (N + 4) + 4 * c4 * sx;
+      r = make_float4(rr[0], rr[sx], rr[2 * sx], rr[3 * sx]);
+    }
     float4 v = make_float4(r.x * scale, r.y * scale, r.z * scale, r.w * scale);
     if (sub) {
       v.x -= sb4[it].x;
@@ -303,43 +329,47 @@ __global__ __launch_bounds__(256) void k_fft_rows_c2r(const float2* __restrict__
 // ------------------------------------------------------------- launchers
 template <int N, int DIR>
 static void launch_cols(const float2* in, float2* out, int nh, int S, int rs, const int32_t* imap,
-                        const int32_t* omap, int nin, int nout, hipStream_t st) {
+                        const int32_t* omap, int nin, int istride, int nout, int ostride,
+                        hipStream_t st) {
   constexpr int SB = ColSB<N>::value;
   const int sfast = S >= 2048;
   const int nsb = (S + SB - 1) / SB;
   dim3 grid = sfast ? dim3(nsb, nh) : dim3(nh, nsb);
   k_fft_cols<N, DIR><<<grid, SB * Split<N>::N1, 0, st>>>(in, out, nh, S, rs, imap, omap, sfast,
-                                                         nin, nout);
+                                                         nin, istride, nout, ostride);
 }
 
 template <int DIR>
 static pat_status cols(const float2* in, float2* out, int fy, int nh, int S, int rs,
-                       const int32_t* imap, const int32_t* omap, int nin, int nout,
-                       hipStream_t st) {
+                       const int32_t* imap, const int32_t* omap, int nin, int istride, int nout,
+                       int ostride, hipStream_t st) {
+#define PAT_COLS(N) launch_cols<N, DIR>(in, out, nh, S, rs, imap, omap, nin, istride, nout, ostride, st)
   switch (fy) {
-    case 16: launch_cols<16, DIR>(in, out, nh, S, rs, imap, omap, nin, nout, st); break;
-    case 32: launch_cols<32, DIR>(in, out, nh, S, rs, imap, omap, nin, nout, st); break;
-    case 64: launch_cols<64, DIR>(in, out, nh, S, rs, imap, omap, nin, nout, st); break;
-    case 128: launch_cols<128, DIR>(in, out, nh, S, rs, imap, omap, nin, nout, st); break;
-    case 256: launch_cols<256, DIR>(in, out, nh, S, rs, imap, omap, nin, nout, st); break;
-    case 512: launch_cols<512, DIR>(in, out, nh, S, rs, imap, omap, nin, nout, st); break;
+    case 16: PAT_COLS(16); break;
+    case 32: PAT_COLS(32); break;
+    case 64: PAT_COLS(64); break;
+    case 128: PAT_COLS(128); break;
+    case 256: PAT_COLS(256); break;
+    case 512: PAT_COLS(512); break;
     default: return fail(PAT_EUNSUPPORTED, "transform size along y must be a power of two in [16, 512]");
   }
+#undef PAT_COLS
   PAT_LAUNCHED("fft columns");
   return PAT_OK;
 }
 
 template <int N, int Q>
-static void rows_r2c(const float* f, float2* T, int nyd, int nxd, int S, int rs, hipStream_t st) {
-  dim3 grid(nyd, (S + 2 * Q - 1) / (2 * Q));
-  k_fft_rows_r2c<N, Q><<<grid, Q * Split<N>::N1, 0, st>>>(f, T, nyd, nxd, S, rs);
+static void rows_r2c(const float* f, float2* T, int nyc, int nxc, int sx, int S, int rs,
+                     hipStream_t st) {
+  dim3 grid(nyc, (S + 2 * Q - 1) / (2 * Q));
+  k_fft_rows_r2c<N, Q><<<grid, Q * Split<N>::N1, 0, st>>>(f, T, nyc, nxc, sx, S, rs);
 }
 
 template <int N, int Q>
-static void rows_c2r(const float2* T, float* f, int nyd, int nxd, int S, int rs, float scale,
+static void rows_c2r(const float2* T, float* f, int nyc, int nxc, int sx, int S, int rs, float scale,
                      const float* sub, hipStream_t st) {
-  dim3 grid(nyd, (S + 2 * Q - 1) / (2 * Q));
-  k_fft_rows_c2r<N, Q><<<grid, Q * Split<N>::N1, 0, st>>>(T, f, nyd, nxd, S, rs, scale, sub);
+  dim3 grid(nyc, (S + 2 * Q - 1) / (2 * Q));
+  k_fft_rows_c2r<N, Q><<<grid, Q * Split<N>::N1, 0, st>>>(T, f, nyc, nxc, sx, S, rs, scale, sub);
 }
 
 // 8 packed sequences (16 real slices) per row block: small enough for several
@@ -347,43 +377,50 @@ static void rows_c2r(const float2* T, float* f, int nyd, int nxd, int S, int rs,
 constexpr int kRowQ = 8;
 #define PAT_ROWS(fn, N, ...) (fn<N, kRowQ>(__VA_ARGS__))
 
-static bool extents_ok(int fx, int fy, int nxd, int nyd) {
-  return nxd >= 4 && nyd >= 1 && nxd <= fx && nyd <= fy && (nxd & 3) == 0;
+static bool extents_ok(int fx, int fy, int nxw, int nyw, int sx, int sy) {
+  if (sx < 1 || sy < 1 || nxw > fx || nyw > fy || nxw % sx || nyw % sy) return false;
+  const int nxc = nxw / sx, nyc = nyw / sy;
+  return nxc >= 4 && nyc >= 1 && (nxc & 3) == 0;
 }
 
-pat_status fft2_r2c(const float* f, float2* T, float2* X, int fx, int fy, int nxd, int nyd, int S,
-                    const int32_t* rowmap, hipStream_t st) {
+pat_status fft2_r2c(const float* f, float2* T, float2* X, int fx, int fy, int nxw, int nyw, int sx,
+                    int sy, int S, const int32_t* rowmap, hipStream_t st) {
   if (S <= 0) return PAT_OK;
-  if (!extents_ok(fx, fy, nxd, nyd)) return fail(PAT_EINVAL, "fft: data extent does not fit the transform");
+  if (!extents_ok(fx, fy, nxw, nyw, sx, sy))
+    return fail(PAT_EINVAL, "fft: data extent or sampling does not fit the transform");
   const int nh = fx / 2 + 1;
   const int rs = spec_stride(S);
+  const int nxc = nxw / sx, nyc = nyw / sy;
   switch (fx) {
-    case 16: PAT_ROWS(rows_r2c, 16, f, T, nyd, nxd, S, rs, st); break;
-    case 32: PAT_ROWS(rows_r2c, 32, f, T, nyd, nxd, S, rs, st); break;
-    case 64: PAT_ROWS(rows_r2c, 64, f, T, nyd, nxd, S, rs, st); break;
-    case 128: PAT_ROWS(rows_r2c, 128, f, T, nyd, nxd, S, rs, st); break;
-    case 256: PAT_ROWS(rows_r2c, 256, f, T, nyd, nxd, S, rs, st); break;
-    case 512: PAT_ROWS(rows_r2c, 512, f, T, nyd, nxd, S, rs, st); break;
+    case 16: PAT_ROWS(rows_r2c, 16, f, T, nyc, nxc, sx, S, rs, st); break;
+    case 32: PAT_ROWS(rows_r2c, 32, f, T, nyc, nxc, sx, S, rs, st); break;
+    case 64: PAT_ROWS(rows_r2c, 64, f, T, nyc, nxc, sx, S, rs, st); break;
+    case 128: PAT_ROWS(rows_r2c, 128, f, T, nyc, nxc, sx, S, rs, st); break;
+    case 256: PAT_ROWS(rows_r2c, 256, f, T, nyc, nxc, sx, S, rs, st); break;
+    case 512: PAT_ROWS(rows_r2c, 512, f, T, nyc, nxc, sx, S, rs, st); break;
     default: return fail(PAT_EUNSUPPORTED, "transform size along x must be a power of two in [16, 512]");
   }
   PAT_LAUNCHED("fft rows r2c");
-  return cols<-1>(T, X, fy, nh, S, rs, nullptr, rowmap, nyd, fy, st);
+  return cols<-1>(T, X, fy, nh, S, rs, nullptr, rowmap, nyc, sy, fy, 1, st);
 }
 
-pat_status fft2_c2r(const float2* X, float2* T, float* f, int fx, int fy, int nxd, int nyd, int S,
-                    float scale, const float* sub, const int32_t* rowmap, hipStream_t st) {
+pat_status fft2_c2r(const float2* X, float2* T, float* f, int fx, int fy, int nxw, int nyw, int sx,
+                    int sy, int S, float scale, const float* sub, const int32_t* rowmap,
+                    hipStream_t st) {
   if (S <= 0) return PAT_OK;
-  if (!extents_ok(fx, fy, nxd, nyd)) return fail(PAT_EINVAL, "fft: data extent does not fit the transform");
+  if (!extents_ok(fx, fy, nxw, nyw, sx, sy))
+    return fail(PAT_EINVAL, "fft: data extent or sampling does not fit the transform");
   const int nh = fx / 2 + 1;
   const int rs = spec_stride(S);
-  PAT_TRY(cols<+1>(X, T, fy, nh, S, rs, rowmap, nullptr, fy, nyd, st));
+  const int nxc = nxw / sx, nyc = nyw / sy;
+  PAT_TRY(cols<+1>(X, T, fy, nh, S, rs, rowmap, nullptr, fy, 1, nyc, sy, st));
   switch (fx) {
-    case 16: PAT_ROWS(rows_c2r, 16, T, f, nyd, nxd, S, rs, scale, sub, st); break;
-    case 32: PAT_ROWS(rows_c2r, 32, T, f, nyd, nxd, S, rs, scale, sub, st); break;
-    case 64: PAT_ROWS(rows_c2r, 64, T, f, nyd, nxd, S, rs, scale, sub, st); break;
-    case 128: PAT_ROWS(rows_c2r, 128, T, f, nyd, nxd, S, rs, scale, sub, st); break;
-    case 256: PAT_ROWS(rows_c2r, 256, T, f, nyd, nxd, S, rs, scale, sub, st); break;
-    case 512: PAT_ROWS(rows_c2r, 512, T, f, nyd, nxd, S, rs, scale, sub, st); break;
+    case 16: PAT_ROWS(rows_c2r, 16, T, f, nyc, nxc, sx, S, rs, scale, sub, st); break;
+    case 32: PAT_ROWS(rows_c2r, 32, T, f, nyc, nxc, sx, S, rs, scale, sub, st); break;
+    case 64: PAT_ROWS(rows_c2r, 64, T, f, nyc, nxc, sx, S, rs, scale, sub, st); break;
+    case 128: PAT_ROWS(rows_c2r, 128, T, f, nyc, nxc, sx, S, rs, scale, sub, st); break;
+    case 256: PAT_ROWS(rows_c2r, 256, T, f, nyc, nxc, sx, S, rs, scale, sub, st); break;
+    case 512: PAT_ROWS(rows_c2r, 512, T, f, nyc, nxc, sx, S, rs, scale, sub, st); break;
     default: return fail(PAT_EUNSUPPORTED, "transform size along x must be a power of two in [16, 512]");
   }
   PAT_LAUNCHED("fft rows c2r");

@@ -19,6 +19,7 @@ struct pat_op {
   pat_geometry g;
   int nq;
   int fx, fy;   // transform grid (2 nx x 2 ny for the linear boundary)
+  int sx, sy;   // scan-grid sampling of the data (1: every grid point)
   int nh, nk;   // half-spectrum columns fx/2+1 and frequencies fy*nh
   int G;        // member slots per work item (8: radial, 4: octant, 2: quadrant fold)
   int nclass;   // stored slabs
@@ -72,6 +73,11 @@ static int default_nq(const pat_geometry& g) {
   return nq;
 }
 
+// scan-grid sampling steps (0 in a zero-initialised geometry means 1)
+static int scan_sx(const pat_geometry& g) { return g.sx > 1 ? g.sx : 1; }
+static int scan_sy(const pat_geometry& g) { return g.sy > 1 ? g.sy : 1; }
+static bool sampled(const pat_geometry& g) { return scan_sx(g) > 1 || scan_sy(g) > 1; }
+
 // the periodic grid the transforms and the library live on
 static pat_geometry transform_geometry(const pat_geometry& g) {
   pat_geometry t = g;
@@ -97,6 +103,9 @@ static pat_status check_geometry(const pat_geometry* g) {
     return fail(PAT_EUNSUPPORTED, "linear: nx and ny must be powers of two in [8, 256]");
   if (g->nz > 2048 || g->nt > 2048) return fail(PAT_EUNSUPPORTED, "nz and nt must be <= 2048");
   if (g->n_ir < 0 || g->n_ir > kMaxIr) return fail(PAT_EUNSUPPORTED, "n_ir must be in [0, 64]");
+  if (g->sx < 0 || g->sy < 0) return fail(PAT_EINVAL, "sx and sy must be >= 0");
+  if (g->nx % scan_sx(*g) || g->ny % scan_sy(*g) || (g->nx / scan_sx(*g)) % 4)
+    return fail(PAT_EUNSUPPORTED, "sx must divide nx with nx/sx a multiple of 4, and sy must divide ny");
   if (g->n_ir > 0) {
     if (!g->ir) return fail(PAT_EINVAL, "ir is null while n_ir > 0");
     for (int j = 0; j < g->n_ir; ++j)
@@ -237,9 +246,10 @@ static HLayout h_layout(const pat_geometry& g, const Classes& C) {
   L.off_amax = o;    o = align_up(o + (size_t)g.nz * 8, 256);
   L.off_ir = o;      o = align_up(o + (size_t)g.n_ir * 8, 256);
   L.sG_row = (int)align_up((size_t)g.nz, 4);
-  // Gram blocks serve the normal-operator gradient, which only the periodic
-  // boundary has (see pat_recon_fista)
-  L.bytes_G = g.boundary == PAT_BOUNDARY_PERIODIC ? (size_t)L.nclass * g.nz * L.sG_row * 4 : 0;
+  // Gram blocks serve the normal-operator gradient, which only the periodic,
+  // unsampled operator has (see pat_recon_fista)
+  L.bytes_G = (g.boundary == PAT_BOUNDARY_PERIODIC && !sampled(g))
+                  ? (size_t)L.nclass * g.nz * L.sG_row * 4 : 0;
   L.off_Ar = o;      o = align_up(o + L.bytes_Ar, 256);
   L.off_Tr = o;      o = align_up(o + L.bytes_Tr, 256);
   L.off_A = o;       o = align_up(o + L.bytes_A, 256);
@@ -405,18 +415,18 @@ static pat_status run_gram(pat_op* op, const float2* in, float2* out, const floa
 static pat_status run_A(pat_op* op, const float* x, float* y, int B, const float* sub, const Work& w,
                         hipStream_t st) {
   const pat_geometry& g = op->g;
-  PAT_TRY(fft2_r2c(x, w.T, w.Xs, op->fx, op->fy, g.nx, g.ny, B * g.nz, op->rowmap, st));
+  PAT_TRY(fft2_r2c(x, w.T, w.Xs, op->fx, op->fy, g.nx, g.ny, 1, 1, B * g.nz, op->rowmap, st));
   PAT_TRY(run_contract(op, false, w.Xs, w.Ds, B, st));
-  return fft2_c2r(w.Ds, w.T, y, op->fx, op->fy, g.nx, g.ny, B * g.nt, inv_area(op), sub,
+  return fft2_c2r(w.Ds, w.T, y, op->fx, op->fy, g.nx, g.ny, op->sx, op->sy, B * g.nt, inv_area(op), sub,
                   op->rowmap, st);
 }
 
 // x = A^T y, B data sets
 static pat_status run_AT(pat_op* op, const float* y, float* x, int B, const Work& w, hipStream_t st) {
   const pat_geometry& g = op->g;
-  PAT_TRY(fft2_r2c(y, w.T, w.Ds, op->fx, op->fy, g.nx, g.ny, B * g.nt, op->rowmap, st));
+  PAT_TRY(fft2_r2c(y, w.T, w.Ds, op->fx, op->fy, g.nx, g.ny, op->sx, op->sy, B * g.nt, op->rowmap, st));
   PAT_TRY(run_contract(op, true, w.Ds, w.Xs, B, st));
-  return fft2_c2r(w.Xs, w.T, x, op->fx, op->fy, g.nx, g.ny, B * g.nz, inv_area(op), nullptr,
+  return fft2_c2r(w.Xs, w.T, x, op->fx, op->fy, g.nx, g.ny, 1, 1, B * g.nz, inv_area(op), nullptr,
                   op->rowmap, st);
 }
 
@@ -500,6 +510,8 @@ pat_status pat_H_build(pat_ctx* ctx, const pat_geometry* geom, void* h_buf, size
   op->g.nz_sim = op->nq;
   op->fx = tg.nx;
   op->fy = tg.ny;
+  op->sx = scan_sx(*geom);
+  op->sy = scan_sy(*geom);
   op->nh = op->fx / 2 + 1;
   op->nk = op->fy * op->nh;
   op->G = L.G;
@@ -693,7 +705,7 @@ pat_status pat_spectrum(pat_op* op, const float* f, float* spec, int32_t S, void
   PAT_TRY(check_stage(op, S, ws, ws_bytes, &w));
   PAT_TRY(check_ptr(f, "f"));
   PAT_TRY(check_ptr(spec, "spec"));
-  return fft2_r2c(f, w.T, (float2*)spec, op->fx, op->fy, op->g.nx, op->g.ny, S, op->rowmap,
+  return fft2_r2c(f, w.T, (float2*)spec, op->fx, op->fy, op->g.nx, op->g.ny, 1, 1, S, op->rowmap,
                   (hipStream_t)stream);
 }
 
@@ -704,7 +716,7 @@ pat_status pat_inverse_spectrum(pat_op* op, const float* spec, float* f, int32_t
   PAT_TRY(check_ptr(f, "f"));
   PAT_TRY(check_ptr(spec, "spec"));
   if (sub) PAT_TRY(check_ptr(sub, "sub"));
-  return fft2_c2r((const float2*)spec, w.T, f, op->fx, op->fy, op->g.nx, op->g.ny, S,
+  return fft2_c2r((const float2*)spec, w.T, f, op->fx, op->fy, op->g.nx, op->g.ny, 1, 1, S,
                   inv_area(op), sub, op->rowmap, (hipStream_t)stream);
 }
 
@@ -759,19 +771,20 @@ pat_status pat_recon_fista(pat_op* op, const float* d, float* x, int32_t niter, 
   hipStream_t st = (hipStream_t)stream;
   const pat_geometry& g = op->g;
   const long long n = (long long)g.nz * g.nx * g.ny;
-  const long long nd = (long long)g.nt * g.nx * g.ny;
+  const long long nd = (long long)g.nt * (g.nx / op->sx) * (g.ny / op->sy);
   const float inv = inv_area(op);
   // The periodic operator is block diagonal in the transverse frequency, so
   // A^T A is too and the gradient is formed per frequency with the Gram
-  // blocks.  The linear boundary crops the data between A and A^T, which
-  // couples frequencies: its gradient is taken explicitly, A then A^T.
+  // blocks.  The linear boundary (crop) and the scan-grid sampling act on
+  // the data between A and A^T and couple frequencies: their gradient is
+  // taken explicitly, A then A^T.
   const bool normal = op->gram != nullptr;
   if (normal) {
     // b^ = spectrum of A^T d (the adjoint up to its inverse transform), once
-    PAT_TRY(fft2_r2c(d, w.T, w.Ds, op->fx, op->fy, g.nx, g.ny, g.nt, op->rowmap, st));
+    PAT_TRY(fft2_r2c(d, w.T, w.Ds, op->fx, op->fy, g.nx, g.ny, op->sx, op->sy, g.nt, op->rowmap, st));
     PAT_TRY(run_contract(op, true, w.Ds, w.Bs, 1, st));
     if (trace) {
-      PAT_TRY(fft2_c2r(w.Bs, w.T, w.V, op->fx, op->fy, g.nx, g.ny, g.nz, inv, nullptr, op->rowmap, st));  // b = A^T d
+      PAT_TRY(fft2_c2r(w.Bs, w.T, w.V, op->fx, op->fy, g.nx, g.ny, 1, 1, g.nz, inv, nullptr, op->rowmap, st));  // b = A^T d
       PAT_TRY(dot_f64(d, d, nd, w.part64, w.s64 + 2, st));
     }
   } else if (trace) {
@@ -785,9 +798,9 @@ pat_status pat_recon_fista(pat_op* op, const float* d, float* x, int32_t niter, 
   for (int k = 1; k <= niter; ++k) {
     if (normal) {
       // gradient A^T (A z - d) = A^T A z - A^T d, per frequency: G z^ - b^
-      PAT_TRY(fft2_r2c(w.Z, w.T, w.Xs, op->fx, op->fy, g.nx, g.ny, g.nz, op->rowmap, st));
+      PAT_TRY(fft2_r2c(w.Z, w.T, w.Xs, op->fx, op->fy, g.nx, g.ny, 1, 1, g.nz, op->rowmap, st));
       PAT_TRY(run_gram(op, w.Xs, w.Gs, w.Bs, 1, st));
-      PAT_TRY(fft2_c2r(w.Gs, w.T, w.U, op->fx, op->fy, g.nx, g.ny, g.nz, inv, nullptr, op->rowmap, st));
+      PAT_TRY(fft2_c2r(w.Gs, w.T, w.U, op->fx, op->fy, g.nx, g.ny, 1, 1, g.nz, inv, nullptr, op->rowmap, st));
       if (trace) {
         // 1/2 ||A z - d||^2 = 1/2 (<z, g> - <z, b> + ||d||^2), float64 sums
         PAT_TRY(dot_f64(w.Z, w.U, n, w.part64, w.s64 + 0, st));
@@ -871,9 +884,9 @@ pat_status pat_fista_step_normal(pat_op* op, int32_t B, const float* atd, float*
     p.o[b].beta = (float)beta[b];
     p.o[b].nonneg = nonneg[b] ? 1 : 0;
   }
-  PAT_TRY(fft2_r2c(z, w.T, w.Xs, op->fx, op->fy, g.nx, g.ny, B * g.nz, op->rowmap, st));
+  PAT_TRY(fft2_r2c(z, w.T, w.Xs, op->fx, op->fy, g.nx, g.ny, 1, 1, B * g.nz, op->rowmap, st));
   PAT_TRY(run_gram(op, w.Xs, w.Gs, nullptr, B, st));
-  PAT_TRY(fft2_c2r(w.Gs, w.T, w.U, op->fx, op->fy, g.nx, g.ny, B * g.nz, inv_area(op), atd,
+  PAT_TRY(fft2_c2r(w.Gs, w.T, w.U, op->fx, op->fy, g.nx, g.ny, 1, 1, B * g.nz, inv_area(op), atd,
                    op->rowmap, st));  // U = A^T A z - A^T d
   return fista_update(x, z, w.U, n, B, p, nonfinite, st);
 }
@@ -888,7 +901,7 @@ pat_status pat_adjoint_check(pat_op* op, const float* x, const float* y, double*
   hipStream_t st = (hipStream_t)stream;
   const pat_geometry& g = op->g;
   const long long n = (long long)g.nz * g.nx * g.ny;
-  const long long nd = (long long)g.nt * g.nx * g.ny;
+  const long long nd = (long long)g.nt * (g.nx / op->sx) * (g.ny / op->sy);
   PAT_TRY(run_A(op, x, w.R, 1, nullptr, w, st));
   PAT_TRY(run_AT(op, y, w.U, 1, w, st));
   PAT_TRY(dot_f64(w.R, y, nd, w.part64, w.s64 + 0, st));

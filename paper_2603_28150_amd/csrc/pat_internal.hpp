@@ -37,21 +37,23 @@ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 inline int spec_stride(int S) { return (S + 63) / 64 * 64 + 32; }
 
 // Slice layouts (S slices, element type float / float2, rs = spec_stride(S)):
-//   real slices      f[s][nyd][nxd]
+//   real slices      f[s][nyw/sy][nxw/sx]
 //   half spectrum    X[row(p*nh + m) * rs + s] (frequency rows, slice fastest;
 //                    nh = nx/2 + 1; row() is the class-major row map, or the
 //                    identity when rowmap is null)
 //   row-transformed  T[(j*nh + m) * rs + s]   (y not yet transformed)
 // Forward transforms are unnormalised; the inverse multiplies by `scale`.
 pat_status fft_init_device();  // uploads the twiddle table to the current device
-// f holds S slices of nxd x nyd (the data extent); the transforms are taken
-// on the fx x fy grid (nxd <= fx, nyd <= fy, powers of two up to 512):
-// zero-padding on the way in, cropping on the way out.
-pat_status fft2_r2c(const float* f, float2* T, float2* X, int fx, int fy, int nxd, int nyd, int S,
-                    const int32_t* rowmap, hipStream_t st);
+// f holds S slices covering the nxw x nyw window of the fx x fy transform
+// grid (powers of two up to 512), sampled every sx columns and sy rows:
+// f[s][nyw/sy][nxw/sx].  Zero-padding and zero-filling on the way in,
+// cropping and sampling on the way out.
+pat_status fft2_r2c(const float* f, float2* T, float2* X, int fx, int fy, int nxw, int nyw, int sx,
+                    int sy, int S, const int32_t* rowmap, hipStream_t st);
 // f = scale * c2r(X) - sub (sub may be null; same layout as f)
-pat_status fft2_c2r(const float2* X, float2* T, float* f, int fx, int fy, int nxd, int nyd, int S,
-                    float scale, const float* sub, const int32_t* rowmap, hipStream_t st);
+pat_status fft2_c2r(const float2* X, float2* T, float* f, int fx, int fy, int nxw, int nyw, int sx,
+                    int sy, int S, float scale, const float* sub, const int32_t* rowmap,
+                    hipStream_t st);
 
 // ------------------------------------------------------ contraction (VALU)
 // out[t*G+g][obj*nj + j] = sum_i slab_s[i][j] * in[t*G+g][obj*ni + i] (* scales)

@@ -28,18 +28,20 @@ class Geometry:
     nz_sim: int = 0
     boundary: str = "periodic"     # "periodic" or "linear" (zero-padded, Sec. 2.3)
     ir: tuple = ()                 # sensor response taps (causal FIR along t), () = ideal
+    sx: int = 1                    # scan grid: data at every sx-th column ...
+    sy: int = 1                    # ... and sy-th row of the sensor grid
 
     @staticmethod
     def paper_like(nx, ny, nz, nt, dx=100e-6, c=1500.0, cfl=0.3, nz_sim=0,
-                   boundary="periodic", ir=()) -> "Geometry":
+                   boundary="periodic", ir=(), sx=1, sy=1) -> "Geometry":
         """dx = dy = dz, dt = cfl * dx / c (the physics of the synthetic workloads)."""
         return Geometry(nx, ny, nz, nt, dx, dx, dx, cfl * dx / c, c, nz_sim, boundary,
-                        tuple(float(v) for v in ir))
+                        tuple(float(v) for v in ir), sx, sy)
 
     def to_c(self, h_dtype: str) -> _lib.Geometry:
         g = _lib.Geometry(self.nx, self.ny, self.nz, self.nt, self.dx, self.dy, self.dz,
                           self.dt, self.c, self.nz_sim, _lib.HDTYPES[h_dtype],
-                          _lib.BOUNDARIES[self.boundary], len(self.ir))
+                          _lib.BOUNDARIES[self.boundary], len(self.ir), None, self.sx, self.sy)
         if self.ir:
             g.ir = (C.c_double * len(self.ir))(*self.ir)   # kept alive by the struct
         return g
@@ -115,7 +117,7 @@ class Operator:
 
     @property
     def d_shape(self):
-        return (self.geom.nt, self.geom.ny, self.geom.nx)
+        return (self.geom.nt, self.geom.ny // self.geom.sy, self.geom.nx // self.geom.sx)
 
     @property
     def nk(self) -> int:

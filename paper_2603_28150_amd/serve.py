@@ -113,7 +113,7 @@ class HipBackend:
         g = op.geom
         if self.uses_normal(op):
             return 4 * g.nx * g.ny * 3 * g.nz + 4
-        return 4 * g.nx * g.ny * (2 * g.nz + g.nt) + 4
+        return 4 * (2 * g.nz * g.ny * g.nx + g.nt * (g.ny // g.sy) * (g.nx // g.sx)) + 4
 
     def workspace_bytes(self, op, cap) -> int:
         return op.workspace_bytes(cap)
