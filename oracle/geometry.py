@@ -74,6 +74,21 @@ def doubled(g: Geometry) -> Geometry:
     return replace(g, nx=2 * g.nx, ny=2 * g.ny, nz_sim=g.nq)
 
 
+def linear_grid(g: Geometry) -> Geometry:
+    """The periodic grid of the zero-padded linear convolution of an Nx x Ny
+    window: along each axis the smallest power of two >= max(16, 2N), so no
+    source-sensor offset inside the window wraps (equals ``doubled`` when N is
+    a power of two >= 8)."""
+    from dataclasses import replace
+
+    def size(n):
+        p = 16
+        while p < 2 * n:
+            p *= 2
+        return p
+    return replace(g, nx=size(g.nx), ny=size(g.ny), nz_sim=g.nq)
+
+
 def time_axis(g: Geometry) -> np.ndarray:
     return np.arange(g.nt, dtype=np.float64) * g.dt
 

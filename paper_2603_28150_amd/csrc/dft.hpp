@@ -134,5 +134,6 @@ template <> struct Split<64> { static constexpr int N1 = 8, N2 = 8; };
 template <> struct Split<128> { static constexpr int N1 = 16, N2 = 8; };
 template <> struct Split<256> { static constexpr int N1 = 16, N2 = 16; };
 template <> struct Split<512> { static constexpr int N1 = 32, N2 = 16; };
+template <> struct Split<1024> { static constexpr int N1 = 32, N2 = 32; };
 
 }  // namespace pat

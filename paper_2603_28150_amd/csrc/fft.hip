@@ -26,7 +26,7 @@
 
 namespace pat {
 
-constexpr int kTwN = 512;  // largest transform size
+constexpr int kTwN = 1024;  // largest transform size
 __device__ float2 g_tw[kTwN];
 
 pat_status fft_init_device() {
@@ -55,7 +55,7 @@ __device__ __forceinline__ void load_twiddles(float2* tw, int tid, int nthreads)
 // only rows j = istride*j' with j' < nin are present (the others are zeros),
 // at row j'*nh + m, and only rows p = ostride*p' with p' < nout are written,
 // at row p'*nh + m.
-template <int N> struct ColSB { static constexpr int value = N <= 256 ? 16 : 8; };  // slices per block
+template <int N> struct ColSB { static constexpr int value = N <= 256 ? 16 : N == 512 ? 8 : 4; };  // slices per block
 
 template <int N, int DIR>
 __global__ __launch_bounds__(256) void k_fft_cols(const float2* __restrict__ in,
@@ -141,8 +141,18 @@ __global__ __launch_bounds__(256) void k_fft_rows_r2c(const float* __restrict__ 
     const int row = u / (N / 4), c4 = u % (N / 4);
     const int s = s0 + row;
     ld[it] = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (u < 2 * Q * (N / 4) && s < S && 4 * c4 < nxd)
-      ld[it] = reinterpret_cast<const float4*>(f + ((size_t)s * ny + j) * nxd)[c4];
+    if (u < 2 * Q * (N / 4) && s < S && 4 * c4 < nxd) {
+      const float* src = f + ((size_t)s * ny + j) * nxd;
+      if ((nxd & 3) == 0) {
+        ld[it] = reinterpret_cast<const float4*>(src)[c4];
+      } else {  // rows not 16-byte aligned: element loads, zeros past the row
+        const int i0 = 4 * c4;
+        ld[it].x = src[i0];
+        if (i0 + 1 < nxd) ld[it].y = src[i0 + 1];
+        if (i0 + 2 < nxd) ld[it].z = src[i0 + 2];
+        if (i0 + 3 < nxd) ld[it].w = src[i0 + 3];
+      }
+    }
   }
   if (sx > 1) {  // samples land sx columns apart: clear the row buffers first
     for (int e = tid; e < Q * PAD; e += NT) ex[e] = make_float2(0.f, 0.f);
@@ -163,9 +173,9 @@ __global__ __launch_bounds__(256) void k_fft_rows_r2c(const float* __restrict__ 
       float* z = reinterpret_cast<float*>(ex + (row >> 1) * PAD) + (row & 1);
       const int i0 = 4 * c4 * sx;
       z[2 * i0] = ld[it].x;
-      z[2 * (i0 + sx)] = ld[it].y;
-      z[2 * (i0 + 2 * sx)] = ld[it].z;
-      z[2 * (i0 + 3 * sx)] = ld[it].w;
+      if (4 * c4 + 1 < nxd) z[2 * (i0 + sx)] = ld[it].y;
+      if (4 * c4 + 2 < nxd) z[2 * (i0 + 2 * sx)] = ld[it].z;
+      if (4 * c4 + 3 < nxd) z[2 * (i0 + 3 * sx)] = ld[it].w;
     }
   }
   __syncthreads();
@@ -298,8 +308,18 @@ __global__ __launch_bounds__(256) void k_fft_rows_c2r(const float2* __restrict__
       const int row = u / (N / 4), c4 = u % (N / 4);
       const int s = s0 + row;
       sb4[it] = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (u < 2 * Q * (N / 4) && s < S && 4 * c4 < nxd)
-        sb4[it] = reinterpret_cast<const float4*>(sub + ((size_t)s * ny + j) * nxd)[c4];
+      if (u < 2 * Q * (N / 4) && s < S && 4 * c4 < nxd) {
+        const float* src = sub + ((size_t)s * ny + j) * nxd;
+        if ((nxd & 3) == 0) {
+          sb4[it] = reinterpret_cast<const float4*>(src)[c4];
+        } else {
+          const int i0 = 4 * c4;
+          sb4[it].x = src[i0];
+          if (i0 + 1 < nxd) sb4[it].y = src[i0 + 1];
+          if (i0 + 2 < nxd) sb4[it].z = src[i0 + 2];
+          if (i0 + 3 < nxd) sb4[it].w = src[i0 + 3];
+        }
+      }
     }
   }
 #pragma unroll
@@ -309,11 +329,14 @@ __global__ __launch_bounds__(256) void k_fft_rows_c2r(const float2* __restrict__
     const int s = s0 + row;
     if (u >= 2 * Q * (N / 4) || s >= S || 4 * c4 >= nxd) continue;
     float4 r;
+    const int i0 = 4 * c4;
     if (sx == 1) {
-      r = *reinterpret_cast<const float4*>(rows + row * (N + 4) + 4 * c4);
+      r = *reinterpret_cast<const float4*>(rows + row * (N + 4) + i0);
     } else {
-      const float* rr = rows + row * (N + 4) + 4 * c4 * sx;
-      r = make_float4(rr[0], rr[sx], rr[2 * sx], rr[3 * sx]);
+      // samples past the row end read in-range LDS and are not stored
+      const float* rr = rows + row * (N + 4);
+      r = make_float4(rr[i0 * sx], rr[min(i0 + 1, nxd - 1) * sx], rr[min(i0 + 2, nxd - 1) * sx],
+                      rr[min(i0 + 3, nxd - 1) * sx]);
     }
     float4 v = make_float4(r.x * scale, r.y * scale, r.z * scale, r.w * scale);
     if (sub) {
@@ -322,7 +345,15 @@ __global__ __launch_bounds__(256) void k_fft_rows_c2r(const float2* __restrict__
       v.z -= sb4[it].z;
       v.w -= sb4[it].w;
     }
-    reinterpret_cast<float4*>(f + ((size_t)s * ny + j) * nxd)[c4] = v;
+    float* dst = f + ((size_t)s * ny + j) * nxd;
+    if ((nxd & 3) == 0) {
+      reinterpret_cast<float4*>(dst)[c4] = v;
+    } else {
+      dst[i0] = v.x;
+      if (i0 + 1 < nxd) dst[i0 + 1] = v.y;
+      if (i0 + 2 < nxd) dst[i0 + 2] = v.z;
+      if (i0 + 3 < nxd) dst[i0 + 3] = v.w;
+    }
   }
 }
 
@@ -351,7 +382,8 @@ static pat_status cols(const float2* in, float2* out, int fy, int nh, int S, int
     case 128: PAT_COLS(128); break;
     case 256: PAT_COLS(256); break;
     case 512: PAT_COLS(512); break;
-    default: return fail(PAT_EUNSUPPORTED, "transform size along y must be a power of two in [16, 512]");
+    case 1024: PAT_COLS(1024); break;
+    default: return fail(PAT_EUNSUPPORTED, "transform size along y must be a power of two in [16, 1024]");
   }
 #undef PAT_COLS
   PAT_LAUNCHED("fft columns");
@@ -379,8 +411,7 @@ constexpr int kRowQ = 8;
 
 static bool extents_ok(int fx, int fy, int nxw, int nyw, int sx, int sy) {
   if (sx < 1 || sy < 1 || nxw > fx || nyw > fy || nxw % sx || nyw % sy) return false;
-  const int nxc = nxw / sx, nyc = nyw / sy;
-  return nxc >= 4 && nyc >= 1 && (nxc & 3) == 0;
+  return nxw / sx >= 1 && nyw / sy >= 1;
 }
 
 pat_status fft2_r2c(const float* f, float2* T, float2* X, int fx, int fy, int nxw, int nyw, int sx,
@@ -398,7 +429,8 @@ pat_status fft2_r2c(const float* f, float2* T, float2* X, int fx, int fy, int nx
     case 128: PAT_ROWS(rows_r2c, 128, f, T, nyc, nxc, sx, S, rs, st); break;
     case 256: PAT_ROWS(rows_r2c, 256, f, T, nyc, nxc, sx, S, rs, st); break;
     case 512: PAT_ROWS(rows_r2c, 512, f, T, nyc, nxc, sx, S, rs, st); break;
-    default: return fail(PAT_EUNSUPPORTED, "transform size along x must be a power of two in [16, 512]");
+    case 1024: PAT_ROWS(rows_r2c, 1024, f, T, nyc, nxc, sx, S, rs, st); break;
+    default: return fail(PAT_EUNSUPPORTED, "transform size along x must be a power of two in [16, 1024]");
   }
   PAT_LAUNCHED("fft rows r2c");
   return cols<-1>(T, X, fy, nh, S, rs, nullptr, rowmap, nyc, sy, fy, 1, st);
@@ -421,7 +453,8 @@ pat_status fft2_c2r(const float2* X, float2* T, float* f, int fx, int fy, int nx
     case 128: PAT_ROWS(rows_c2r, 128, T, f, nyc, nxc, sx, S, rs, scale, sub, st); break;
     case 256: PAT_ROWS(rows_c2r, 256, T, f, nyc, nxc, sx, S, rs, scale, sub, st); break;
     case 512: PAT_ROWS(rows_c2r, 512, T, f, nyc, nxc, sx, S, rs, scale, sub, st); break;
-    default: return fail(PAT_EUNSUPPORTED, "transform size along x must be a power of two in [16, 512]");
+    case 1024: PAT_ROWS(rows_c2r, 1024, T, f, nyc, nxc, sx, S, rs, scale, sub, st); break;
+    default: return fail(PAT_EUNSUPPORTED, "transform size along x must be a power of two in [16, 1024]");
   }
   PAT_LAUNCHED("fft rows c2r");
   return PAT_OK;

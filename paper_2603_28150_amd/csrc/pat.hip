@@ -78,12 +78,20 @@ static int scan_sx(const pat_geometry& g) { return g.sx > 1 ? g.sx : 1; }
 static int scan_sy(const pat_geometry& g) { return g.sy > 1 ? g.sy : 1; }
 static bool sampled(const pat_geometry& g) { return scan_sx(g) > 1 || scan_sy(g) > 1; }
 
+// linear boundary: the transform grid is the smallest power of two holding
+// twice the window (so that no offset inside the window wraps), at least 16
+static int linear_size(int n) {
+  int p = 16;
+  while (p < 2 * n) p <<= 1;
+  return p;
+}
+
 // the periodic grid the transforms and the library live on
 static pat_geometry transform_geometry(const pat_geometry& g) {
   pat_geometry t = g;
   if (g.boundary == PAT_BOUNDARY_LINEAR) {
-    t.nx = 2 * g.nx;
-    t.ny = 2 * g.ny;
+    t.nx = linear_size(g.nx);
+    t.ny = linear_size(g.ny);
   }
   return t;
 }
@@ -97,15 +105,15 @@ static pat_status check_geometry(const pat_geometry* g) {
   if (g->h_dtype < PAT_H_F32 || g->h_dtype > PAT_H_F16) return fail(PAT_EINVAL, "unknown h_dtype");
   if (g->boundary != PAT_BOUNDARY_PERIODIC && g->boundary != PAT_BOUNDARY_LINEAR)
     return fail(PAT_EINVAL, "unknown boundary");
-  if (g->boundary == PAT_BOUNDARY_PERIODIC && (!pow2_in(g->nx, 16, 512) || !pow2_in(g->ny, 16, 512)))
-    return fail(PAT_EUNSUPPORTED, "periodic: nx and ny must be powers of two in [16, 512]");
-  if (g->boundary == PAT_BOUNDARY_LINEAR && (!pow2_in(g->nx, 8, 256) || !pow2_in(g->ny, 8, 256)))
-    return fail(PAT_EUNSUPPORTED, "linear: nx and ny must be powers of two in [8, 256]");
+  if (g->boundary == PAT_BOUNDARY_PERIODIC && (!pow2_in(g->nx, 16, 1024) || !pow2_in(g->ny, 16, 1024)))
+    return fail(PAT_EUNSUPPORTED, "periodic: nx and ny must be powers of two in [16, 1024]");
+  if (g->boundary == PAT_BOUNDARY_LINEAR && (g->nx < 4 || g->nx > 512 || g->ny < 1 || g->ny > 512))
+    return fail(PAT_EUNSUPPORTED, "linear: nx must be in [4, 512] and ny in [1, 512]");
   if (g->nz > 2048 || g->nt > 2048) return fail(PAT_EUNSUPPORTED, "nz and nt must be <= 2048");
   if (g->n_ir < 0 || g->n_ir > kMaxIr) return fail(PAT_EUNSUPPORTED, "n_ir must be in [0, 64]");
   if (g->sx < 0 || g->sy < 0) return fail(PAT_EINVAL, "sx and sy must be >= 0");
-  if (g->nx % scan_sx(*g) || g->ny % scan_sy(*g) || (g->nx / scan_sx(*g)) % 4)
-    return fail(PAT_EUNSUPPORTED, "sx must divide nx with nx/sx a multiple of 4, and sy must divide ny");
+  if (g->nx % scan_sx(*g) || g->ny % scan_sy(*g))
+    return fail(PAT_EUNSUPPORTED, "sx must divide nx and sy must divide ny");
   if (g->n_ir > 0) {
     if (!g->ir) return fail(PAT_EINVAL, "ir is null while n_ir > 0");
     for (int j = 0; j < g->n_ir; ++j)

@@ -47,6 +47,17 @@ class Geometry:
         return g
 
 
+def transform_size(n: int, boundary: str) -> int:
+    """Transform grid size along one axis: n (periodic), or the smallest power
+    of two >= max(16, 2 n) (linear)."""
+    if boundary != "linear":
+        return n
+    p = 16
+    while p < 2 * n:
+        p *= 2
+    return p
+
+
 def _stream(device: torch.device) -> int:
     return torch.cuda.current_stream(device).cuda_stream
 
@@ -121,10 +132,10 @@ class Operator:
 
     @property
     def nk(self) -> int:
-        """Half-spectrum frequencies of the transform grid (doubled for the
-        linear boundary)."""
-        f = 2 if self.geom.boundary == "linear" else 1
-        return f * self.geom.ny * (f * self.geom.nx // 2 + 1)
+        """Half-spectrum frequencies of the transform grid (the padded grid
+        of the linear boundary)."""
+        fx, fy = transform_size(self.geom.nx, self.geom.boundary), transform_size(self.geom.ny, self.geom.boundary)
+        return fy * (fx // 2 + 1)
 
     def info(self) -> dict:
         """Stored-library shape: nk, nclass, members_max, nz_sim, slab bytes per layout."""

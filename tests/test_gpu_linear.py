@@ -1,8 +1,10 @@
 """GPU parity of the zero-padded linear convolution (Sec. 2.3) and of the
-512-point transforms it needs, through the C ABI, against the float64 oracle.
+512- and 1024-point transforms it needs, through the C ABI, against the
+float64 oracle, on power-of-two windows and on the paper's grid shapes.
 
-The linear operator pads the object into the doubled periodic grid, applies
-the operator of that grid and crops the data; the HIP path never stores the
+The linear operator pads the object into the periodic grid of the smallest
+power of two holding twice the window, applies the operator of that grid
+and crops the data; the HIP path never stores the
 padding (the transforms skip the zero rows and columns on the way in and the
 cropped ones on the way out).  Bars as in the periodic parity tests: library
 1e-7, A, A^T and FISTA iterates 1e-5 (float32), 2e-5 against the oracle
@@ -12,7 +14,7 @@ import pytest
 import torch
 
 from oracle import hlib, operators as ops, quant, solvers
-from oracle.geometry import Geometry as OGeom, doubled
+from oracle.geometry import Geometry as OGeom, linear_grid
 from paper_2603_28150_amd import _lib, inputs
 from paper_2603_28150_amd.op import Geometry, Operator
 
@@ -23,11 +25,17 @@ LINEAR = {
     "ragged": Geometry(32, 16, 13, 37, 1e-4, 1.3e-4, 1e-4, 2e-8, 1500.0, 0, "linear"),  # 64 x 32
     "mid": Geometry.paper_like(64, 64, 40, 130, boundary="linear"),         # 128^2
     "big": Geometry.paper_like(256, 256, 4, 24, boundary="linear"),         # 512^2
+    # the paper's grid shapes (wire phantom 202^2, in vivo 384 x 326): rows
+    # that are not a multiple of 4 long, 512^2 and 1024^2 transforms
+    "wire202": Geometry.paper_like(202, 202, 17, 48, boundary="linear"),
+    "invivo384x326": Geometry.paper_like(384, 326, 4, 24, boundary="linear"),
 }
 PERIODIC_512 = {
     "512x16": Geometry(512, 16, 5, 19, 1e-4, 1.2e-4, 1e-4, 2e-8, 1500.0),
     "16x512": Geometry(16, 512, 4, 21, 1e-4, 1e-4, 1e-4, 2e-8, 1500.0),
     "512x512": Geometry.paper_like(512, 512, 4, 24),
+    "1024x16": Geometry(1024, 16, 3, 17, 1e-4, 1e-4, 1e-4, 2e-8, 1500.0),
+    "16x1024": Geometry(16, 1024, 3, 17, 1e-4, 1e-4, 1e-4, 2e-8, 1500.0),
 }
 
 
@@ -54,12 +62,12 @@ def linear_setup(name, h_dtype="f32"):
     key = (name, h_dtype)
     if key not in _cache:
         g = LINEAR[name]
-        _cache[key] = (g, Operator(g, h_dtype), hlib.H_half(doubled(og(g))))
+        _cache[key] = (g, Operator(g, h_dtype), hlib.H_half(linear_grid(og(g))))
     return _cache[key]
 
 
 @pytest.mark.parametrize("name", list(LINEAR))
-def test_linear_library_is_that_of_the_doubled_grid(name):
+def test_linear_library_is_that_of_the_padded_grid(name):
     g, op, Hh2 = linear_setup(name)
     assert op.nk == Hh2.shape[0] * Hh2.shape[1]
     Hg = host(op.export_H())
@@ -108,7 +116,7 @@ def test_linear_fista_matches_oracle_and_rejects_normal_step():
     x_true = inputs.gaussian_blobs((g.nz, g.ny, g.nx), seed=830)
     clean = A(x_true)
     d = clean + 0.01 * np.sqrt(np.mean(clean ** 2)) * inputs.noise_like(clean.shape, seed=831)
-    tau = float(np.float32(0.9 / solvers.norm_exact(Hh2)))   # ||A_lin|| <= ||A_doubled||
+    tau = float(np.float32(0.9 / solvers.norm_exact(Hh2)))   # ||A_lin|| <= ||A_padded||
     K = 12
     xs = solvers.fista(A, AT, d, (g.nz, g.ny, g.nx), K, tau, 1e-3, nonneg=True)
     for k in (1, 4, K):
