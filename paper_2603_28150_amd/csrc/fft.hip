@@ -117,7 +117,9 @@ __global__ __launch_bounds__(256) void k_fft_cols(const float2* __restrict__ in,
 // The 2Q rows of a block are read with 16-byte loads into LDS, packed in
 // pairs as z = f[2q] + i f[2q+1]; after the transform the two real spectra are
 // separated and written slice-fastest (contiguous across threads).
-template <int N, int Q>  // Q packed complex sequences = 2Q real slices per block
+// GEN: rows of any length (element loads) or scan-grid sampling; the common
+// case (16-byte aligned rows, every column) compiles to plain vector loads
+template <int N, int Q, bool GEN>  // Q packed complex sequences = 2Q real slices per block
 __global__ __launch_bounds__(256) void k_fft_rows_r2c(const float* __restrict__ f,
                                                       float2* __restrict__ T, int ny, int nxd,
                                                       int sx, int S, int rs) {
@@ -143,7 +145,7 @@ __global__ __launch_bounds__(256) void k_fft_rows_r2c(const float* __restrict__ 
     ld[it] = make_float4(0.f, 0.f, 0.f, 0.f);
     if (u < 2 * Q * (N / 4) && s < S && 4 * c4 < nxd) {
       const float* src = f + ((size_t)s * ny + j) * nxd;
-      if ((nxd & 3) == 0) {
+      if (!GEN || (nxd & 3) == 0) {
         ld[it] = reinterpret_cast<const float4*>(src)[c4];
       } else {  // rows not 16-byte aligned: element loads, zeros past the row
         const int i0 = 4 * c4;
@@ -154,7 +156,7 @@ __global__ __launch_bounds__(256) void k_fft_rows_r2c(const float* __restrict__ 
       }
     }
   }
-  if (sx > 1) {  // samples land sx columns apart: clear the row buffers first
+  if (GEN && sx > 1) {  // samples land sx columns apart: clear the row buffers first
     for (int e = tid; e < Q * PAD; e += NT) ex[e] = make_float2(0.f, 0.f);
     __syncthreads();
   }
@@ -163,7 +165,7 @@ __global__ __launch_bounds__(256) void k_fft_rows_r2c(const float* __restrict__ 
     const int u = tid + it * NT;
     if (u >= 2 * Q * (N / 4)) break;
     const int row = u / (N / 4), c4 = u % (N / 4);
-    if (sx == 1) {
+    if (!GEN || sx == 1) {
       float* z = reinterpret_cast<float*>(ex + (row >> 1) * PAD + 4 * c4) + (row & 1);
       z[0] = ld[it].x;
       z[2] = ld[it].y;
@@ -223,7 +225,7 @@ __global__ __launch_bounds__(256) void k_fft_rows_r2c(const float* __restrict__ 
 // F Hermitian-extended from m = 0..N/2 (imaginary parts of m = 0, N/2 dropped),
 // stored for the samples i = 0..nxc-1 at transform columns sx*i (slices
 // f[s][ny][nxc]; the rest of the period is not stored)
-template <int N, int Q>
+template <int N, int Q, bool GEN>
 __global__ __launch_bounds__(256) void k_fft_rows_c2r(const float2* __restrict__ T,
                                                       float* __restrict__ f, int ny, int nxd,
                                                       int sx, int S, int rs, float scale,
@@ -310,7 +312,7 @@ __global__ __launch_bounds__(256) void k_fft_rows_c2r(const float2* __restrict__
       sb4[it] = make_float4(0.f, 0.f, 0.f, 0.f);
       if (u < 2 * Q * (N / 4) && s < S && 4 * c4 < nxd) {
         const float* src = sub + ((size_t)s * ny + j) * nxd;
-        if ((nxd & 3) == 0) {
+        if (!GEN || (nxd & 3) == 0) {
           sb4[it] = reinterpret_cast<const float4*>(src)[c4];
         } else {
           const int i0 = 4 * c4;
@@ -330,7 +332,7 @@ __global__ __launch_bounds__(256) void k_fft_rows_c2r(const float2* __restrict__
     if (u >= 2 * Q * (N / 4) || s >= S || 4 * c4 >= nxd) continue;
     float4 r;
     const int i0 = 4 * c4;
-    if (sx == 1) {
+    if (!GEN || sx == 1) {
       r = *reinterpret_cast<const float4*>(rows + row * (N + 4) + i0);
     } else {
       // samples past the row end read in-range LDS and are not stored
@@ -346,7 +348,7 @@ __global__ __launch_bounds__(256) void k_fft_rows_c2r(const float2* __restrict__
       v.w -= sb4[it].w;
     }
     float* dst = f + ((size_t)s * ny + j) * nxd;
-    if ((nxd & 3) == 0) {
+    if (!GEN || (nxd & 3) == 0) {
       reinterpret_cast<float4*>(dst)[c4] = v;
     } else {
       dst[i0] = v.x;
@@ -394,14 +396,20 @@ template <int N, int Q>
 static void rows_r2c(const float* f, float2* T, int nyc, int nxc, int sx, int S, int rs,
                      hipStream_t st) {
   dim3 grid(nyc, (S + 2 * Q - 1) / (2 * Q));
-  k_fft_rows_r2c<N, Q><<<grid, Q * Split<N>::N1, 0, st>>>(f, T, nyc, nxc, sx, S, rs);
+  if (sx == 1 && (nxc & 3) == 0)
+    k_fft_rows_r2c<N, Q, false><<<grid, Q * Split<N>::N1, 0, st>>>(f, T, nyc, nxc, sx, S, rs);
+  else
+    k_fft_rows_r2c<N, Q, true><<<grid, Q * Split<N>::N1, 0, st>>>(f, T, nyc, nxc, sx, S, rs);
 }
 
 template <int N, int Q>
 static void rows_c2r(const float2* T, float* f, int nyc, int nxc, int sx, int S, int rs, float scale,
                      const float* sub, hipStream_t st) {
   dim3 grid(nyc, (S + 2 * Q - 1) / (2 * Q));
-  k_fft_rows_c2r<N, Q><<<grid, Q * Split<N>::N1, 0, st>>>(T, f, nyc, nxc, sx, S, rs, scale, sub);
+  if (sx == 1 && (nxc & 3) == 0)
+    k_fft_rows_c2r<N, Q, false><<<grid, Q * Split<N>::N1, 0, st>>>(T, f, nyc, nxc, sx, S, rs, scale, sub);
+  else
+    k_fft_rows_c2r<N, Q, true><<<grid, Q * Split<N>::N1, 0, st>>>(T, f, nyc, nxc, sx, S, rs, scale, sub);
 }
 
 // 8 packed sequences (16 real slices) per row block: small enough for several
