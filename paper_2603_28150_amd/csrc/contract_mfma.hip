@@ -217,8 +217,11 @@ __global__ __launch_bounds__(512, MT == 4 ? 2 : 4) void k_contract_mfma(MfmaArgs
           const int pair = p0 + pl;
           const int g = pair / a.B, b = pair % a.B;
           if (a.members[c * a.G + g] < 0) continue;
-          a.out[(size_t)(c * a.G + g) * a.out_rs + (size_t)b * a.N + row] =
-              make_float2(acc[m][v] * sc, acc[m][v + 1] * sc);
+          // streamed out: not read again by this kernel
+          typedef float v2f __attribute__((ext_vector_type(2)));
+          __builtin_nontemporal_store(v2f{acc[m][v] * sc, acc[m][v + 1] * sc},
+                                      reinterpret_cast<v2f*>(a.out + (size_t)(c * a.G + g) * a.out_rs +
+                                                             (size_t)b * a.N + row));
         }
       }
     }
