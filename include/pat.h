@@ -206,7 +206,12 @@ pat_status pat_apply_AT(pat_op* op, const float* y, float* x, int32_t B,
  * a workspace sized by pat_workspace_bytes for some B with S <= B*max(nz, nt).
  * pat_contract (step (ii)): adjoint == 0: out[k][b*nt+n] = sum_l H^[k,l,n] in[k][b*nz+l];
  * adjoint != 0: out[k][b*nz+l] = sum_n conj(H^[k,l,n]) in[k][b*nt+n]; rows of
- * in and out have the strides of B*nz and B*nt slices; no workspace. */
+ * in and out have the strides of B*nz and B*nt slices; no workspace.  B = 1
+ * runs on the vector units in float32; B >= 2 on the matrix cores, with the
+ * spectra entering as bfloat16 hi + lo pairs (2^-17 relative) and float32
+ * library values as three bfloat16 terms (exact), accumulated in float32:
+ * an object's result in a batch agrees with its B = 1 result to about 1e-6
+ * relative (l2), not bit for bit. */
 pat_status pat_spectrum(pat_op* op, const float* f, float* spec, int32_t S, void* ws,
                         size_t ws_bytes, void* stream);
 pat_status pat_inverse_spectrum(pat_op* op, const float* spec, float* f, int32_t S, const float* sub,

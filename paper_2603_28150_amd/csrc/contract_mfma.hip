@@ -18,25 +18,47 @@
 // formats run on the bf16 MFMA with float32 accumulation and no overflow risk.
 // Output columns come out of the accumulators as (re, im) pairs along the
 // slab's output index: 256-byte contiguous stores.
+//
+// Float32 libraries (batches of objects) take the B operand from the stored
+// rows that run along k (the [n][l] rows for A, the [l][n] rows for A^T):
+// each lane reads 8 consecutive floats and splits each into three bfloat16
+// terms, exact for float32 significands; with the hi + lo spectra that is
+// five MFMAs per step (the two smallest products dropped, 2^-26 relative).
+//
+// Workgroups: when a batch needs several column groups per work item, the
+// groups of one item get indices equal modulo 8 and close together, so they
+// run on the same XCD at about the same time and its L2 serves the slab to
+// all of them.
 #include "pat_internal.hpp"
 
 namespace pat {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kWaves = 8;      // waves per workgroup
+constexpr int kWaves = 4;      // waves per workgroup (two workgroups share a CU)
 constexpr int kKC = 8;         // k-steps (of 16) per staged chunk
 constexpr int kMT = 4;         // most 32-column tiles per launch group (64 pairs)
 constexpr int kTerms = 2;      // hi + lo split of the spectra
 
-__device__ __forceinline__ unsigned short bf16_rne(float f) {
-  unsigned u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
+// two floats -> two bfloat16 (round to nearest even) packed low, high
+__device__ __forceinline__ unsigned pk_bf16(float a, float b) {
+  const bf16x2 h = __builtin_convertvector((f32x2){a, b}, bf16x2);
+  unsigned u;
+  __builtin_memcpy(&u, &h, 4);
+  return u;
 }
-__device__ __forceinline__ float bf16_to_f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+__device__ __forceinline__ float lo_f(unsigned u) { return __uint_as_float(u << 16); }
+__device__ __forceinline__ float hi_f(unsigned u) { return __uint_as_float(u & 0xffff0000u); }
+
+// (a, b) -> hi + lo bfloat16 pairs: a = hi.a + lo.a to 2^-17 relative
+__device__ __forceinline__ void split2(float a, float b, unsigned& hi, unsigned& lo) {
+  hi = pk_bf16(a, b);
+  lo = pk_bf16(a - lo_f(hi), b - hi_f(hi));
+}
 
 union Frag {
   u32x4 u;
@@ -44,16 +66,35 @@ union Frag {
   unsigned short s[8];
 };
 
+enum { kSrcBf16 = 0, kSrcF16 = 1, kSrcF32 = 2 };
+
+// 8 float32 values (two 16-byte units) -> three bfloat16 fragments whose sum
+// is exact (24 significant bits in three 8-bit pieces)
+__device__ __forceinline__ void split_f32(const u32x4 (&raw)[2], Frag& b1, Frag& b2, Frag& b3) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const float x0 = __uint_as_float(raw[j >> 1][2 * (j & 1)]);
+    const float x1 = __uint_as_float(raw[j >> 1][2 * (j & 1) + 1]);
+    const unsigned u1 = pk_bf16(x0, x1);
+    const float r0 = x0 - lo_f(u1), r1 = x1 - hi_f(u1);
+    const unsigned u2 = pk_bf16(r0, r1);
+    b1.u[j] = u1;
+    b2.u[j] = u2;
+    b3.u[j] = pk_bf16(r0 - lo_f(u2), r1 - hi_f(u2));
+  }
+}
+
 // float16 fragment -> two bfloat16 fragments whose sum is exact
 __device__ __forceinline__ void split_f16(const Frag& in, Frag& hi, Frag& lo) {
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    _Float16 h;
-    __builtin_memcpy(&h, &in.s[e], 2);
-    const float f = (float)h;
-    const unsigned short a = bf16_rne(f);
-    hi.s[e] = a;
-    lo.s[e] = bf16_rne(f - bf16_to_f(a));
+  for (int j = 0; j < 4; ++j) {
+    _Float16 h0, h1;
+    __builtin_memcpy(&h0, &in.s[2 * j], 2);
+    __builtin_memcpy(&h1, &in.s[2 * j + 1], 2);
+    unsigned a, b;
+    split2((float)h0, (float)h1, a, b);
+    hi.u[j] = a;
+    lo.u[j] = b;
   }
 }
 
@@ -75,17 +116,28 @@ __device__ __forceinline__ void stage_chunk(const MfmaArgs& a, u32x4* lds, int c
       const int g = pair / a.B, b = pair % a.B;
       if (a.members[c * a.G + g] >= 0) {
         const float2* src = a.in + (size_t)(c * a.G + g) * a.in_rs + (size_t)b * a.K;
+const int kb = k0 + ko * 8;
+        if (kb + 8 <= a.K) {  // 64 aligned bytes
+          const float4* s4 = reinterpret_cast<const float4*>(src + kb);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int k = k0 + ko * 8 + e;
-          if (k < a.K) {
-            v[e] = src[k];
-            if (a.in_scale) {
-              const float sc = a.in_scale[k];
+          for (int e = 0; e < 4; ++e) {
+            const float4 q = s4[e];
+            v[2 * e] = make_float2(q.x, q.y);
+            v[2 * e + 1] = make_float2(q.z, q.w);
+          }
+        } else {
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            if (kb + e < a.K) v[e] = src[kb + e];
+        }
+        if (a.in_scale) {
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            if (kb + e < a.K) {
+              const float sc = a.in_scale[kb + e];
               v[e].x *= sc;
               v[e].y *= sc;
             }
-          }
         }
       }
     }
@@ -96,10 +148,14 @@ __device__ __forceinline__ void stage_chunk(const MfmaArgs& a, u32x4* lds, int c
       const int mt = col >> 5, r = col & 31;
       Frag hi, lo;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const float x = part ? v[e].y : v[e].x;
-        hi.s[e] = bf16_rne(x);
-        lo.s[e] = bf16_rne(x - bf16_to_f(hi.s[e]));
+      for (int j = 0; j < 4; ++j) {
+        unsigned h, l;
+        if (part)
+          split2(v[2 * j].y, v[2 * j + 1].y, h, l);
+        else
+          split2(v[2 * j].x, v[2 * j + 1].x, h, l);
+        hi.u[j] = h;
+        lo.u[j] = l;
       }
       const int unit = (ks * MT + mt) * 64 + r + 32 * half;
       lds[unit] = hi.u;
@@ -108,12 +164,19 @@ __device__ __forceinline__ void stage_chunk(const MfmaArgs& a, u32x4* lds, int c
   }
 }
 
-template <bool F16, int MT>
-__global__ __launch_bounds__(512, MT == 4 ? 2 : 4) void k_contract_mfma(MfmaArgs a) {
+template <int SRC, int MT>
+__global__ __launch_bounds__(kWaves * 64, 2) void k_contract_mfma(MfmaArgs a, int groups) {
   extern __shared__ u32x4 lds[];  // [term][ks][mt][lane] 16-byte units
+  constexpr int KB = SRC == kSrcF32 ? kKC / 4 : kKC / 2;  // k-steps per batch of B loads
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
-  const int c = blockIdx.x, cg = blockIdx.y;  // c: work item
+  int c, cg;  // work item, column group
+  {
+    const int x = blockIdx.x & 7, r = blockIdx.x >> 3;
+    cg = r % groups;
+    c = (r / groups) * 8 + x;
+    if (c >= a.nitem) return;  // whole workgroup: padding of the last XCD round
+  }
   const int npairs = a.G * a.B;
   const int p0 = cg * (kMT * 16);
   const int gp = min(MT * 16, npairs - p0);  // pairs in this launch group
@@ -125,7 +188,10 @@ __global__ __launch_bounds__(512, MT == 4 ? 2 : 4) void k_contract_mfma(MfmaArgs
   const int wslot = w / kparts;
   const int wstride = kWaves / kparts;
   const int nchunks = (a.ksteps + kKC - 1) / kKC;
-  const u32x4* slab = reinterpret_cast<const u32x4*>(a.frag) + (size_t)a.item_slab[c] * a.ntiles * a.ksteps * 64;
+  const u32x4* slab = SRC == kSrcF32 ? nullptr
+                                      : reinterpret_cast<const u32x4*>(a.frag) +
+                                            (size_t)a.item_slab[c] * a.ntiles * a.ksteps * 64;
+  const float* krow = SRC == kSrcF32 ? a.krows + (size_t)a.item_slab[c] * a.k_slab : nullptr;
   bool staged = false;  // LDS holds chunk 0 (kept only when there is one chunk)
 
   for (int tile0 = 0; tile0 < a.ntiles; tile0 += wstride) {
@@ -143,42 +209,81 @@ __global__ __launch_bounds__(512, MT == 4 ? 2 : 4) void k_contract_mfma(MfmaArgs
         __syncthreads();
         staged = true;
       }
-      // this wave's slab fragments of the chunk, all loads issued up front
-      Frag fr[kKC];
+      // this wave's B operands of the chunk, in batches of KB k-steps with all
+      // loads of a batch issued before its MFMAs
 #pragma unroll
-      for (int s = 0; s < kKC; ++s) {
-        const int ks = kpart + s * kparts;
-        if (has && s * kparts < kKC && ks < nks)
-          fr[s].u = __builtin_nontemporal_load(slab + ((size_t)tile * a.ksteps + ch * kKC + ks) * 64 + lane);
-        else
-          fr[s].u = u32x4(0);
-      }
-      if (has) {
+      for (int s0 = 0; s0 < kKC; s0 += KB) {
+        Frag fr[KB];
+        u32x4 raw[KB][2];  // float32 rows: 8 floats per lane and k-step
 #pragma unroll
-        for (int s = 0; s < kKC; ++s) {
-          const int ks = kpart + s * kparts;
-          if (s * kparts >= kKC || ks >= nks) break;
-          if constexpr (!F16) {
-#pragma unroll
-            for (int m = 0; m < MT; ++m) {
-              Frag ah, al;
-              ah.u = lds[(ks * MT + m) * 64 + lane];
-              al.u = lds[(kKC * MT + ks * MT + m) * 64 + lane];
-              acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah.b, fr[s].b, acc[m], 0, 0, 0);
-              acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al.b, fr[s].b, acc[m], 0, 0, 0);
-            }
+        for (int s = 0; s < KB; ++s) {
+          const int ks = kpart + (s0 + s) * kparts;
+          const bool ok = has && (s0 + s) * kparts < kKC && ks < nks;
+          if constexpr (SRC != kSrcF32) {
+            if (ok)
+              fr[s].u = __builtin_nontemporal_load(slab + ((size_t)tile * a.ksteps + ch * kKC + ks) * 64 + lane);
+            else
+              fr[s].u = u32x4(0);
           } else {
-            Frag hh, hl;
-            split_f16(fr[s], hh, hl);
+            const int n = tile * 32 + (lane & 31);
+            const int k0 = (ch * kKC + ks) * 16 + 8 * (lane >> 5);
+            raw[s][0] = u32x4(0);
+            raw[s][1] = u32x4(0);
+            if (ok && n < a.N) {
+              const float* src = krow + (size_t)n * a.k_srow + k0;
+              if (k0 + 8 <= a.K) {
+                // plain loads: the 128-byte lines serve two k-steps
+                raw[s][0] = *reinterpret_cast<const u32x4*>(src);
+                raw[s][1] = *(reinterpret_cast<const u32x4*>(src) + 1);
+              } else {
 #pragma unroll
-            for (int m = 0; m < MT; ++m) {
-              Frag ah, al;
-              ah.u = lds[(ks * MT + m) * 64 + lane];
-              al.u = lds[(kKC * MT + ks * MT + m) * 64 + lane];
-              acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah.b, hh.b, acc[m], 0, 0, 0);
-              acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al.b, hh.b, acc[m], 0, 0, 0);
-              acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah.b, hl.b, acc[m], 0, 0, 0);
-              acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al.b, hl.b, acc[m], 0, 0, 0);
+                for (int e = 0; e < 8; ++e)
+                  if (k0 + e < a.K) raw[s][e >> 2][e & 3] = __float_as_uint(src[e]);
+              }
+            }
+          }
+        }
+        if (has) {
+#pragma unroll
+          for (int s = 0; s < KB; ++s) {
+            const int ks = kpart + (s0 + s) * kparts;
+            if ((s0 + s) * kparts >= kKC || ks >= nks) break;
+            if constexpr (SRC == kSrcBf16) {
+#pragma unroll
+              for (int m = 0; m < MT; ++m) {
+                Frag ah, al;
+                ah.u = lds[(ks * MT + m) * 64 + lane];
+                al.u = lds[(kKC * MT + ks * MT + m) * 64 + lane];
+                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah.b, fr[s].b, acc[m], 0, 0, 0);
+                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al.b, fr[s].b, acc[m], 0, 0, 0);
+              }
+            } else if constexpr (SRC == kSrcF16) {
+              Frag hh, hl;
+              split_f16(fr[s], hh, hl);
+#pragma unroll
+              for (int m = 0; m < MT; ++m) {
+                Frag ah, al;
+                ah.u = lds[(ks * MT + m) * 64 + lane];
+                al.u = lds[(kKC * MT + ks * MT + m) * 64 + lane];
+                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah.b, hh.b, acc[m], 0, 0, 0);
+                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al.b, hh.b, acc[m], 0, 0, 0);
+                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah.b, hl.b, acc[m], 0, 0, 0);
+                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al.b, hl.b, acc[m], 0, 0, 0);
+              }
+            } else {
+              Frag b1, b2, b3;
+              split_f32(raw[s], b1, b2, b3);
+#pragma unroll
+              for (int m = 0; m < MT; ++m) {
+                Frag ah, al;
+                ah.u = lds[(ks * MT + m) * 64 + lane];
+                al.u = lds[(kKC * MT + ks * MT + m) * 64 + lane];
+                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah.b, b1.b, acc[m], 0, 0, 0);
+                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah.b, b2.b, acc[m], 0, 0, 0);
+                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al.b, b1.b, acc[m], 0, 0, 0);
+                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah.b, b3.b, acc[m], 0, 0, 0);
+                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al.b, b2.b, acc[m], 0, 0, 0);
+              }
             }
           }
         }
@@ -229,28 +334,34 @@ __global__ __launch_bounds__(512, MT == 4 ? 2 : 4) void k_contract_mfma(MfmaArgs
 }
 
 template <int MT>
-static void launch_mt(const MfmaArgs& a, int hdtype, dim3 grid, hipStream_t st) {
+static void launch_mt(const MfmaArgs& a, int src, int groups, hipStream_t st) {
   const size_t lds = (size_t)kTerms * kKC * MT * 64 * 16;
   const size_t red = (size_t)kWaves * 16 * 64 * 4;  // k-part reduction buffer
   const size_t bytes = lds > red ? lds : red;
-  if (hdtype == PAT_H_F16)
-    k_contract_mfma<true, MT><<<grid, kWaves * 64, bytes, st>>>(a);
+  dim3 grid((unsigned)((a.nitem + 7) / 8 * 8 * groups));
+  if (src == kSrcF16)
+    k_contract_mfma<kSrcF16, MT><<<grid, kWaves * 64, bytes, st>>>(a, groups);
+  else if (src == kSrcF32)
+    k_contract_mfma<kSrcF32, MT><<<grid, kWaves * 64, bytes, st>>>(a, groups);
   else
-    k_contract_mfma<false, MT><<<grid, kWaves * 64, bytes, st>>>(a);
+    k_contract_mfma<kSrcBf16, MT><<<grid, kWaves * 64, bytes, st>>>(a, groups);
 }
 
 pat_status contract_mfma(const MfmaArgs& a, int hdtype, hipStream_t st) {
   if (a.nitem == 0 || a.B == 0) return PAT_OK;
+  const int src = hdtype == PAT_H_F16 ? kSrcF16 : hdtype == PAT_H_F32 ? kSrcF32 : kSrcBf16;
+  if (src == kSrcF32 && !a.krows) return fail(PAT_EINVAL, "float32 contraction on the matrix cores needs the k rows");
+  if (src != kSrcF32 && !a.frag) return fail(PAT_EINVAL, "16-bit contraction needs the operand tiles");
   const int npairs = a.G * a.B;
   const int groups = (npairs + kMT * 16 - 1) / (kMT * 16);
+  if ((long long)(a.nitem + 7) / 8 * 8 * groups > 0x7fffffffLL) return fail(PAT_EUNSUPPORTED, "contraction grid too large");
   const int cols = 2 * (groups > 1 ? kMT * 16 : npairs);  // columns of the widest group
-  dim3 grid(a.nitem, groups);
   if (cols <= 32)
-    launch_mt<1>(a, hdtype, grid, st);
+    launch_mt<1>(a, src, groups, st);
   else if (cols <= 64)
-    launch_mt<2>(a, hdtype, grid, st);
+    launch_mt<2>(a, src, groups, st);
   else
-    launch_mt<4>(a, hdtype, grid, st);
+    launch_mt<4>(a, src, groups, st);
   PAT_LAUNCHED("contraction (MFMA)");
   return PAT_OK;
 }

@@ -344,9 +344,14 @@ static pat_status run_contract(pat_op* op, bool adjoint, const float2* in, float
   const float* sc = g.h_dtype == PAT_H_F32 ? nullptr : op->inv_scale;
   // one object: the VALU kernel on the row layouts streams the library at
   // the FP32 kernel's rate; batches go to the matrix cores (one slab read
-  // serves every object)
-  if (g.h_dtype != PAT_H_F32 && B > 1) {
+  // serves every object; FP32 values enter as three bf16 terms)
+  const bool f32 = g.h_dtype == PAT_H_F32;
+  if (B > 1) {
     MfmaArgs m;
+    m.krows = nullptr;
+    m.k_srow = 0;
+    m.k_slab = 0;
+    m.frag = nullptr;
     m.members = op->members;
     m.item_slab = op->item_slab;
     m.in = in;
@@ -355,7 +360,13 @@ static pat_status run_contract(pat_op* op, bool adjoint, const float2* in, float
     m.B = B;
     m.nitem = op->nitem;
     if (!adjoint) {
-      m.frag = op->slabA;
+      if (f32) {
+        m.krows = static_cast<const float*>(op->rowT);  // [n][l]: runs along k = l
+        m.k_srow = op->sT_row;
+        m.k_slab = (long long)g.nt * op->sT_row;
+      } else {
+        m.frag = op->slabA;
+      }
       m.K = g.nz;
       m.N = g.nt;
       m.ntiles = op->ntA;
@@ -363,7 +374,13 @@ static pat_status run_contract(pat_op* op, bool adjoint, const float2* in, float
       m.in_scale = sc;
       m.out_scale = nullptr;
     } else {
-      m.frag = op->slabT;
+      if (f32) {
+        m.krows = static_cast<const float*>(op->rowA);  // [l][n]: runs along k = n
+        m.k_srow = op->sA_row;
+        m.k_slab = (long long)g.nz * op->sA_row;
+      } else {
+        m.frag = op->slabT;
+      }
       m.K = g.nt;
       m.N = g.nz;
       m.ntiles = op->ntT;

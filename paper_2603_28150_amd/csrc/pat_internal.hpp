@@ -81,7 +81,7 @@ pat_status contract(const ContractArgs& a, int hdtype, int G, int B, hipStream_t
 // fragment (tile, kstep) of class c holds S_c(kstep*16 + 8*(lane/32) + e,
 // tile*32 + lane%32) at 16-byte unit lane, element e.
 struct MfmaArgs {
-  const void* frag;          // [nslab][ntiles][ksteps][64] 16-byte units
+  const void* frag;          // 16-bit libraries: [nslab][ntiles][ksteps][64] 16-byte units (else null)
   const int32_t* members;    // [nitem][G]
   const int32_t* item_slab;  // [nitem]
   const float2* in;          // [nitem*G][in_rs]
@@ -89,6 +89,9 @@ struct MfmaArgs {
   const float* in_scale;     // [K] or null
   const float* out_scale;    // [N] or null
   int K, N, ntiles, ksteps, in_rs, out_rs, G, B, nitem;
+  const float* krows;        // float32 libraries: [nslab][N][k_srow] rows along k (else null)
+  int k_srow;
+  long long k_slab;          // N * k_srow
 };
 pat_status contract_mfma(const MfmaArgs& a, int hdtype, hipStream_t st);
 

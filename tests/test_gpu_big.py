@@ -73,3 +73,25 @@ def test_big_16bit_library_batch(kind):
         Dg = ops.dft_at(ys[b], M, P)
         Do = ops.A_at_freqs(Hk, xs[b], M, P)
         assert np.linalg.norm(Dg - Do) / np.linalg.norm(Do) < 5e-3
+
+
+def test_big_float32_batch_of_16(big):
+    # the batch form of the benchmark (16 objects, float32 library on the
+    # matrix cores): sampled objects of the batch against the oracle's
+    # spectra at the sampled frequencies, forward and adjoint
+    op, Hk = big
+    B = 16
+    xs = np.stack([inputs.gaussian_random((BIG.nz, BIG.ny, BIG.nx), seed=700 + b) for b in range(B)])
+    ys = op.apply_A(torch.from_numpy(xs.astype(np.float32)).cuda()).cpu().numpy().astype(np.float64)
+    rs = np.stack([inputs.gaussian_random((BIG.nt, BIG.ny, BIG.nx), seed=800 + b) for b in (0, 5, 15)])
+    rb = np.zeros((B, BIG.nt, BIG.ny, BIG.nx), np.float32)
+    rb[[0, 5, 15]] = rs
+    gs = op.apply_AT(torch.from_numpy(rb).cuda()).cpu().numpy().astype(np.float64)
+    for i, b in enumerate((0, 5, 15)):
+        Dg = ops.dft_at(ys[b], M, P)
+        Do = ops.A_at_freqs(Hk, xs[b], M, P)
+        assert np.linalg.norm(Dg - Do) / np.linalg.norm(Do) < 1e-5, b
+        Gg = ops.dft_at(gs[b], M, P)
+        Go = ops.AT_at_freqs(Hk, rs[i], M, P)
+        assert np.linalg.norm(Gg - Go) / np.linalg.norm(Go) < 1e-5, b
+    assert np.abs(gs[1]).max() == 0.0                # zero data, zero image

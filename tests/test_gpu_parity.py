@@ -104,7 +104,8 @@ def test_batch_matches_single_and_is_repeatable():
     assert torch.equal(yb, yb2)                      # same stream, same bits: no races
     for b in range(3):
         assert rel(host(yb[b]), ops.A_fft(Hh, xs[b])) < 1e-5
-        assert rel(host(yb[b]), host(op.apply_A(dev(xs[b])))) < 1e-6
+        # a batch runs on the matrix cores (spectra split to 2^-17 relative)
+        assert rel(host(yb[b]), host(op.apply_A(dev(xs[b])))) < 1e-5
     ds = np.stack([inputs.gaussian_random((g.nt, g.ny, g.nx), seed=40 + b) for b in range(3)])
     gb = op.apply_AT(dev(ds))
     for b in range(3):
@@ -236,7 +237,7 @@ def test_batched_fista_step_isolates_objects():
         z1 = torch.zeros_like(x1)
         for k in range(4):
             op.fista_step(dev(ds[b])[None], x1, z1, [0.1 * k], [taus[b]], [lams[b]], [nn[b]])
-        assert rel(host(xb[b]), host(x1[0])) < 1e-6
+        assert rel(host(xb[b]), host(x1[0])) < 1e-5   # batch on the matrix cores
     assert int(bad.sum()) == 0
 
 
@@ -318,6 +319,28 @@ def test_quantised_batched_matrix_core_path(kind, name, B):
         assert rel(ys[b], host(op.apply_A(dev(xs[b])))) < 1e-5
         assert rel(gs[b], host(op.apply_AT(dev(ds[b])))) < 1e-5
     assert op.adjoint_check(dev(xs[0]), dev(ds[0])) < 1e-5
+
+
+@pytest.mark.parametrize("name,B", [("tiny", 16), ("ragged", 4), ("mid", 5), ("ragged", 2)])
+def test_float32_batched_path(name, B):
+    # float32 batches run on the matrix cores (library rows split into three
+    # bf16 terms, spectra into two): every object matches the oracle to the
+    # float32 bar, and its own single-object apply (the VALU kernel) to 1e-5;
+    # the ragged shapes (13 and 37 along k) end in a partial k-step, the mid
+    # one spans two k-chunks for A^T
+    g, op, Hh = setup(name)
+    xs = np.stack([inputs.gaussian_blobs((g.nz, g.ny, g.nx), seed=500 + b) for b in range(B)])
+    ds = np.stack([inputs.gaussian_random((g.nt, g.ny, g.nx), seed=600 + b) for b in range(B)])
+    yb = op.apply_A(dev(xs))
+    gb = op.apply_AT(dev(ds))
+    assert torch.equal(yb, op.apply_A(dev(xs)))      # repeatable bits
+    ys, gs = host(yb), host(gb)
+    for b in range(B):
+        assert rel(ys[b], ops.A_fft(Hh, xs[b])) < 1e-5, b
+        assert rel(gs[b], ops.AT_fft(Hh, ds[b])) < 1e-5, b
+    for b in (0, B - 1):
+        assert rel(ys[b], host(op.apply_A(dev(xs[b])))) < 1e-5
+        assert rel(gs[b], host(op.apply_AT(dev(ds[b])))) < 1e-5
 
 
 @pytest.mark.parametrize("name,kind", [("ragged", "f32"), ("mid", "f32"), ("tiny", "bf16"), ("tiny", "f16")])
