@@ -73,16 +73,18 @@ typedef enum { PAT_H_F32 = 0, PAT_H_BF16 = 1, PAT_H_F16 = 2 } pat_hdtype;
 /* Transverse boundary of the convolution.  PERIODIC: circular at nx x ny.
  * LINEAR: the zero-padded linear convolution of Sec. 2.3 (the object and the
  * data live on nx x ny; the transforms and the library are taken on the
- * px x py periodic grid, px the smallest power of two >= max(16, 2 nx), and
- * likewise py; the object is zero-padded and the data cropped, so that A^T
+ * px x py periodic grid, px the smallest transform size (see nx below)
+ * >= max(16, 2 nx), and likewise py; the object is zero-padded and the data
+ * cropped, so that A^T
  * stays the exact adjoint).  That library is the free-space response on the
  * nx x ny window as long as the wavefront does not travel round the period
  * within the record, c*dt*(nt-1) < (px-nx+1)*dx and (py-ny+1)*dy. */
 typedef enum { PAT_BOUNDARY_PERIODIC = 0, PAT_BOUNDARY_LINEAR = 1 } pat_boundary;
 
 typedef struct {
-  int32_t nx, ny;  /* transverse grid (x fastest): powers of two in [16, 1024]
-                      (periodic); any nx in [4, 512], ny in [1, 512] (linear) */
+  int32_t nx, ny;  /* transverse grid (x fastest): transform sizes, 2^a in
+                      [16, 1024] or 3 * 2^a in [48, 768] (periodic); any nx in
+                      [4, 512], ny in [1, 512] (linear) */
   int32_t nz, nt;  /* depths and time samples, >= 1 */
   double dx, dy, dz, dt, c; /* spacings [m], time step [s], sound speed [m/s]; all > 0 */
   int32_t nz_sim;  /* z-period of the simulated medium in grid points: 0 selects

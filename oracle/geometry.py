@@ -8,8 +8,9 @@ The object lives on G_rho = G_xy x G_z and the data on G_d = G_xy x T
 * the sensor plane is depth index l = 0 (z_l = l*dz), and the time grid is
   t_n = n*dt for n = 0..Nt-1 (it includes t = 0);
 * the transverse boundary is periodic at Nx x Ny (circular convolution), or,
-  for the zero-padded linear convolution, periodic at 2Nx x 2Ny with the
-  object padded and the data cropped (``doubled``);
+  for the zero-padded linear convolution, periodic at a period of at least
+  2Nx x 2Ny with the object padded and the data cropped (``linear_grid``;
+  ``doubled`` is exactly 2Nx x 2Ny);
 * the simulated medium is periodic in z with period nz_sim >= Nz; by default
   nz_sim is the smallest power of two >= Nz + ceil(c*dt*(Nt-1)/dz) + 1, so
   that the wrapped image of the object cannot reach the sensor within the
@@ -74,18 +75,23 @@ def doubled(g: Geometry) -> Geometry:
     return replace(g, nx=2 * g.nx, ny=2 * g.ny, nz_sim=g.nq)
 
 
+def transform_sizes():
+    """Periods the zero-padded convolution may be taken on: 2^a in [16, 1024]
+    and 3 * 2^a in [48, 768] (any period >= 2N keeps every source-sensor
+    offset of an N-point window from wrapping; these are the ones with fast
+    transforms)."""
+    return sorted({2 ** a for a in range(4, 11)} | {3 * 2 ** a for a in range(4, 9)})
+
+
 def linear_grid(g: Geometry) -> Geometry:
     """The periodic grid of the zero-padded linear convolution of an Nx x Ny
-    window: along each axis the smallest power of two >= max(16, 2N), so no
-    source-sensor offset inside the window wraps (equals ``doubled`` when N is
-    a power of two >= 8)."""
+    window: along each axis the smallest of ``transform_sizes`` that is
+    >= max(16, 2N), so no source-sensor offset inside the window wraps
+    (equals ``doubled`` when N is a power of two >= 8)."""
     from dataclasses import replace
 
     def size(n):
-        p = 16
-        while p < 2 * n:
-            p *= 2
-        return p
+        return min(p for p in transform_sizes() if p >= max(16, 2 * n))
     return replace(g, nx=size(g.nx), ny=size(g.ny), nz_sim=g.nq)
 
 

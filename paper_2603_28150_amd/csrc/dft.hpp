@@ -1,4 +1,5 @@
-// Small in-register DFTs (sizes 1, 2, 4, 8, 16) used by the 2D FFT kernels.
+// Small in-register DFTs (sizes 1, 2, 3, 4, 6, 8, 12, 16, 24, 32) used by the
+// 2D FFT kernels.
 // DIR = -1: forward, exp(-2 pi i n k / R); DIR = +1: inverse (unnormalised).
 #pragma once
 
@@ -51,6 +52,21 @@ __device__ __forceinline__ float2 w16(int e) {
   return make_float2(cs[e & 15], DIR < 0 ? -sn[e & 15] : sn[e & 15]);
 }
 
+// exp(DIR * 2 pi i e / 48), e >= 0, from cos(7.5 j degrees), j = 0..12.
+__device__ __forceinline__ float cos48(int e) {
+  const float c[13] = {1.f, 0.9914448613738104f, 0.9659258262890683f, 0.9238795325112867f,
+                       0.8660254037844387f, 0.7933533402912352f, 0.7071067811865476f,
+                       0.6087614290087207f, 0.5f, 0.38268343236508984f, 0.25881904510252074f,
+                       0.1305261922200517f, 0.f};
+  e %= 48;
+  return e <= 12 ? c[e] : e <= 24 ? -c[24 - e] : e <= 36 ? -c[e - 24] : c[48 - e];
+}
+template <int DIR>
+__device__ __forceinline__ float2 w48(int e) {
+  const float sn = cos48(e + 36);  // sin(t) = cos(t - 90 degrees)
+  return make_float2(cos48(e), DIR < 0 ? -sn : sn);
+}
+
 template <int DIR>
 __device__ __forceinline__ void dft2(float2& a, float2& b) {
   float2 t = a;
@@ -69,6 +85,49 @@ __device__ __forceinline__ void dft4(float2* v, int s) {
   v[3 * s] = csub(a1, b1);
 }
 
+// in place on a, b, c: X1 = a - (b+c)/2 + DIR i (sqrt(3)/2)(b-c), X2 its mirror
+template <int DIR>
+__device__ __forceinline__ void dft3(float2& a, float2& b, float2& c) {
+  constexpr float h = 0.8660254037844386f;  // sqrt(3)/2
+  const float2 s = cadd(b, c), d = csub(b, c);
+  const float2 m = make_float2(a.x - 0.5f * s.x, a.y - 0.5f * s.y);
+  const float2 r = rot90<DIR>(cscale(d, h));
+  a = cadd(a, s);
+  b = cadd(m, r);
+  c = csub(m, r);
+}
+
+template <int R, int DIR>
+__device__ __forceinline__ void dft(float2* v);
+
+// R = P * Q points (R dividing 48): input n = Q n1 + n2, output k = k1 + P k2;
+// P-point DFTs over n1, twiddles exp(DIR 2 pi i n2 k1 / R), Q-point DFTs over n2
+template <int P, int Q, int DIR>
+__device__ __forceinline__ void dft_pq(float2* v) {
+  constexpr int R = P * Q;
+  static_assert(48 % R == 0, "twiddles come from the 48-point table");
+  float2 y[R];
+#pragma unroll
+  for (int n2 = 0; n2 < Q; ++n2) {
+    float2 t[P];
+#pragma unroll
+    for (int n1 = 0; n1 < P; ++n1) t[n1] = v[Q * n1 + n2];
+    dft<P, DIR>(t);
+#pragma unroll
+    for (int k1 = 0; k1 < P; ++k1)
+      y[n2 * P + k1] = (n2 * k1 == 0) ? t[k1] : cmul(t[k1], w48<DIR>(n2 * k1 * (48 / R)));
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < P; ++k1) {
+    float2 t[Q];
+#pragma unroll
+    for (int n2 = 0; n2 < Q; ++n2) t[n2] = y[n2 * P + k1];
+    dft<Q, DIR>(t);
+#pragma unroll
+    for (int k2 = 0; k2 < Q; ++k2) v[k1 + P * k2] = t[k2];
+  }
+}
+
 // Full DFT of R points held in v[0..R-1]; natural order in and out.
 template <int R, int DIR>
 __device__ __forceinline__ void dft(float2* v) {
@@ -76,6 +135,10 @@ __device__ __forceinline__ void dft(float2* v) {
     return;
   } else if constexpr (R == 2) {
     dft2<DIR>(v[0], v[1]);
+  } else if constexpr (R == 3) {
+    dft3<DIR>(v[0], v[1], v[2]);
+  } else if constexpr (R == 6 || R == 12 || R == 24) {
+    dft_pq<R / 3, 3, DIR>(v);
   } else if constexpr (R == 4) {
     dft4<DIR>(v, 1);
   } else if constexpr (R == 8) {
@@ -107,7 +170,8 @@ __device__ __forceinline__ void dft(float2* v) {
 #pragma unroll
       for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[k2];
     }
-  } else if constexpr (R == 32) {
+  } else {
+    static_assert(R == 32, "unsupported DFT size");
     // radix 2 x 16: even/odd halves, then combine with exp(DIR 2 pi i k / 32)
     float2 e[16], o[16];
 #pragma unroll
@@ -135,5 +199,10 @@ template <> struct Split<128> { static constexpr int N1 = 16, N2 = 8; };
 template <> struct Split<256> { static constexpr int N1 = 16, N2 = 16; };
 template <> struct Split<512> { static constexpr int N1 = 32, N2 = 16; };
 template <> struct Split<1024> { static constexpr int N1 = 32, N2 = 32; };
+template <> struct Split<48> { static constexpr int N1 = 8, N2 = 6; };
+template <> struct Split<96> { static constexpr int N1 = 12, N2 = 8; };
+template <> struct Split<192> { static constexpr int N1 = 16, N2 = 12; };
+template <> struct Split<384> { static constexpr int N1 = 24, N2 = 16; };
+template <> struct Split<768> { static constexpr int N1 = 32, N2 = 24; };
 
 }  // namespace pat

@@ -1,4 +1,5 @@
-// Batched 2D transverse FFTs for power-of-two sizes 16..256 (gfx950).
+// Batched 2D transverse FFTs (gfx950) for transform sizes 2^a in [16, 1024]
+// and 3 * 2^a in [48, 768].
 //
 // Step (i) and step (iii) of the FFT realisation of the operator (Sec. 3.2):
 // every depth or time slice is transformed over (x, y).  Each 1D transform
@@ -10,8 +11,8 @@
 //            complex transform;
 //   columns: complex transforms along y on the frequency-major layout, slices
 //            fastest, so that loads and stores are contiguous across threads.
-// Twiddles exp(-2 pi i e / 512) are tabulated on the host in float64 and
-// rounded once to float32.
+// Twiddles exp(-2 pi i e / 1024) and exp(-2 pi i e / 768) are tabulated on
+// the host in float64 and rounded once to float32.
 //
 // Transform sizes and data extents are separate: slices cover an nx_d x ny_d
 // window of the fx x fy transform grid (nx_d <= fx, ny_d <= fy), sampled at
@@ -26,24 +27,35 @@
 
 namespace pat {
 
-constexpr int kTwN = 1024;  // largest transform size
+constexpr int kTwN = 1024;  // largest power-of-two transform size
+constexpr int kTw3N = 768;  // largest transform size 3 * 2^a
 __device__ float2 g_tw[kTwN];
+__device__ float2 g_tw3[kTw3N];
+
+template <int M>
+static void twiddle_table(float2* host) {
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int e = 0; e < M; ++e) {
+    const double a = two_pi * e / (double)M;
+    host[e] = make_float2((float)std::cos(a), (float)-std::sin(a));
+  }
+}
 
 pat_status fft_init_device() {
   float2 host[kTwN];
-  const double two_pi = 6.283185307179586476925286766559;
-  for (int e = 0; e < kTwN; ++e) {
-    double a = two_pi * e / (double)kTwN;
-    host[e] = make_float2((float)std::cos(a), (float)-std::sin(a));
-  }
-  PAT_HIP(hipMemcpyToSymbol(HIP_SYMBOL(g_tw), host, sizeof(host), 0, hipMemcpyHostToDevice));
+  twiddle_table<kTwN>(host);
+  PAT_HIP(hipMemcpyToSymbol(HIP_SYMBOL(g_tw), host, sizeof(float2) * kTwN, 0, hipMemcpyHostToDevice));
+  twiddle_table<kTw3N>(host);
+  PAT_HIP(hipMemcpyToSymbol(HIP_SYMBOL(g_tw3), host, sizeof(float2) * kTw3N, 0, hipMemcpyHostToDevice));
   return PAT_OK;
 }
 
+// exp(DIR 2 pi i e / N), e < N, into LDS
 template <int N, int DIR>
 __device__ __forceinline__ void load_twiddles(float2* tw, int tid, int nthreads) {
+  static_assert(kTwN % N == 0 || kTw3N % N == 0, "no twiddle table for this size");
   for (int e = tid; e < N; e += nthreads) {
-    float2 w = g_tw[e * (kTwN / N)];
+    const float2 w = kTwN % N == 0 ? g_tw[e * (kTwN / N)] : g_tw3[e * (kTw3N / N)];
     tw[e] = DIR < 0 ? w : cconj(w);
   }
 }
@@ -55,7 +67,7 @@ __device__ __forceinline__ void load_twiddles(float2* tw, int tid, int nthreads)
 // only rows j = istride*j' with j' < nin are present (the others are zeros),
 // at row j'*nh + m, and only rows p = ostride*p' with p' < nout are written,
 // at row p'*nh + m.
-template <int N> struct ColSB { static constexpr int value = N <= 256 ? 16 : N == 512 ? 8 : 4; };  // slices per block
+template <int N> struct ColSB { static constexpr int value = N <= 256 ? 16 : N <= 512 ? 8 : 4; };  // slices per block
 
 template <int N, int DIR>
 __global__ __launch_bounds__(256) void k_fft_cols(const float2* __restrict__ in,
@@ -208,7 +220,7 @@ __global__ __launch_bounds__(256) void k_fft_rows_r2c(const float* __restrict__ 
     if (s >= S) continue;
     const int qq = sl >> 1;
     const float2 zm = ex[qq * PAD + m];
-    const float2 zc = cconj(ex[qq * PAD + ((N - m) & (N - 1))]);
+    const float2 zc = cconj(ex[qq * PAD + (m == 0 ? 0 : N - m)]);
     float2 r;
     if ((sl & 1) == 0) {
       r = make_float2(0.5f * (zm.x + zc.x), 0.5f * (zm.y + zc.y));
@@ -385,7 +397,12 @@ static pat_status cols(const float2* in, float2* out, int fy, int nh, int S, int
     case 256: PAT_COLS(256); break;
     case 512: PAT_COLS(512); break;
     case 1024: PAT_COLS(1024); break;
-    default: return fail(PAT_EUNSUPPORTED, "transform size along y must be a power of two in [16, 1024]");
+    case 48: PAT_COLS(48); break;
+    case 96: PAT_COLS(96); break;
+    case 192: PAT_COLS(192); break;
+    case 384: PAT_COLS(384); break;
+    case 768: PAT_COLS(768); break;
+    default: return fail(PAT_EUNSUPPORTED, "transform size along y must be 2^a in [16, 1024] or 3 * 2^a in [48, 768]");
   }
 #undef PAT_COLS
   PAT_LAUNCHED("fft columns");
@@ -438,7 +455,12 @@ pat_status fft2_r2c(const float* f, float2* T, float2* X, int fx, int fy, int nx
     case 256: PAT_ROWS(rows_r2c, 256, f, T, nyc, nxc, sx, S, rs, st); break;
     case 512: PAT_ROWS(rows_r2c, 512, f, T, nyc, nxc, sx, S, rs, st); break;
     case 1024: PAT_ROWS(rows_r2c, 1024, f, T, nyc, nxc, sx, S, rs, st); break;
-    default: return fail(PAT_EUNSUPPORTED, "transform size along x must be a power of two in [16, 1024]");
+    case 48: PAT_ROWS(rows_r2c, 48, f, T, nyc, nxc, sx, S, rs, st); break;
+    case 96: PAT_ROWS(rows_r2c, 96, f, T, nyc, nxc, sx, S, rs, st); break;
+    case 192: PAT_ROWS(rows_r2c, 192, f, T, nyc, nxc, sx, S, rs, st); break;
+    case 384: PAT_ROWS(rows_r2c, 384, f, T, nyc, nxc, sx, S, rs, st); break;
+    case 768: PAT_ROWS(rows_r2c, 768, f, T, nyc, nxc, sx, S, rs, st); break;
+    default: return fail(PAT_EUNSUPPORTED, "transform size along x must be 2^a in [16, 1024] or 3 * 2^a in [48, 768]");
   }
   PAT_LAUNCHED("fft rows r2c");
   return cols<-1>(T, X, fy, nh, S, rs, nullptr, rowmap, nyc, sy, fy, 1, st);
@@ -462,7 +484,12 @@ pat_status fft2_c2r(const float2* X, float2* T, float* f, int fx, int fy, int nx
     case 256: PAT_ROWS(rows_c2r, 256, T, f, nyc, nxc, sx, S, rs, scale, sub, st); break;
     case 512: PAT_ROWS(rows_c2r, 512, T, f, nyc, nxc, sx, S, rs, scale, sub, st); break;
     case 1024: PAT_ROWS(rows_c2r, 1024, T, f, nyc, nxc, sx, S, rs, scale, sub, st); break;
-    default: return fail(PAT_EUNSUPPORTED, "transform size along x must be a power of two in [16, 1024]");
+    case 48: PAT_ROWS(rows_c2r, 48, T, f, nyc, nxc, sx, S, rs, scale, sub, st); break;
+    case 96: PAT_ROWS(rows_c2r, 96, T, f, nyc, nxc, sx, S, rs, scale, sub, st); break;
+    case 192: PAT_ROWS(rows_c2r, 192, T, f, nyc, nxc, sx, S, rs, scale, sub, st); break;
+    case 384: PAT_ROWS(rows_c2r, 384, T, f, nyc, nxc, sx, S, rs, scale, sub, st); break;
+    case 768: PAT_ROWS(rows_c2r, 768, T, f, nyc, nxc, sx, S, rs, scale, sub, st); break;
+    default: return fail(PAT_EUNSUPPORTED, "transform size along x must be 2^a in [16, 1024] or 3 * 2^a in [48, 768]");
   }
   PAT_LAUNCHED("fft rows c2r");
   return PAT_OK;

@@ -65,6 +65,9 @@ pat_status hip_check(hipError_t e, const char* what) {
 // ---------------------------------------------------------- geometry rules
 static bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
 
+// transform sizes the FFT kernels provide: 2^a in [16, 1024], 3 * 2^a in [48, 768]
+static bool fft_size(int v) { return pow2_in(v, 16, 1024) || (v % 3 == 0 && pow2_in(v / 3, 16, 256)); }
+
 static int default_nq(const pat_geometry& g) {
   const double reach = std::ceil(g.c * g.dt * (double)(g.nt - 1) / g.dz);
   const long long need = (long long)g.nz + (long long)reach + 1;
@@ -78,11 +81,11 @@ static int scan_sx(const pat_geometry& g) { return g.sx > 1 ? g.sx : 1; }
 static int scan_sy(const pat_geometry& g) { return g.sy > 1 ? g.sy : 1; }
 static bool sampled(const pat_geometry& g) { return scan_sx(g) > 1 || scan_sy(g) > 1; }
 
-// linear boundary: the transform grid is the smallest power of two holding
+// linear boundary: the transform grid is the smallest transform size holding
 // twice the window (so that no offset inside the window wraps), at least 16
 static int linear_size(int n) {
-  int p = 16;
-  while (p < 2 * n) p <<= 1;
+  int p = n > 8 ? 2 * n : 16;
+  while (!fft_size(p)) ++p;
   return p;
 }
 
@@ -105,8 +108,8 @@ static pat_status check_geometry(const pat_geometry* g) {
   if (g->h_dtype < PAT_H_F32 || g->h_dtype > PAT_H_F16) return fail(PAT_EINVAL, "unknown h_dtype");
   if (g->boundary != PAT_BOUNDARY_PERIODIC && g->boundary != PAT_BOUNDARY_LINEAR)
     return fail(PAT_EINVAL, "unknown boundary");
-  if (g->boundary == PAT_BOUNDARY_PERIODIC && (!pow2_in(g->nx, 16, 1024) || !pow2_in(g->ny, 16, 1024)))
-    return fail(PAT_EUNSUPPORTED, "periodic: nx and ny must be powers of two in [16, 1024]");
+  if (g->boundary == PAT_BOUNDARY_PERIODIC && (!fft_size(g->nx) || !fft_size(g->ny)))
+    return fail(PAT_EUNSUPPORTED, "periodic: nx and ny must be transform sizes: 2^a in [16, 1024] or 3 * 2^a in [48, 768]");
   if (g->boundary == PAT_BOUNDARY_LINEAR && (g->nx < 4 || g->nx > 512 || g->ny < 1 || g->ny > 512))
     return fail(PAT_EUNSUPPORTED, "linear: nx must be in [4, 512] and ny in [1, 512]");
   if (g->nz > 2048 || g->nt > 2048) return fail(PAT_EUNSUPPORTED, "nz and nt must be <= 2048");

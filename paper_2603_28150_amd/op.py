@@ -47,14 +47,20 @@ class Geometry:
         return g
 
 
+def _fft_size(v: int) -> bool:
+    pow2 = lambda u, lo, hi: lo <= u <= hi and u & (u - 1) == 0
+    return pow2(v, 16, 1024) or (v % 3 == 0 and pow2(v // 3, 16, 256))
+
+
 def transform_size(n: int, boundary: str) -> int:
-    """Transform grid size along one axis: n (periodic), or the smallest power
-    of two >= max(16, 2 n) (linear)."""
+    """Transform grid size along one axis: n (periodic), or the smallest
+    transform size (2^a in [16, 1024] or 3 * 2^a in [48, 768]) >= max(16, 2 n)
+    (linear)."""
     if boundary != "linear":
         return n
-    p = 16
-    while p < 2 * n:
-        p *= 2
+    p = max(16, 2 * n)
+    while not _fft_size(p):
+        p += 1
     return p
 
 

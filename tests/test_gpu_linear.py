@@ -1,9 +1,10 @@
 """GPU parity of the zero-padded linear convolution (Sec. 2.3) and of the
-512- and 1024-point transforms it needs, through the C ABI, against the
-float64 oracle, on power-of-two windows and on the paper's grid shapes.
+larger transforms it needs (512 and 1024 points, and the 3 * 2^a sizes), through
+the C ABI, against the float64 oracle, on power-of-two windows and on the
+paper's grid shapes.
 
 The linear operator pads the object into the periodic grid of the smallest
-power of two holding twice the window, applies the operator of that grid
+transform size holding twice the window, applies the operator of that grid
 and crops the data; the HIP path never stores the
 padding (the transforms skip the zero rows and columns on the way in and the
 cropped ones on the way out).  Bars as in the periodic parity tests: library
@@ -28,14 +29,21 @@ LINEAR = {
     # the paper's grid shapes (wire phantom 202^2, in vivo 384 x 326): rows
     # that are not a multiple of 4 long, 512^2 and 1024^2 transforms
     "wire202": Geometry.paper_like(202, 202, 17, 48, boundary="linear"),
-    "invivo384x326": Geometry.paper_like(384, 326, 4, 24, boundary="linear"),
+    "invivo384x326": Geometry.paper_like(384, 326, 4, 24, boundary="linear"),   # 768^2
+    "w20x40": Geometry.paper_like(20, 40, 6, 30, boundary="linear"),            # 48 x 96
 }
-PERIODIC_512 = {
+PERIODIC_LARGE = {
     "512x16": Geometry(512, 16, 5, 19, 1e-4, 1.2e-4, 1e-4, 2e-8, 1500.0),
     "16x512": Geometry(16, 512, 4, 21, 1e-4, 1e-4, 1e-4, 2e-8, 1500.0),
     "512x512": Geometry.paper_like(512, 512, 4, 24),
     "1024x16": Geometry(1024, 16, 3, 17, 1e-4, 1e-4, 1e-4, 2e-8, 1500.0),
     "16x1024": Geometry(16, 1024, 3, 17, 1e-4, 1e-4, 1e-4, 2e-8, 1500.0),
+    # transform sizes 3 * 2^a (radix-3 stages)
+    "48x96": Geometry(48, 96, 5, 19, 1e-4, 1.2e-4, 1e-4, 2e-8, 1500.0),
+    "192x192": Geometry.paper_like(192, 192, 6, 30),
+    "384x16": Geometry(384, 16, 3, 17, 1e-4, 1e-4, 1e-4, 2e-8, 1500.0),
+    "16x768": Geometry(16, 768, 3, 17, 1e-4, 1e-4, 1e-4, 2e-8, 1500.0),
+    "768x768": Geometry.paper_like(768, 768, 2, 12),
 }
 
 
@@ -134,9 +142,9 @@ def test_linear_fista_matches_oracle_and_rejects_normal_step():
         op.fista_step_normal(x, x, torch.zeros_like(x), [0.0], [tau], [0.0], [True])
 
 
-@pytest.mark.parametrize("name", list(PERIODIC_512))
-def test_periodic_512_point_transforms(name):
-    g = PERIODIC_512[name]
+@pytest.mark.parametrize("name", list(PERIODIC_LARGE))
+def test_periodic_large_and_radix3_transforms(name):
+    g = PERIODIC_LARGE[name]
     op = Operator(g)
     Hh = hlib.H_half(og(g))
     x = inputs.gaussian_random((g.nz, g.ny, g.nx), seed=840)

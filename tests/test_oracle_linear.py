@@ -8,17 +8,20 @@ import numpy as np
 import pytest
 
 from oracle import hlib, operators as ops
-from oracle.geometry import Geometry, doubled, linear_grid, paper_like
+from oracle.geometry import Geometry, doubled, linear_grid, paper_like, transform_sizes
 from paper_2603_28150_amd import inputs
 
 
-@pytest.mark.parametrize("shape", [(8, 8, 3, 12), (8, 4, 2, 9), (4, 8, 3, 7), (6, 5, 3, 10), (5, 7, 2, 9)])
+@pytest.mark.parametrize("shape", [(8, 8, 3, 12), (8, 4, 2, 9), (4, 8, 3, 7), (6, 5, 3, 10), (5, 7, 2, 9),
+                                   (20, 8, 2, 6), (24, 40, 2, 5)])
 def test_linear_fft_form_equals_direct_offset_sums(shape):
     # power-of-two windows on the doubled grid, other windows on the
-    # smallest power-of-two grid holding twice the window
+    # smallest transform size holding twice the window (48 x 16 and 48 x 96
+    # for the last two: periods of the form 3 * 2^a)
     nx, ny, nz, nt = shape
     g = paper_like(nx, ny, nz, nt)
     g2 = linear_grid(g)
+    assert g2.nx >= 2 * nx and g2.ny >= 2 * ny
     if nx & (nx - 1) == 0 and ny & (ny - 1) == 0 and min(nx, ny) >= 8:
         assert g2 == doubled(g)
     Hf2 = hlib.H_full(g2)
@@ -31,6 +34,17 @@ def test_linear_fft_form_equals_direct_offset_sums(shape):
     # the linear operator is not the periodic one of the window
     d_per = ops.A_fft(hlib.H_half(g), x)
     assert np.abs(d_per - d_fft).max() > 1e-3 * np.abs(d_fft).max()
+
+
+def test_linear_grid_sizes_for_the_paper_shapes():
+    # the wire phantom (202^2) and the in vivo grid (384 x 326): the period
+    # holds twice the window, is one of the fast transform sizes, and no
+    # smaller such size would
+    sizes = transform_sizes()
+    for n, want in [(202, 512), (326, 768), (384, 768), (16, 32), (20, 48), (100, 256), (512, 1024)]:
+        p = linear_grid(paper_like(n, n, 1, 2)).nx
+        assert p == want and p >= 2 * n and p in sizes
+        assert not [q for q in sizes if 2 * n <= q < p]
 
 
 def test_linear_adjoint_and_dense_transpose():
