@@ -76,11 +76,12 @@ def doubled(g: Geometry) -> Geometry:
 
 
 def transform_sizes():
-    """Periods the zero-padded convolution may be taken on: 2^a in [16, 1024]
-    and 3 * 2^a in [48, 768] (any period >= 2N keeps every source-sensor
-    offset of an N-point window from wrapping; these are the ones with fast
-    transforms)."""
-    return sorted({2 ** a for a in range(4, 11)} | {3 * 2 ** a for a in range(4, 9)})
+    """Periods the zero-padded convolution may be taken on (any period >= 2N
+    keeps every source-sensor offset of an N-point window from wrapping;
+    these are the ones with fast transforms): 2^a 3^b with b <= 3, multiples
+    of 4 in [16, 1024], and at least 48 when b > 0."""
+    return sorted(v for v in (2 ** a * 3 ** b for a in range(2, 11) for b in range(4))
+                  if 16 <= v <= 1024 and (v & (v - 1) == 0 or v >= 48))
 
 
 def linear_grid(g: Geometry) -> Geometry:

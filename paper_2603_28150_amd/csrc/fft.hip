@@ -1,5 +1,6 @@
-// Batched 2D transverse FFTs (gfx950) for transform sizes 2^a in [16, 1024]
-// and 3 * 2^a in [48, 768].
+// Batched 2D transverse FFTs (gfx950) for the transform sizes 2^a 3^b of
+// PAT_FFT_SIZES: powers of two 16..1024 and 48..864 with b = 1..3 (radix-3
+// stages; every size a multiple of 4 so that rows move as 16-byte units).
 //
 // Step (i) and step (iii) of the FFT realisation of the operator (Sec. 3.2):
 // every depth or time slice is transformed over (x, y).  Each 1D transform
@@ -11,8 +12,8 @@
 //            complex transform;
 //   columns: complex transforms along y on the frequency-major layout, slices
 //            fastest, so that loads and stores are contiguous across threads.
-// Twiddles exp(-2 pi i e / 1024) and exp(-2 pi i e / 768) are tabulated on
-// the host in float64 and rounded once to float32.
+// Twiddles exp(-2 pi i e / 27648) (27648 = 1024 * 27, a multiple of every
+// size) are tabulated on the host in float64 and rounded once to float32.
 //
 // Transform sizes and data extents are separate: slices cover an nx_d x ny_d
 // window of the fx x fy transform grid (nx_d <= fx, ny_d <= fy), sampled at
@@ -21,41 +22,37 @@
 // never read (forward) and never written (inverse), so the zero-padded
 // linear convolution and the scan-grid sampling cost no extra HBM traffic.
 #include <cmath>
+#include <vector>
 
 #include "dft.hpp"
 #include "pat_internal.hpp"
 
 namespace pat {
 
-constexpr int kTwN = 1024;  // largest power-of-two transform size
-constexpr int kTw3N = 768;  // largest transform size 3 * 2^a
-__device__ float2 g_tw[kTwN];
-__device__ float2 g_tw3[kTw3N];
+#define PAT_FFT_SIZES(X) \
+  X(16) X(32) X(48) X(64) X(72) X(96) X(108) X(128) X(144) X(192) X(216) X(256) X(288) X(384) \
+  X(432) X(512) X(576) X(768) X(864) X(1024)
 
-template <int M>
-static void twiddle_table(float2* host) {
-  const double two_pi = 6.283185307179586476925286766559;
-  for (int e = 0; e < M; ++e) {
-    const double a = two_pi * e / (double)M;
-    host[e] = make_float2((float)std::cos(a), (float)-std::sin(a));
-  }
-}
+constexpr int kTwN = 27648;  // multiple of every transform size
+__device__ float2 g_tw[kTwN];
 
 pat_status fft_init_device() {
-  float2 host[kTwN];
-  twiddle_table<kTwN>(host);
-  PAT_HIP(hipMemcpyToSymbol(HIP_SYMBOL(g_tw), host, sizeof(float2) * kTwN, 0, hipMemcpyHostToDevice));
-  twiddle_table<kTw3N>(host);
-  PAT_HIP(hipMemcpyToSymbol(HIP_SYMBOL(g_tw3), host, sizeof(float2) * kTw3N, 0, hipMemcpyHostToDevice));
+  std::vector<float2> host(kTwN);
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int e = 0; e < kTwN; ++e) {
+    const double a = two_pi * e / (double)kTwN;
+    host[e] = make_float2((float)std::cos(a), (float)-std::sin(a));
+  }
+  PAT_HIP(hipMemcpyToSymbol(HIP_SYMBOL(g_tw), host.data(), sizeof(float2) * kTwN, 0, hipMemcpyHostToDevice));
   return PAT_OK;
 }
 
 // exp(DIR 2 pi i e / N), e < N, into LDS
 template <int N, int DIR>
 __device__ __forceinline__ void load_twiddles(float2* tw, int tid, int nthreads) {
-  static_assert(kTwN % N == 0 || kTw3N % N == 0, "no twiddle table for this size");
+  static_assert(kTwN % N == 0, "no twiddles for this size");
   for (int e = tid; e < N; e += nthreads) {
-    const float2 w = kTwN % N == 0 ? g_tw[e * (kTwN / N)] : g_tw3[e * (kTw3N / N)];
+    const float2 w = g_tw[e * (kTwN / N)];
     tw[e] = DIR < 0 ? w : cconj(w);
   }
 }
@@ -67,7 +64,11 @@ __device__ __forceinline__ void load_twiddles(float2* tw, int tid, int nthreads)
 // only rows j = istride*j' with j' < nin are present (the others are zeros),
 // at row j'*nh + m, and only rows p = ostride*p' with p' < nout are written,
 // at row p'*nh + m.
-template <int N> struct ColSB { static constexpr int value = N <= 256 ? 16 : N <= 512 ? 8 : 4; };  // slices per block
+// slices per block, at most 256 threads
+template <int N> struct ColSB {
+  static constexpr int base = N <= 256 ? 16 : N <= 512 ? 8 : 4;
+  static constexpr int value = base * Split<N>::N1 <= 256 ? base : base / 2;
+};
 
 template <int N, int DIR>
 __global__ __launch_bounds__(256) void k_fft_cols(const float2* __restrict__ in,
@@ -390,19 +391,11 @@ static pat_status cols(const float2* in, float2* out, int fy, int nh, int S, int
                        int ostride, hipStream_t st) {
 #define PAT_COLS(N) launch_cols<N, DIR>(in, out, nh, S, rs, imap, omap, nin, istride, nout, ostride, st)
   switch (fy) {
-    case 16: PAT_COLS(16); break;
-    case 32: PAT_COLS(32); break;
-    case 64: PAT_COLS(64); break;
-    case 128: PAT_COLS(128); break;
-    case 256: PAT_COLS(256); break;
-    case 512: PAT_COLS(512); break;
-    case 1024: PAT_COLS(1024); break;
-    case 48: PAT_COLS(48); break;
-    case 96: PAT_COLS(96); break;
-    case 192: PAT_COLS(192); break;
-    case 384: PAT_COLS(384); break;
-    case 768: PAT_COLS(768); break;
-    default: return fail(PAT_EUNSUPPORTED, "transform size along y must be 2^a in [16, 1024] or 3 * 2^a in [48, 768]");
+#define PAT_CASE(N) \
+    case N: PAT_COLS(N); break;
+    PAT_FFT_SIZES(PAT_CASE)
+#undef PAT_CASE
+    default: return fail(PAT_EUNSUPPORTED, "transform size along y is not one of the FFT sizes");
   }
 #undef PAT_COLS
   PAT_LAUNCHED("fft columns");
@@ -448,19 +441,11 @@ pat_status fft2_r2c(const float* f, float2* T, float2* X, int fx, int fy, int nx
   const int rs = spec_stride(S);
   const int nxc = nxw / sx, nyc = nyw / sy;
   switch (fx) {
-    case 16: PAT_ROWS(rows_r2c, 16, f, T, nyc, nxc, sx, S, rs, st); break;
-    case 32: PAT_ROWS(rows_r2c, 32, f, T, nyc, nxc, sx, S, rs, st); break;
-    case 64: PAT_ROWS(rows_r2c, 64, f, T, nyc, nxc, sx, S, rs, st); break;
-    case 128: PAT_ROWS(rows_r2c, 128, f, T, nyc, nxc, sx, S, rs, st); break;
-    case 256: PAT_ROWS(rows_r2c, 256, f, T, nyc, nxc, sx, S, rs, st); break;
-    case 512: PAT_ROWS(rows_r2c, 512, f, T, nyc, nxc, sx, S, rs, st); break;
-    case 1024: PAT_ROWS(rows_r2c, 1024, f, T, nyc, nxc, sx, S, rs, st); break;
-    case 48: PAT_ROWS(rows_r2c, 48, f, T, nyc, nxc, sx, S, rs, st); break;
-    case 96: PAT_ROWS(rows_r2c, 96, f, T, nyc, nxc, sx, S, rs, st); break;
-    case 192: PAT_ROWS(rows_r2c, 192, f, T, nyc, nxc, sx, S, rs, st); break;
-    case 384: PAT_ROWS(rows_r2c, 384, f, T, nyc, nxc, sx, S, rs, st); break;
-    case 768: PAT_ROWS(rows_r2c, 768, f, T, nyc, nxc, sx, S, rs, st); break;
-    default: return fail(PAT_EUNSUPPORTED, "transform size along x must be 2^a in [16, 1024] or 3 * 2^a in [48, 768]");
+#define PAT_CASE(N) \
+    case N: PAT_ROWS(rows_r2c, N, f, T, nyc, nxc, sx, S, rs, st); break;
+    PAT_FFT_SIZES(PAT_CASE)
+#undef PAT_CASE
+    default: return fail(PAT_EUNSUPPORTED, "transform size along x is not one of the FFT sizes");
   }
   PAT_LAUNCHED("fft rows r2c");
   return cols<-1>(T, X, fy, nh, S, rs, nullptr, rowmap, nyc, sy, fy, 1, st);
@@ -477,19 +462,11 @@ pat_status fft2_c2r(const float2* X, float2* T, float* f, int fx, int fy, int nx
   const int nxc = nxw / sx, nyc = nyw / sy;
   PAT_TRY(cols<+1>(X, T, fy, nh, S, rs, rowmap, nullptr, fy, 1, nyc, sy, st));
   switch (fx) {
-    case 16: PAT_ROWS(rows_c2r, 16, T, f, nyc, nxc, sx, S, rs, scale, sub, st); break;
-    case 32: PAT_ROWS(rows_c2r, 32, T, f, nyc, nxc, sx, S, rs, scale, sub, st); break;
-    case 64: PAT_ROWS(rows_c2r, 64, T, f, nyc, nxc, sx, S, rs, scale, sub, st); break;
-    case 128: PAT_ROWS(rows_c2r, 128, T, f, nyc, nxc, sx, S, rs, scale, sub, st); break;
-    case 256: PAT_ROWS(rows_c2r, 256, T, f, nyc, nxc, sx, S, rs, scale, sub, st); break;
-    case 512: PAT_ROWS(rows_c2r, 512, T, f, nyc, nxc, sx, S, rs, scale, sub, st); break;
-    case 1024: PAT_ROWS(rows_c2r, 1024, T, f, nyc, nxc, sx, S, rs, scale, sub, st); break;
-    case 48: PAT_ROWS(rows_c2r, 48, T, f, nyc, nxc, sx, S, rs, scale, sub, st); break;
-    case 96: PAT_ROWS(rows_c2r, 96, T, f, nyc, nxc, sx, S, rs, scale, sub, st); break;
-    case 192: PAT_ROWS(rows_c2r, 192, T, f, nyc, nxc, sx, S, rs, scale, sub, st); break;
-    case 384: PAT_ROWS(rows_c2r, 384, T, f, nyc, nxc, sx, S, rs, scale, sub, st); break;
-    case 768: PAT_ROWS(rows_c2r, 768, T, f, nyc, nxc, sx, S, rs, scale, sub, st); break;
-    default: return fail(PAT_EUNSUPPORTED, "transform size along x must be 2^a in [16, 1024] or 3 * 2^a in [48, 768]");
+#define PAT_CASE(N) \
+    case N: PAT_ROWS(rows_c2r, N, T, f, nyc, nxc, sx, S, rs, scale, sub, st); break;
+    PAT_FFT_SIZES(PAT_CASE)
+#undef PAT_CASE
+    default: return fail(PAT_EUNSUPPORTED, "transform size along x is not one of the FFT sizes");
   }
   PAT_LAUNCHED("fft rows c2r");
   return PAT_OK;

@@ -65,8 +65,15 @@ pat_status hip_check(hipError_t e, const char* what) {
 // ---------------------------------------------------------- geometry rules
 static bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
 
-// transform sizes the FFT kernels provide: 2^a in [16, 1024], 3 * 2^a in [48, 768]
-static bool fft_size(int v) { return pow2_in(v, 16, 1024) || (v % 3 == 0 && pow2_in(v / 3, 16, 256)); }
+// transform sizes the FFT kernels provide: 2^a 3^b, b <= 3, multiples of 4
+// in [16, 1024], at least 48 when b > 0
+static bool fft_size(int v) {
+  static const int sizes[] = {16,  32,  48,  64,  72,  96,  108, 128, 144, 192,
+                              216, 256, 288, 384, 432, 512, 576, 768, 864, 1024};
+  for (int s : sizes)
+    if (v == s) return true;
+  return false;
+}
 
 static int default_nq(const pat_geometry& g) {
   const double reach = std::ceil(g.c * g.dt * (double)(g.nt - 1) / g.dz);
@@ -109,7 +116,8 @@ static pat_status check_geometry(const pat_geometry* g) {
   if (g->boundary != PAT_BOUNDARY_PERIODIC && g->boundary != PAT_BOUNDARY_LINEAR)
     return fail(PAT_EINVAL, "unknown boundary");
   if (g->boundary == PAT_BOUNDARY_PERIODIC && (!fft_size(g->nx) || !fft_size(g->ny)))
-    return fail(PAT_EUNSUPPORTED, "periodic: nx and ny must be transform sizes: 2^a in [16, 1024] or 3 * 2^a in [48, 768]");
+    return fail(PAT_EUNSUPPORTED, "periodic: nx and ny must be transform sizes (16, 32, 48, 64, 72, 96, 108, 128, "
+                                  "144, 192, 216, 256, 288, 384, 432, 512, 576, 768, 864, 1024)");
   if (g->boundary == PAT_BOUNDARY_LINEAR && (g->nx < 4 || g->nx > 512 || g->ny < 1 || g->ny > 512))
     return fail(PAT_EUNSUPPORTED, "linear: nx must be in [4, 512] and ny in [1, 512]");
   if (g->nz > 2048 || g->nt > 2048) return fail(PAT_EUNSUPPORTED, "nz and nt must be <= 2048");

@@ -47,21 +47,16 @@ class Geometry:
         return g
 
 
-def _fft_size(v: int) -> bool:
-    pow2 = lambda u, lo, hi: lo <= u <= hi and u & (u - 1) == 0
-    return pow2(v, 16, 1024) or (v % 3 == 0 and pow2(v // 3, 16, 256))
+# transform sizes of the library's FFTs (include/pat.h, pat_geometry.nx)
+FFT_SIZES = (16, 32, 48, 64, 72, 96, 108, 128, 144, 192, 216, 256, 288, 384, 432, 512, 576, 768, 864, 1024)
 
 
 def transform_size(n: int, boundary: str) -> int:
-    """Transform grid size along one axis: n (periodic), or the smallest
-    transform size (2^a in [16, 1024] or 3 * 2^a in [48, 768]) >= max(16, 2 n)
-    (linear)."""
+    """Transform grid size along one axis: n (periodic), or the smallest of
+    FFT_SIZES >= max(16, 2 n) (linear)."""
     if boundary != "linear":
         return n
-    p = max(16, 2 * n)
-    while not _fft_size(p):
-        p += 1
-    return p
+    return min(p for p in FFT_SIZES if p >= max(16, 2 * n))
 
 
 def _stream(device: torch.device) -> int:

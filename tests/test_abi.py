@@ -54,11 +54,11 @@ def test_host_only_calls(lib):
     radii = {a * a + b * b for a in range(17) for b in range(a, 17)}
     assert hb.value >= len(radii) * 16 * 64 * 4 * 2
     assert hb.value < (len(radii) + 1) * 16 * 64 * 4 * 2 + (1 << 20)
-    for n in (40, 24, 1536, 2048, 8):   # neither 2^a in [16, 1024] nor 3 * 2^a in [48, 768]
+    for n in (40, 24, 54, 36, 1536, 2048, 8, 202):   # not among the transform sizes
         bad = _lib.Geometry(n, 32, 16, 64, 1e-4, 1e-4, 1e-4, 2e-8, 1500.0, 0, 0)
         assert L.pat_H_bytes(ctypes.byref(bad), ctypes.byref(hb), ctypes.byref(sb)) == -2
         assert b"transform sizes" in L.pat_last_error()
-    for n in (48, 96, 384, 768, 16, 1024):
+    for n in (48, 72, 96, 108, 216, 384, 432, 576, 768, 864, 16, 1024):
         ok = _lib.Geometry(n, 32, 16, 64, 1e-4, 1e-4, 1e-4, 2e-8, 1500.0, 0, 0)
         assert L.pat_H_bytes(ctypes.byref(ok), ctypes.byref(hb), ctypes.byref(sb)) == 0
     neg = _lib.Geometry(32, 32, 16, 64, -1e-4, 1e-4, 1e-4, 2e-8, 1500.0, 0, 0)

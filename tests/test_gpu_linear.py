@@ -1,5 +1,5 @@
 """GPU parity of the zero-padded linear convolution (Sec. 2.3) and of the
-larger transforms it needs (512 and 1024 points, and the 3 * 2^a sizes), through
+larger transforms it needs (512 and 1024 points, and the 2^a 3^b sizes), through
 the C ABI, against the float64 oracle, on power-of-two windows and on the
 paper's grid shapes.
 
@@ -28,9 +28,10 @@ LINEAR = {
     "big": Geometry.paper_like(256, 256, 4, 24, boundary="linear"),         # 512^2
     # the paper's grid shapes (wire phantom 202^2, in vivo 384 x 326): rows
     # that are not a multiple of 4 long, 512^2 and 1024^2 transforms
-    "wire202": Geometry.paper_like(202, 202, 17, 48, boundary="linear"),
+    "wire202": Geometry.paper_like(202, 202, 17, 48, boundary="linear"),       # 432^2
     "invivo384x326": Geometry.paper_like(384, 326, 4, 24, boundary="linear"),   # 768^2
     "w20x40": Geometry.paper_like(20, 40, 6, 30, boundary="linear"),            # 48 x 96
+    "w100x30": Geometry.paper_like(100, 30, 5, 24, boundary="linear"),          # 216 x 72
 }
 PERIODIC_LARGE = {
     "512x16": Geometry(512, 16, 5, 19, 1e-4, 1.2e-4, 1e-4, 2e-8, 1500.0),
@@ -44,6 +45,13 @@ PERIODIC_LARGE = {
     "384x16": Geometry(384, 16, 3, 17, 1e-4, 1e-4, 1e-4, 2e-8, 1500.0),
     "16x768": Geometry(16, 768, 3, 17, 1e-4, 1e-4, 1e-4, 2e-8, 1500.0),
     "768x768": Geometry.paper_like(768, 768, 2, 12),
+    # 9 * 2^a and 27 * 2^a (two and three radix-3 stages)
+    "72x108": Geometry(72, 108, 5, 19, 1e-4, 1.2e-4, 1e-4, 2e-8, 1500.0),
+    "144x216": Geometry.paper_like(144, 216, 4, 20),
+    "288x16": Geometry(288, 16, 3, 17, 1e-4, 1e-4, 1e-4, 2e-8, 1500.0),
+    "432x576": Geometry.paper_like(432, 576, 2, 10),
+    "16x864": Geometry(16, 864, 3, 17, 1e-4, 1e-4, 1e-4, 2e-8, 1500.0),
+    "864x32": Geometry(864, 32, 2, 9, 1e-4, 1e-4, 1e-4, 2e-8, 1500.0),
 }
 
 

@@ -13,11 +13,11 @@ from paper_2603_28150_amd import inputs
 
 
 @pytest.mark.parametrize("shape", [(8, 8, 3, 12), (8, 4, 2, 9), (4, 8, 3, 7), (6, 5, 3, 10), (5, 7, 2, 9),
-                                   (20, 8, 2, 6), (24, 40, 2, 5)])
+                                   (20, 8, 2, 6), (24, 40, 2, 5), (36, 4, 1, 4)])
 def test_linear_fft_form_equals_direct_offset_sums(shape):
     # power-of-two windows on the doubled grid, other windows on the
-    # smallest transform size holding twice the window (48 x 16 and 48 x 96
-    # for the last two: periods of the form 3 * 2^a)
+    # smallest transform size holding twice the window (48 x 16, 48 x 96 and
+    # 72 x 16 for the last three: periods 3 * 2^a and 9 * 2^a)
     nx, ny, nz, nt = shape
     g = paper_like(nx, ny, nz, nt)
     g2 = linear_grid(g)
@@ -41,7 +41,7 @@ def test_linear_grid_sizes_for_the_paper_shapes():
     # holds twice the window, is one of the fast transform sizes, and no
     # smaller such size would
     sizes = transform_sizes()
-    for n, want in [(202, 512), (326, 768), (384, 768), (16, 32), (20, 48), (100, 256), (512, 1024)]:
+    for n, want in [(202, 432), (326, 768), (384, 768), (16, 32), (20, 48), (100, 216), (512, 1024), (34, 72)]:
         p = linear_grid(paper_like(n, n, 1, 2)).nx
         assert p == want and p >= 2 * n and p in sizes
         assert not [q for q in sizes if 2 * n <= q < p]
