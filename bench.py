@@ -382,6 +382,29 @@ def forms(op, x, x64, args, samples: dict) -> dict:
         f"contraction {res['linear_contract_GBs']:.0f} GB/s, library {res['linear_library_GiB']:.1f} GiB")
     del ol
     torch.cuda.empty_cache()
+    # the paper's grid shapes on the linear boundary (Sec. 4): the in vivo
+    # 384 x 326 x 96 grid at 50 um (384 samples chosen here) on 768^2
+    # transforms, the wire phantom 202 x 202 x 37 at 10 um (256 samples) on 432^2
+    for name, gp in (("invivo_384x326x96x384", Geometry.paper_like(384, 326, 96, 384, dx=50e-6, boundary="linear")),
+                     ("wire_202x202x37x256", Geometry.paper_like(202, 202, 37, 256, dx=10e-6, boundary="linear"))):
+        t0 = time.perf_counter()
+        op_ = Operator(gp, "f32")
+        torch.cuda.synchronize()
+        build_s = time.perf_counter() - t0
+        inf_ = op_.info()
+        xp = torch.from_numpy(inputs.vascular_phantom(op_.x_shape, seed=4101).astype(np.float32)).cuda()
+        secs, tA, tAT = time_pairs(op_, xp, 5, 2)
+        bp = (contraction_bytes(inf_, op_.nk, gp.nz, gp.nt, False) +
+              contraction_bytes(inf_, op_.nk, gp.nz, gp.nt, True))
+        res[f"{name}_pairs_per_s"] = 5 / secs
+        res[f"{name}_contract_GBs"] = bp / ((tA + tAT) * 1e-3) / 1e9
+        res[f"{name}_library_GiB"] = (inf_["slab_bytes_A"] + inf_["slab_bytes_AT"]) / 2**30
+        res[f"{name}_library_build_s"] = build_s
+        log(f"{name} (linear, {op_.nk} transverse frequencies): {res[f'{name}_pairs_per_s']:.1f} pairs/s, "
+            f"contraction {res[f'{name}_contract_GBs']:.0f} GB/s, library {res[f'{name}_library_GiB']:.1f} GiB, "
+            f"build {build_s:.2f} s")
+        del op_, xp
+        torch.cuda.empty_cache()
     # differentiable form: 200 Adam steps on 1/2 ||A x - y||^2 + 1e-3 TV(x), 128^2 x 64 x 256
     ga = Geometry.paper_like(128, 128, 64, 256)
     oa = Operator(ga, "f32")

@@ -64,14 +64,13 @@ __device__ __forceinline__ void load_twiddles(float2* tw, int tid, int nthreads)
 // only rows j = istride*j' with j' < nin are present (the others are zeros),
 // at row j'*nh + m, and only rows p = ostride*p' with p' < nout are written,
 // at row p'*nh + m.
-// slices per block, at most 256 threads
-template <int N> struct ColSB {
-  static constexpr int base = N <= 256 ? 16 : N <= 512 ? 8 : 4;
-  static constexpr int value = base * Split<N>::N1 <= 256 ? base : base / 2;
-};
+// slices per block: 16 contiguous 8-byte values per spectrum row fill a
+// 128-byte line (8 or 4 slices ran the 512- to 1024-point passes 1.3-1.7x
+// slower); up to 16 * 32 threads and 147 KB of LDS at 1024 points
+template <int N> struct ColSB { static constexpr int value = 16; };
 
 template <int N, int DIR>
-__global__ __launch_bounds__(256) void k_fft_cols(const float2* __restrict__ in,
+__global__ __launch_bounds__(512) void k_fft_cols(const float2* __restrict__ in,
                                                   float2* __restrict__ out, int nh, int S,
                                                   int rs, const int32_t* __restrict__ imap,
                                                   const int32_t* __restrict__ omap, int sfast,
