@@ -21,6 +21,8 @@ namespace pat {
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
+constexpr int kRowParts = 2;  // workgroups per item and object for long rows
+
 template <typename HT> struct Slab;
 
 template <> struct Slab<float> {
@@ -57,8 +59,8 @@ template <> struct Slab<f16_t> {
 // One work item: GG active member slots (GG <= G, the slot count of the
 // spectrum rows).  Uniform per workgroup.
 template <typename HT, int G, int GG, int JPT>
-__device__ __forceinline__ void contract_item(const ContractArgs& a, int lr_log2, int t, int b,
-                                              const int (&kg)[G], float4* smem_raw) {
+__device__ __forceinline__ void contract_item(const ContractArgs& a, int lr_log2, int t, int b, int j0,
+                                              int njl, const int (&kg)[G], float4* smem_raw) {
   typedef Slab<HT> SL;
   typedef typename SL::raw_t raw_t;
   constexpr int VEC = SL::VEC;
@@ -70,8 +72,9 @@ __device__ __forceinline__ void contract_item(const ContractArgs& a, int lr_log2
   const int Lr = 1 << lr_log2, R = 256 >> lr_log2;
   const int lr = tid & (Lr - 1), rg = tid >> lr_log2;
 
-  const HT* slab = reinterpret_cast<const HT*>(a.slab) + (size_t)a.item_slab[t] * a.slab_elems;
-  const int nchunks = (a.nj + VEC - 1) / VEC;
+  // this workgroup's part of the rows: elements j0 .. j0 + njl - 1
+  const HT* slab = reinterpret_cast<const HT*>(a.slab) + (size_t)a.item_slab[t] * a.slab_elems + j0;
+  const int nchunks = (njl + VEC - 1) / VEC;
   bool cl[JPT];
   const HT* colp[JPT];
 #pragma unroll
@@ -105,22 +108,39 @@ __device__ __forceinline__ void contract_item(const ContractArgs& a, int lr_log2
   // member input vectors -> LDS xin[i][g], with the optional per-row scale;
   // 16-byte loads along each member row when the row length is even
   if ((a.ni & 1) == 0) {
+    // batches of kStage loads per thread, all issued before their LDS stores
+    // (one memory latency per batch instead of one per load)
+    constexpr int kStage = 8;
     const int h = a.ni >> 1;
-    for (int idx = tid; idx < GG * h; idx += 256) {
-      const int g = idx / h, i = 2 * (idx - g * h);
-      int k = -1;
+    const int total = GG * h;
+    for (int base = tid; base < total; base += 256 * kStage) {
+      float4 v[kStage];
 #pragma unroll
-      for (int gg = 0; gg < GG; ++gg) k = (gg == g) ? kg[gg] : k;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (k >= 0) {
-        v = *reinterpret_cast<const float4*>(a.in + (size_t)(t * G + g) * a.in_rs + (size_t)b * a.ni + i);
-        if (a.in_scale) {
-          const float s0 = a.in_scale[i], s1 = a.in_scale[i + 1];
-          v = make_float4(v.x * s0, v.y * s0, v.z * s1, v.w * s1);
+      for (int q = 0; q < kStage; ++q) {
+        const int idx = base + q * 256;
+        v[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (idx < total) {
+          const int g = idx / h, i = 2 * (idx - g * h);
+          int k = -1;
+#pragma unroll
+          for (int gg = 0; gg < GG; ++gg) k = (gg == g) ? kg[gg] : k;
+          if (k >= 0)
+            v[q] = *reinterpret_cast<const float4*>(a.in + (size_t)(t * G + g) * a.in_rs + (size_t)b * a.ni + i);
         }
       }
-      xin[i * GG + g] = make_float2(v.x, v.y);
-      xin[(i + 1) * GG + g] = make_float2(v.z, v.w);
+#pragma unroll
+      for (int q = 0; q < kStage; ++q) {
+        const int idx = base + q * 256;
+        if (idx >= total) break;
+        const int g = idx / h, i = 2 * (idx - g * h);
+        float4 w = v[q];
+        if (a.in_scale) {
+          const float s0 = a.in_scale[i], s1 = a.in_scale[i + 1];
+          w = make_float4(w.x * s0, w.y * s0, w.z * s1, w.w * s1);
+        }
+        xin[i * GG + g] = make_float2(w.x, w.y);
+        xin[(i + 1) * GG + g] = make_float2(w.z, w.w);
+      }
     }
   } else {
     for (int idx = tid; idx < a.ni * GG; idx += 256) {
@@ -200,29 +220,29 @@ __device__ __forceinline__ void contract_item(const ContractArgs& a, int lr_log2
 #pragma unroll
       for (int v = 0; v < VEC; ++v) {
         const int j = (lr + jj * Lr) * VEC + v;
-        if (j >= a.nj) continue;
-        const float sc = a.out_scale ? a.out_scale[j] : 1.f;
+        if (j >= njl) continue;
+        const float sc = a.out_scale ? a.out_scale[j0 + j] : 1.f;
 #pragma unroll
         for (int g = 0; g < GG; ++g) {
           const float* p = &acc[((jj * VEC + v) * GG + g) * 2];
-          ob[g * a.nj + j] = make_float2(p[0] * sc, p[1] * sc);
+          ob[g * njl + j] = make_float2(p[0] * sc, p[1] * sc);
         }
       }
     }
   }
   __syncthreads();
-  if ((a.nj & 1) == 0) {
+  if ((njl & 1) == 0 && (a.nj & 1) == 0) {
     // two complex values (16 bytes) per store, non-temporal: the rows are
     // not read again by this kernel
-    const int h = a.nj >> 1;
+    const int h = njl >> 1;
     for (int e = tid; e < GG * h; e += 256) {
       const int g = e / h, j = 2 * (e - g * h);
       int k = -1;
 #pragma unroll
       for (int gg = 0; gg < GG; ++gg) k = (gg == g) ? kg[gg] : k;
       if (k >= 0) {
-        const size_t o = (size_t)(t * G + g) * a.out_rs + (size_t)b * a.nj + j;
-        float4 v = *reinterpret_cast<const float4*>(ob + g * a.nj + j);
+        const size_t o = (size_t)(t * G + g) * a.out_rs + (size_t)b * a.nj + j0 + j;
+        float4 v = *reinterpret_cast<const float4*>(ob + g * njl + j);
         if (a.out_sub) {
           const float4 s = *reinterpret_cast<const float4*>(a.out_sub + o);
           v = make_float4(v.x - s.x, v.y - s.y, v.z - s.z, v.w - s.w);
@@ -231,30 +251,33 @@ __device__ __forceinline__ void contract_item(const ContractArgs& a, int lr_log2
       }
     }
   } else {
-    for (int e = tid; e < GG * a.nj; e += 256) {
-      const int g = e / a.nj, j = e - g * a.nj;
+    for (int e = tid; e < GG * njl; e += 256) {
+      const int g = e / njl, j = e - g * njl;
       int k = -1;
 #pragma unroll
       for (int gg = 0; gg < GG; ++gg) k = (gg == g) ? kg[gg] : k;
       if (k >= 0) {
-        const size_t o = (size_t)(t * G + g) * a.out_rs + (size_t)b * a.nj + j;
+        const size_t o = (size_t)(t * G + g) * a.out_rs + (size_t)b * a.nj + j0 + j;
         a.out[o] = a.out_sub ? csub(ob[e], a.out_sub[o]) : ob[e];
       }
     }
   }
 }
 
-// Workgroups -> (item t, object b).  Workgroups are dealt to the eight XCDs
-// round-robin by index, so for a batch the B objects of one item get indices
-// that are equal modulo 8 and close together: they run on the same XCD at
-// about the same time and share the slab through its L2 instead of each
-// streaming it from HBM.
-__device__ __forceinline__ bool item_of_block(int nitem, int B, int& t, int& b) {
+// Workgroups -> (item t, object b, row part).  Workgroups are dealt to the
+// eight XCDs round-robin by index, so for a batch the B objects of one item
+// get indices that are equal modulo 8 and close together: they run on the
+// same XCD at about the same time and share the slab through its L2 instead
+// of each streaming it from HBM.  One object: JS workgroups per item, each
+// streaming 1/JS of every slab row (shorter workgroups, a shorter tail).
+__device__ __forceinline__ bool item_of_block(int nitem, int B, int JS, int& t, int& b, int& part) {
   if (B == 1) {
-    t = blockIdx.x;
+    t = blockIdx.x / JS;
+    part = blockIdx.x - t * JS;
     b = 0;
     return true;
   }
+  part = 0;
   const int x = blockIdx.x & 7, r = blockIdx.x >> 3;
   b = r % B;
   t = (r / B) * 8 + x;
@@ -262,26 +285,34 @@ __device__ __forceinline__ bool item_of_block(int nitem, int B, int& t, int& b) 
 }
 
 template <typename HT, int G, int JPT>
-__global__ __launch_bounds__(256) void k_contract(ContractArgs a, int lr_log2, int B) {
+__global__ __launch_bounds__(256) void k_contract(ContractArgs a, int lr_log2, int B, int JS, int chpart) {
   extern __shared__ float4 smem_raw[];
-  int t, b;
-  if (!item_of_block(a.nitem, B, t, b)) return;  // whole workgroup: padding of the last XCD round
+  int t, b, part;
+  if (!item_of_block(a.nitem, B, JS, t, b, part)) return;  // whole workgroup: padding of the last XCD round
+  constexpr int VEC = Slab<HT>::VEC;
+  const int j0 = part * chpart * VEC;
+  const int njl = min(a.nj - j0, chpart * VEC);
   int kg[G];
 #pragma unroll
   for (int g = 0; g < G; ++g) kg[g] = a.members[t * G + g];
   if constexpr (G > 4) {
     if (kg[4] < 0) {  // at most four members: the cheaper body
-      contract_item<HT, G, 4, JPT>(a, lr_log2, t, b, kg, smem_raw);
+      contract_item<HT, G, 4, JPT>(a, lr_log2, t, b, j0, njl, kg, smem_raw);
       return;
     }
   }
-  contract_item<HT, G, G, JPT>(a, lr_log2, t, b, kg, smem_raw);
+  contract_item<HT, G, G, JPT>(a, lr_log2, t, b, j0, njl, kg, smem_raw);
 }
 
 template <typename HT, int G>
 static pat_status launch_t(const ContractArgs& a, int B, hipStream_t st) {
   constexpr int VEC = Slab<HT>::VEC;
-  const int nchunks = (a.nj + VEC - 1) / VEC;
+  // one object: rows of 128 or more 16-byte chunks are split over kRowParts
+  // workgroups per item (halves of 1 KB and more still stream well; shorter
+  // parts measured slower)
+  const int JS = (B == 1 && (a.nj + VEC - 1) / VEC >= 128) ? kRowParts : 1;
+  const int chpart = ((a.nj + VEC - 1) / VEC + JS - 1) / JS;  // 16-byte chunks per part
+  const int nchunks = chpart;
   int lr_log2 = 0;
   while ((1 << lr_log2) < nchunks && lr_log2 < 8) ++lr_log2;
   const int Lr = 1 << lr_log2, R = 256 / Lr;
@@ -290,17 +321,17 @@ static pat_status launch_t(const ContractArgs& a, int B, hipStream_t st) {
   const int ns = jpt * VEC * G * 2;
   size_t red_bytes = R > 1 ? (size_t)(R / 2) * Lr * ns * sizeof(float) : 0;
   size_t in_bytes = (size_t)a.ni * G * sizeof(float2);
-  size_t out_bytes = (size_t)a.nj * G * sizeof(float2);
+  size_t out_bytes = (size_t)chpart * VEC * G * sizeof(float2);
   size_t lds = red_bytes > in_bytes ? red_bytes : in_bytes;
   lds = lds > out_bytes ? lds : out_bytes;
   if (lds > 160 * 1024) return fail(PAT_EUNSUPPORTED, "contraction input vector does not fit in LDS");
-  const long long nblk = B == 1 ? a.nitem : (long long)(a.nitem + 7) / 8 * 8 * B;
+  const long long nblk = B == 1 ? (long long)a.nitem * JS : (long long)(a.nitem + 7) / 8 * 8 * B;
   if (nblk > 0x7fffffffLL) return fail(PAT_EUNSUPPORTED, "contraction grid too large");
   dim3 grid((unsigned)nblk);
   if (jpt == 1)
-    k_contract<HT, G, 1><<<grid, 256, lds, st>>>(a, lr_log2, B);
+    k_contract<HT, G, 1><<<grid, 256, lds, st>>>(a, lr_log2, B, JS, chpart);
   else
-    k_contract<HT, G, 2><<<grid, 256, lds, st>>>(a, lr_log2, B);
+    k_contract<HT, G, 2><<<grid, 256, lds, st>>>(a, lr_log2, B, JS, chpart);
   PAT_LAUNCHED("contraction");
   return PAT_OK;
 }

@@ -95,3 +95,20 @@ def test_big_float32_batch_of_16(big):
         Go = ops.AT_at_freqs(Hk, rs[i], M, P)
         assert np.linalg.norm(Gg - Go) / np.linalg.norm(Go) < 1e-5, b
     assert np.abs(gs[1]).max() == 0.0                # zero data, zero image
+
+
+def test_paper_in_vivo_grid_full_size():
+    # the in vivo grid of the paper (384 x 326 x 96 at 50 um, 384 samples here)
+    # on the linear boundary, 768^2 transforms, as the benchmark runs it: the
+    # adjoint identity with float64 dots, and one object of a batch of 2
+    # (matrix cores) against the same object alone (VALU kernel)
+    g = Geometry.paper_like(384, 326, 96, 384, dx=50e-6, boundary="linear")
+    op = Operator(g)
+    assert op.nk == 768 * 385
+    x = torch.from_numpy(inputs.vascular_phantom(op.x_shape, seed=95).astype(np.float32)).cuda()
+    y = torch.from_numpy(inputs.gaussian_random(op.d_shape, seed=96).astype(np.float32)).cuda()
+    assert op.adjoint_check(x, y) < 1e-5
+    x2 = torch.stack([x, torch.flip(x, dims=(0,))])
+    y2 = op.apply_A(x2)
+    y1 = op.apply_A(x)
+    assert float(torch.linalg.norm(y2[0] - y1) / torch.linalg.norm(y1)) < 1e-5
