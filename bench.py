@@ -336,6 +336,12 @@ def main():
                    "stage_ms": dict(zip(["spectrum_z", "contract_A", "inverse_spectrum_t",
                                          "spectrum_t", "contract_AT", "inverse_spectrum_z"],
                                         [float(v) for v in tp["stage_ms"]]))},
+        # the paper's own speed figures, with the hardware it states (context,
+        # not a baseline for this metric: other machine, other workload)
+        "paper_context": {"claim": "forward operator two to three orders of magnitude faster than a k-Wave "
+                                   "solve; 256^3 grid, 1000 time steps: ~1e3 s (k-Wave) vs a few s",
+                          "hardware": "MATLAB, CPU only, 2x AMD EPYC 7662 (2x64 cores), 2 TiB RAM",
+                          "source": "Sec. 3.2 (runtime comparison, Fig. 2)"},
     }
 
     samples = {}
@@ -440,7 +446,7 @@ def forms(op, x, x64, args, samples: dict) -> dict:
         f"contraction {res['linear_contract_GBs']:.0f} GB/s, library {res['linear_library_GiB']:.1f} GiB")
     del ol
     torch.cuda.empty_cache()
-    # the paper's grid shapes on the linear boundary (Sec. 4): the in vivo
+    # the paper's grid shapes on the linear boundary (Sec. 3.3-3.4): the in vivo
     # 384 x 326 x 96 grid at 50 um (384 samples chosen here) on 768^2
     # transforms, the wire phantom 202 x 202 x 37 at 10 um (256 samples) on 432^2
     for name, gp in (("invivo_384x326x96x384", Geometry.paper_like(384, 326, 96, 384, dx=50e-6, boundary="linear")),
