@@ -32,6 +32,9 @@ LINEAR = {
     "invivo384x326": Geometry.paper_like(384, 326, 4, 24, boundary="linear"),   # 768^2
     "w20x40": Geometry.paper_like(20, 40, 6, 30, boundary="linear"),            # 48 x 96
     "w100x30": Geometry.paper_like(100, 30, 5, 24, boundary="linear"),          # 216 x 72
+    # smallest windows: a 4-point line of sensors (16 x 16 transforms), 5 x 3
+    "line4x1": Geometry(4, 1, 3, 9, 1e-4, 1e-4, 1e-4, 2e-8, 1500.0, 0, "linear"),
+    "w5x3": Geometry(5, 3, 2, 7, 1e-4, 1.1e-4, 1e-4, 2e-8, 1500.0, 0, "linear"),
 }
 PERIODIC_LARGE = {
     "512x16": Geometry(512, 16, 5, 19, 1e-4, 1.2e-4, 1e-4, 2e-8, 1500.0),

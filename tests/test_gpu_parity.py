@@ -295,7 +295,7 @@ def test_stage_calls_compose_apply_and_row_map(name):
 
 
 @pytest.mark.parametrize("kind", ["bf16", "f16"])
-@pytest.mark.parametrize("name,B", [("tiny", 16), ("ragged", 3), ("mid", 2)])
+@pytest.mark.parametrize("name,B", [("tiny", 16), ("ragged", 3), ("mid", 2), ("tiny", 19)])
 def test_quantised_batched_matrix_core_path(kind, name, B):
     # 16-bit libraries run batches on the matrix cores; every object of a
     # batch must match the oracle applying the same quantised library (2e-5)
@@ -321,13 +321,14 @@ def test_quantised_batched_matrix_core_path(kind, name, B):
     assert op.adjoint_check(dev(xs[0]), dev(ds[0])) < 1e-5
 
 
-@pytest.mark.parametrize("name,B", [("tiny", 16), ("ragged", 4), ("mid", 5), ("ragged", 2)])
+@pytest.mark.parametrize("name,B", [("tiny", 16), ("ragged", 4), ("mid", 5), ("ragged", 2), ("tiny", 9), ("mid", 11)])
 def test_float32_batched_path(name, B):
     # float32 batches run on the matrix cores (library rows split into three
     # bf16 terms, spectra into two): every object matches the oracle to the
     # float32 bar, and its own single-object apply (the VALU kernel) to 1e-5;
     # the ragged shapes (13 and 37 along k) end in a partial k-step, the mid
-    # one spans two k-chunks for A^T
+    # one spans two k-chunks for A^T; 9 and 11 objects (72 and 88 member-object
+    # pairs) need a second, partial column group of 64 pairs
     g, op, Hh = setup(name)
     xs = np.stack([inputs.gaussian_blobs((g.nz, g.ny, g.nx), seed=500 + b) for b in range(B)])
     ds = np.stack([inputs.gaussian_random((g.nt, g.ny, g.nx), seed=600 + b) for b in range(B)])
