@@ -9,7 +9,8 @@ in HBM.  Each apply is issued as its three steps through the C ABI
 launches) so that HIP events around the contraction, the dominant kernel,
 give its duration inside the timed region.
 
-Prints ONE JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
+Prints ONE JSON line.  `--gpus N` with N > 1 exits: the operator runs on one GPU
+(the multi-GPU sharding is a design note, not code).
 """
 from __future__ import annotations
 
@@ -273,7 +274,7 @@ def main():
                     help="also run a device copy of 1 GiB (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU; --gpus must be 1", file=sys.stderr)
+        print("bench.py: the operator runs on one GPU only (no multi-GPU path); --gpus must be 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
