@@ -3,7 +3,7 @@
 Test infrastructure only (see ``oracle/__init__``).
 
 The paper stores its operator in single-precision complex form (Sec. 4);
-the 16-bit forms are this build's precision variants.  For each depth l,
+the 16-bit forms are precision variants the paper does not have.  For each depth l,
 s_l = 2^(e - ceil(log2 max_{k,n} |H^[k,l,n]|)) with e = 0 for bfloat16 and
 e = 15 for float16; the stored value is H_q = round16(round32(H^ * s_l)),
 both roundings to nearest-even, and the dequantised value H_q / s_l is
