@@ -12,8 +12,8 @@
 //            complex transform;
 //   columns: complex transforms along y on the frequency-major layout, slices
 //            fastest, so that loads and stores are contiguous across threads.
-// Twiddles exp(-2 pi i e / 27648) (27648 = 1024 * 27, a multiple of every
-// size) are tabulated on the host in float64 and rounded once to float32.
+// Twiddles exp(-2 pi i e / N) of every size N are tabulated on the host in
+// float64 and rounded once to float32.
 //
 // Transform sizes and data extents are separate: slices cover an nx_d x ny_d
 // window of the fx x fy transform grid (nx_d <= fx, ny_d <= fy), sampled at
@@ -33,26 +33,47 @@ namespace pat {
   X(16) X(32) X(48) X(64) X(72) X(96) X(108) X(128) X(144) X(192) X(216) X(256) X(288) X(384) \
   X(432) X(512) X(576) X(768) X(864) X(1024)
 
-constexpr int kTwN = 27648;  // multiple of every transform size
-__device__ float2 g_tw[kTwN];
+#define PAT_SIZE_ENTRY(N) N,
+constexpr int kFftSizes[] = {PAT_FFT_SIZES(PAT_SIZE_ENTRY)};
+#undef PAT_SIZE_ENTRY
+
+// twiddles of every size, one contiguous table per size (a block reads its
+// N values as whole cache lines)
+constexpr int tw_offset(int n) {
+  int o = 0;
+  for (int s : kFftSizes) {
+    if (s == n) return o;
+    o += s;
+  }
+  return -1;
+}
+constexpr int tw_total() {
+  int o = 0;
+  for (int s : kFftSizes) o += s;
+  return o;
+}
+__device__ float2 g_tw[tw_total()];
 
 pat_status fft_init_device() {
-  std::vector<float2> host(kTwN);
+  std::vector<float2> host(tw_total());
   const double two_pi = 6.283185307179586476925286766559;
-  for (int e = 0; e < kTwN; ++e) {
-    const double a = two_pi * e / (double)kTwN;
-    host[e] = make_float2((float)std::cos(a), (float)-std::sin(a));
-  }
-  PAT_HIP(hipMemcpyToSymbol(HIP_SYMBOL(g_tw), host.data(), sizeof(float2) * kTwN, 0, hipMemcpyHostToDevice));
+  for (int n : kFftSizes)
+    for (int e = 0; e < n; ++e) {
+      const double a = two_pi * e / (double)n;
+      host[tw_offset(n) + e] = make_float2((float)std::cos(a), (float)-std::sin(a));
+    }
+  PAT_HIP(hipMemcpyToSymbol(HIP_SYMBOL(g_tw), host.data(), sizeof(float2) * host.size(), 0,
+                            hipMemcpyHostToDevice));
   return PAT_OK;
 }
 
 // exp(DIR 2 pi i e / N), e < N, into LDS
 template <int N, int DIR>
 __device__ __forceinline__ void load_twiddles(float2* tw, int tid, int nthreads) {
-  static_assert(kTwN % N == 0, "no twiddles for this size");
+  constexpr int off = tw_offset(N);
+  static_assert(off >= 0, "no twiddles for this size");
   for (int e = tid; e < N; e += nthreads) {
-    const float2 w = g_tw[e * (kTwN / N)];
+    const float2 w = g_tw[off + e];
     tw[e] = DIR < 0 ? w : cconj(w);
   }
 }
