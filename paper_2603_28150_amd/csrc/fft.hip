@@ -157,7 +157,10 @@ __global__ __launch_bounds__(256) void k_fft_rows_r2c(const float* __restrict__ 
                                                       float2* __restrict__ T, int ny, int nxd,
                                                       int sx, int S, int rs) {
   constexpr int N1 = Split<N>::N1, N2 = Split<N>::N2;
-  constexpr int PAD = N + 1;
+  // per packed sequence: N values in natural order, or the N2 x N1 exchange
+  // with rows padded to N1 + 1 (lanes write their N1 outputs to separate banks)
+  constexpr int PX = Split<N>::N1 + 1;
+  constexpr int PAD = Split<N>::N2 * PX + 1;
   constexpr int NT = Q * N1;
   constexpr int NH = N / 2 + 1;
   __shared__ float2 tw[N];
@@ -223,12 +226,12 @@ __global__ __launch_bounds__(256) void k_fft_rows_r2c(const float* __restrict__ 
   if (t < N2) {
     dft<N1, -1>(v);
 #pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) ex[q * PAD + t * N1 + k1] = cmul(v[k1], tw[t * k1]);
+    for (int k1 = 0; k1 < N1; ++k1) ex[q * PAD + t * PX + k1] = cmul(v[k1], tw[t * k1]);
   }
   __syncthreads();
   float2 w[N2];
 #pragma unroll
-  for (int n2 = 0; n2 < N2; ++n2) w[n2] = ex[q * PAD + n2 * N1 + t];
+  for (int n2 = 0; n2 < N2; ++n2) w[n2] = ex[q * PAD + n2 * PX + t];
   dft<N2, -1>(w);
   __syncthreads();
 #pragma unroll
@@ -264,7 +267,8 @@ __global__ __launch_bounds__(256) void k_fft_rows_c2r(const float2* __restrict__
                                                       int sx, int S, int rs, float scale,
                                                       const float* __restrict__ sub) {
   constexpr int N1 = Split<N>::N1, N2 = Split<N>::N2;
-  constexpr int PAD = N + 1;
+  constexpr int PX = Split<N>::N1 + 1;  // exchange row stride, see k_fft_rows_r2c
+  constexpr int PAD = Split<N>::N2 * PX + 1;
   constexpr int NT = Q * N1;
   constexpr int NH = N / 2 + 1;
   constexpr int BUF0 = (2 * Q * NH > Q * PAD) ? 2 * Q * NH : Q * PAD;
@@ -317,12 +321,12 @@ __global__ __launch_bounds__(256) void k_fft_rows_c2r(const float2* __restrict__
   __syncthreads();
   if (t < N2) {
 #pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) buf[q * PAD + t * N1 + k1] = v[k1];
+    for (int k1 = 0; k1 < N1; ++k1) buf[q * PAD + t * PX + k1] = v[k1];
   }
   __syncthreads();
   float2 w[N2];
 #pragma unroll
-  for (int n2 = 0; n2 < N2; ++n2) w[n2] = buf[q * PAD + n2 * N1 + t];
+  for (int n2 = 0; n2 < N2; ++n2) w[n2] = buf[q * PAD + n2 * PX + t];
   dft<N2, +1>(w);
   __syncthreads();
   // real rows 2q (re) and 2q+1 (im) into LDS, then 16-byte row stores
