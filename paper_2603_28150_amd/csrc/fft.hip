@@ -396,6 +396,246 @@ __global__ __launch_bounds__(256) void k_fft_rows_c2r(const float2* __restrict__
   }
 }
 
+// ------------------------------------------------- chirp-z (Bluestein) sizes
+// A transform length N that is not among the fast sizes (even, 16..512) runs
+// as a circular convolution of length M, a power of two >= 2N - 1.  With
+// c[n] = exp(i pi n^2 / N):
+//   forward  X[k] = conj(c[k]) sum_n (x[n] conj(c[n])) c[k - n]
+//   inverse  x[n] = c[n] sum_k (X[k] c[k]) conj(c[n - k])
+// (from 2nk = n^2 + k^2 - (k - n)^2).  The convolution is an M-point forward
+// FFT, a product with the M-point DFT of the chirp kernel (tabulated on the
+// host in float64 with 1/M folded in; the kernel is even, so the inverse
+// direction uses its conjugate), and an M-point inverse FFT.
+
+// In-place M-point FFT of one LDS sequence, natural order in and out; t <
+// Split<M>::N1 is the thread's index within its sequence.  Every thread of the
+// block calls it (it synchronises the block).
+template <int M, int DIR>
+__device__ __forceinline__ void lds_fft(float2* seq, const float2* tw, int t) {
+  constexpr int N1 = Split<M>::N1, N2 = Split<M>::N2, PX = N1 + 1;
+  float2 v[N1];
+  if (t < N2) {
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) v[n1] = seq[t + N2 * n1];
+    dft<N1, DIR>(v);
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) v[k1] = cmul(v[k1], DIR < 0 ? tw[t * k1] : cconj(tw[t * k1]));
+  }
+  __syncthreads();
+  if (t < N2) {
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) seq[t * PX + k1] = v[k1];
+  }
+  __syncthreads();
+  float2 w[N2];
+#pragma unroll
+  for (int n2 = 0; n2 < N2; ++n2) w[n2] = seq[n2 * PX + t];
+  dft<N2, DIR>(w);
+  __syncthreads();
+#pragma unroll
+  for (int k2 = 0; k2 < N2; ++k2) seq[t + N1 * k2] = w[k2];
+  __syncthreads();
+}
+
+constexpr int kChirpMaxN = 512;  // longest chirp-z transform
+
+// rows, r2c, length N by chirp-z: the 2Q real rows of slices s0.. at row j
+// (f[s][ny][N]) packed in pairs as in k_fft_rows_r2c; T as there
+template <int M, int Q>
+__global__ __launch_bounds__(256) void k_fft_rows_r2c_cz(const float* __restrict__ f,
+                                                         float2* __restrict__ T, int ny, int N,
+                                                         int S, int rs, const float2* __restrict__ cz,
+                                                         const float2* __restrict__ bz) {
+  constexpr int N1 = Split<M>::N1, N2 = Split<M>::N2, PX = N1 + 1;
+  constexpr int PAD = N2 * PX + 1;
+  constexpr int NT = Q * N1;  // Q * M = N2 * NT elements, N2 per thread
+  __shared__ float2 tw[M];
+  __shared__ float2 ex[Q * PAD];
+  const int tid = threadIdx.x;
+  const int t = tid % N1, q = tid / N1;
+  const int j = blockIdx.x;
+  const int s0 = blockIdx.y * 2 * Q;
+  const int NH = N / 2 + 1;
+  load_twiddles<M, -1>(tw, tid, NT);
+  float2 z[N2];
+#pragma unroll
+  for (int it = 0; it < N2; ++it) {
+    const int e = tid + it * NT;
+    const int qq = e / M, n = e % M;
+    const int s = s0 + 2 * qq;
+    float a = 0.f, b = 0.f;
+    if (n < N) {
+      if (s < S) a = f[((size_t)s * ny + j) * N + n];
+      if (s + 1 < S) b = f[((size_t)(s + 1) * ny + j) * N + n];
+    }
+    z[it] = make_float2(a, b);
+  }
+#pragma unroll
+  for (int it = 0; it < N2; ++it) {
+    const int e = tid + it * NT;
+    const int qq = e / M, n = e % M;
+    ex[qq * PAD + n] = n < N ? cmul(z[it], cconj(cz[n])) : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  lds_fft<M, -1>(ex + q * PAD, tw, t);
+  for (int e = tid; e < Q * M; e += NT) {
+    const int qq = e / M, n = e % M;
+    ex[qq * PAD + n] = cmul(ex[qq * PAD + n], bz[n]);
+  }
+  __syncthreads();
+  lds_fft<M, +1>(ex + q * PAD, tw, t);
+  for (int e = tid; e < Q * N; e += NT) {
+    const int qq = e / N, n = e % N;
+    ex[qq * PAD + n] = cmul(ex[qq * PAD + n], cconj(cz[n]));
+  }
+  __syncthreads();
+  // separate the two packed real transforms and store slice-fastest
+  for (int idx = tid; idx < NH * 2 * Q; idx += NT) {
+    const int m = idx / (2 * Q), sl = idx % (2 * Q);
+    const int s = s0 + sl;
+    if (s >= S) continue;
+    const int qq = sl >> 1;
+    const float2 zm = ex[qq * PAD + m];
+    const float2 zc = cconj(ex[qq * PAD + (m == 0 ? 0 : N - m)]);
+    float2 r;
+    if ((sl & 1) == 0) {
+      r = make_float2(0.5f * (zm.x + zc.x), 0.5f * (zm.y + zc.y));
+    } else {
+      const float2 d = csub(zm, zc);
+      r = make_float2(0.5f * d.y, -0.5f * d.x);
+    }
+    T[(size_t)(j * NH + m) * rs + s] = r;
+  }
+}
+
+// rows, c2r, length N by chirp-z: f = scale * (real rows of the Hermitian
+// half spectra in T) - sub, as k_fft_rows_c2r without sampling
+template <int M, int Q>
+__global__ __launch_bounds__(256) void k_fft_rows_c2r_cz(const float2* __restrict__ T,
+                                                         float* __restrict__ f, int ny, int N, int S,
+                                                         int rs, float scale,
+                                                         const float* __restrict__ sub,
+                                                         const float2* __restrict__ cz,
+                                                         const float2* __restrict__ bz) {
+  constexpr int N1 = Split<M>::N1, N2 = Split<M>::N2, PX = N1 + 1;
+  constexpr int PAD = N2 * PX + 1;
+  constexpr int NT = Q * N1;
+  constexpr int NHMAX = kChirpMaxN / 2 + 1;
+  __shared__ float2 tw[M];
+  __shared__ float2 ex[Q * PAD];
+  __shared__ float2 hb[2 * Q * NHMAX];
+  const int tid = threadIdx.x;
+  const int t = tid % N1, q = tid / N1;
+  const int j = blockIdx.x;
+  const int s0 = blockIdx.y * 2 * Q;
+  const int NH = N / 2 + 1;
+  for (int idx = tid; idx < NH * 2 * Q; idx += NT) {
+    const int m = idx / (2 * Q), sl = idx % (2 * Q);
+    const int s = s0 + sl;
+    float2 F = s < S ? T[(size_t)(j * NH + m) * rs + s] : make_float2(0.f, 0.f);
+    if (m == 0 || m == N / 2) F.y = 0.f;
+    hb[sl * NH + m] = F;
+  }
+  load_twiddles<M, -1>(tw, tid, NT);
+  __syncthreads();
+  // z = Fa + i Fb over the full period (Hermitian extension), times c
+  for (int e = tid; e < Q * M; e += NT) {
+    const int qq = e / M, i = e % M;
+    float2 v = make_float2(0.f, 0.f);
+    if (i < N) {
+      float2 fa, fb;
+      if (i <= N / 2) {
+        fa = hb[(2 * qq) * NH + i];
+        fb = hb[(2 * qq + 1) * NH + i];
+      } else {
+        fa = cconj(hb[(2 * qq) * NH + N - i]);
+        fb = cconj(hb[(2 * qq + 1) * NH + N - i]);
+      }
+      v = cmul(make_float2(fa.x - fb.y, fa.y + fb.x), cz[i]);
+    }
+    ex[qq * PAD + i] = v;
+  }
+  __syncthreads();
+  lds_fft<M, -1>(ex + q * PAD, tw, t);
+  for (int e = tid; e < Q * M; e += NT) {
+    const int qq = e / M, n = e % M;
+    ex[qq * PAD + n] = cmul(ex[qq * PAD + n], cconj(bz[n]));
+  }
+  __syncthreads();
+  lds_fft<M, +1>(ex + q * PAD, tw, t);
+  // real rows 2q (re) and 2q+1 (im)
+  for (int e = tid; e < Q * N; e += NT) {
+    const int qq = e / N, n = e % N;
+    const int s = s0 + 2 * qq;
+    const float2 v = cmul(ex[qq * PAD + n], cz[n]);
+    if (s < S) {
+      const size_t o = ((size_t)s * ny + j) * N + n;
+      f[o] = v.x * scale - (sub ? sub[o] : 0.f);
+    }
+    if (s + 1 < S) {
+      const size_t o = ((size_t)(s + 1) * ny + j) * N + n;
+      f[o] = v.y * scale - (sub ? sub[o] : 0.f);
+    }
+  }
+}
+
+// columns, length N by chirp-z: out[orow(p)*rs + s] = sum_j exp(DIR 2 pi i p j / N)
+// in[irow(j)*rs + s], maps as in k_fft_cols (full columns, no strides)
+template <int M, int DIR>
+__global__ __launch_bounds__(512) void k_fft_cols_cz(const float2* __restrict__ in,
+                                                     float2* __restrict__ out, int nh, int S, int rs,
+                                                     const int32_t* __restrict__ imap,
+                                                     const int32_t* __restrict__ omap, int sfast,
+                                                     int N, const float2* __restrict__ cz,
+                                                     const float2* __restrict__ bz) {
+  constexpr int N1 = Split<M>::N1, N2 = Split<M>::N2, PX = N1 + 1;
+  constexpr int SB = 16;
+  constexpr int PAD = N2 * PX + 1;
+  constexpr int NT = SB * N1;
+  __shared__ float2 tw[M];
+  __shared__ float2 ex[SB * PAD];
+  __shared__ int rin[kChirpMaxN], rout[kChirpMaxN];
+  const int tid = threadIdx.x;
+  const int s = tid % SB, t = tid / SB;
+  const int m = sfast ? blockIdx.y : blockIdx.x;
+  const int sg = (sfast ? blockIdx.x : blockIdx.y) * SB + s;
+  const bool live = sg < S;
+  load_twiddles<M, -1>(tw, tid, NT);
+  for (int y = tid; y < N; y += NT) {
+    rin[y] = imap ? imap[y * nh + m] : y * nh + m;
+    rout[y] = omap ? omap[y * nh + m] : y * nh + m;
+  }
+  __syncthreads();
+  float2 z[N2];  // y = t + N1 * i, i < N2 covers the period
+#pragma unroll
+  for (int i = 0; i < N2; ++i) {
+    const int y = t + N1 * i;
+    z[i] = (live && y < N && rin[y] >= 0) ? in[(size_t)rin[y] * rs + sg] : make_float2(0.f, 0.f);
+  }
+#pragma unroll
+  for (int i = 0; i < N2; ++i) {
+    const int y = t + N1 * i;
+    ex[s * PAD + y] = y < N ? cmul(z[i], DIR < 0 ? cconj(cz[y]) : cz[y]) : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  lds_fft<M, -1>(ex + s * PAD, tw, t);
+#pragma unroll
+  for (int i = 0; i < N2; ++i) {
+    const int y = t + N1 * i;
+    ex[s * PAD + y] = cmul(ex[s * PAD + y], DIR < 0 ? bz[y] : cconj(bz[y]));
+  }
+  __syncthreads();
+  lds_fft<M, +1>(ex + s * PAD, tw, t);
+  if (live) {
+#pragma unroll
+    for (int i = 0; i < N2; ++i) {
+      const int p = t + N1 * i;
+      if (p < N && rout[p] >= 0)
+        out[(size_t)rout[p] * rs + sg] = cmul(ex[s * PAD + p], DIR < 0 ? cconj(cz[p]) : cz[p]);
+    }
+  }
+}
+
 // ------------------------------------------------------------- launchers
 template <int N, int DIR>
 static void launch_cols(const float2* in, float2* out, int nh, int S, int rs, const int32_t* imap,
@@ -456,14 +696,73 @@ static bool extents_ok(int fx, int fy, int nxw, int nyw, int sx, int sy) {
   return nxw / sx >= 1 && nyw / sy >= 1;
 }
 
+template <int M, int Q>
+static void rows_r2c_cz(const float* f, float2* T, int ny, int N, int S, int rs, const float2* cz,
+                        const float2* bz, hipStream_t st) {
+  dim3 grid(ny, (S + 2 * Q - 1) / (2 * Q));
+  k_fft_rows_r2c_cz<M, Q><<<grid, Q * Split<M>::N1, 0, st>>>(f, T, ny, N, S, rs, cz, bz);
+}
+
+template <int M, int Q>
+static void rows_c2r_cz(const float2* T, float* f, int ny, int N, int S, int rs, float scale,
+                        const float* sub, const float2* cz, const float2* bz, hipStream_t st) {
+  dim3 grid(ny, (S + 2 * Q - 1) / (2 * Q));
+  k_fft_rows_c2r_cz<M, Q><<<grid, Q * Split<M>::N1, 0, st>>>(T, f, ny, N, S, rs, scale, sub, cz, bz);
+}
+
+template <int M, int DIR>
+static void launch_cols_cz(const float2* in, float2* out, int nh, int S, int rs, const int32_t* imap,
+                           const int32_t* omap, int N, const float2* cz, const float2* bz,
+                           hipStream_t st) {
+  constexpr int SB = 16;
+  const int sfast = S >= 2048;
+  const int nsb = (S + SB - 1) / SB;
+  dim3 grid = sfast ? dim3(nsb, nh) : dim3(nh, nsb);
+  k_fft_cols_cz<M, DIR><<<grid, SB * Split<M>::N1, 0, st>>>(in, out, nh, S, rs, imap, omap, sfast, N,
+                                                            cz, bz);
+}
+
+#define PAT_CHIRP_M(X) X(64) X(128) X(256) X(512) X(1024)
+
+template <int DIR>
+static pat_status cols_cz(const float2* in, float2* out, int fy, int nh, int S, int rs,
+                          const int32_t* imap, const int32_t* omap, const float2* cz, const float2* bz,
+                          int M, hipStream_t st) {
+  if (fy > kChirpMaxN || 2 * fy - 1 > M) return fail(PAT_EINVAL, "chirp-z: table length does not fit");
+  switch (M) {
+#define PAT_CASE(MM) \
+    case MM: launch_cols_cz<MM, DIR>(in, out, nh, S, rs, imap, omap, fy, cz, bz, st); break;
+    PAT_CHIRP_M(PAT_CASE)
+#undef PAT_CASE
+    default: return fail(PAT_EUNSUPPORTED, "chirp-z convolution length must be a power of two in [64, 1024]");
+  }
+  PAT_LAUNCHED("fft columns (chirp-z)");
+  return PAT_OK;
+}
+
 pat_status fft2_r2c(const float* f, float2* T, float2* X, int fx, int fy, int nxw, int nyw, int sx,
-                    int sy, int S, const int32_t* rowmap, hipStream_t st) {
+                    int sy, int S, const int32_t* rowmap, const FftChirp& ch, hipStream_t st) {
   if (S <= 0) return PAT_OK;
   if (!extents_ok(fx, fy, nxw, nyw, sx, sy))
     return fail(PAT_EINVAL, "fft: data extent or sampling does not fit the transform");
   const int nh = fx / 2 + 1;
   const int rs = spec_stride(S);
   const int nxc = nxw / sx, nyc = nyw / sy;
+  if ((ch.mx && (nxw != fx || sx != 1)) || (ch.my && (nyw != fy || sy != 1)))
+    return fail(PAT_EUNSUPPORTED, "fft: chirp-z axes take whole, unsampled slices");
+  if (ch.mx) {
+    if (fx > kChirpMaxN || 2 * fx - 1 > ch.mx) return fail(PAT_EINVAL, "chirp-z: table length does not fit");
+    switch (ch.mx) {
+#define PAT_CASE(MM) \
+      case MM: rows_r2c_cz<MM, kRowQ>(f, T, nyc, fx, S, rs, ch.cx, ch.bx, st); break;
+      PAT_CHIRP_M(PAT_CASE)
+#undef PAT_CASE
+      default: return fail(PAT_EUNSUPPORTED, "chirp-z convolution length must be a power of two in [64, 1024]");
+    }
+    PAT_LAUNCHED("fft rows r2c (chirp-z)");
+    if (ch.my) return cols_cz<-1>(T, X, fy, nh, S, rs, nullptr, rowmap, ch.cy, ch.by, ch.my, st);
+    return cols<-1>(T, X, fy, nh, S, rs, nullptr, rowmap, nyc, sy, fy, 1, st);
+  }
   switch (fx) {
 #define PAT_CASE(N) \
     case N: PAT_ROWS(rows_r2c, N, f, T, nyc, nxc, sx, S, rs, st); break;
@@ -472,19 +771,37 @@ pat_status fft2_r2c(const float* f, float2* T, float2* X, int fx, int fy, int nx
     default: return fail(PAT_EUNSUPPORTED, "transform size along x is not one of the FFT sizes");
   }
   PAT_LAUNCHED("fft rows r2c");
+  if (ch.my) return cols_cz<-1>(T, X, fy, nh, S, rs, nullptr, rowmap, ch.cy, ch.by, ch.my, st);
   return cols<-1>(T, X, fy, nh, S, rs, nullptr, rowmap, nyc, sy, fy, 1, st);
 }
 
 pat_status fft2_c2r(const float2* X, float2* T, float* f, int fx, int fy, int nxw, int nyw, int sx,
                     int sy, int S, float scale, const float* sub, const int32_t* rowmap,
-                    hipStream_t st) {
+                    const FftChirp& ch, hipStream_t st) {
   if (S <= 0) return PAT_OK;
   if (!extents_ok(fx, fy, nxw, nyw, sx, sy))
     return fail(PAT_EINVAL, "fft: data extent or sampling does not fit the transform");
   const int nh = fx / 2 + 1;
   const int rs = spec_stride(S);
   const int nxc = nxw / sx, nyc = nyw / sy;
-  PAT_TRY(cols<+1>(X, T, fy, nh, S, rs, rowmap, nullptr, fy, 1, nyc, sy, st));
+  if ((ch.mx && (nxw != fx || sx != 1)) || (ch.my && (nyw != fy || sy != 1)))
+    return fail(PAT_EUNSUPPORTED, "fft: chirp-z axes take whole, unsampled slices");
+  if (ch.my)
+    PAT_TRY(cols_cz<+1>(X, T, fy, nh, S, rs, rowmap, nullptr, ch.cy, ch.by, ch.my, st));
+  else
+    PAT_TRY(cols<+1>(X, T, fy, nh, S, rs, rowmap, nullptr, fy, 1, nyc, sy, st));
+  if (ch.mx) {
+    if (fx > kChirpMaxN || 2 * fx - 1 > ch.mx) return fail(PAT_EINVAL, "chirp-z: table length does not fit");
+    switch (ch.mx) {
+#define PAT_CASE(MM) \
+      case MM: rows_c2r_cz<MM, kRowQ>(T, f, nyc, fx, S, rs, scale, sub, ch.cx, ch.bx, st); break;
+      PAT_CHIRP_M(PAT_CASE)
+#undef PAT_CASE
+      default: return fail(PAT_EUNSUPPORTED, "chirp-z convolution length must be a power of two in [64, 1024]");
+    }
+    PAT_LAUNCHED("fft rows c2r (chirp-z)");
+    return PAT_OK;
+  }
   switch (fx) {
 #define PAT_CASE(N) \
     case N: PAT_ROWS(rows_c2r, N, T, f, nyc, nxc, sx, S, rs, scale, sub, st); break;

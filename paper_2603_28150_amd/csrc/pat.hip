@@ -42,6 +42,8 @@ struct pat_op {
   void* rowT;         // [nclass][nt][sT_row] rows of the storage type (= slabT for FP32)
   float* gram;        // [nclass][nz][sG_row]  Gram blocks of the library
   int sG_row;
+  pat::FftChirp chirp;  // chirp-z tables of axes that are not fast FFT sizes
+  std::vector<float2> h_cz;  // their host copy: c and the kernel DFT, x then y
   std::vector<int32_t> h_members, h_kclass, h_cls_freq, h_rowmap, h_item_slab;
   std::vector<double> h_ir;  // sensor response taps folded into the library
 };
@@ -73,6 +75,50 @@ static bool fft_size(int v) {
   for (int s : sizes)
     if (v == s) return true;
   return false;
+}
+
+// other even lengths in [16, 512] (the paper's 202 and 326 among them) run as
+// chirp-z transforms: a circular convolution of length chirp_m(n), the
+// smallest power of two >= 2n - 1
+static bool chirp_size(int v) { return !fft_size(v) && v >= 16 && v <= 512 && v % 2 == 0; }
+static int chirp_m(int n) {
+  int m = 64;
+  while (m < 2 * n - 1) m <<= 1;
+  return m;
+}
+
+// c[k] = exp(i pi k^2 / n), k < n, then the m-point DFT of the even kernel
+// b[j] = c[|j|] (|j| < n, j taken mod m) divided by m; float64, rounded once
+static void chirp_tables(int n, int m, std::vector<float2>& out) {
+  const double pi = 3.141592653589793238462643383279502884;
+  std::vector<double> cr(n), ci(n);
+  for (int k = 0; k < n; ++k) {
+    const long long r = ((long long)k * k) % (2LL * n);  // exact phase reduction
+    cr[k] = std::cos(pi * (double)r / n);
+    ci[k] = std::sin(pi * (double)r / n);
+    out.push_back(make_float2((float)cr[k], (float)ci[k]));
+  }
+  std::vector<double> br(m, 0.0), bi(m, 0.0);
+  for (int j = 0; j < n; ++j) {
+    br[j] = cr[j];
+    bi[j] = ci[j];
+    if (j > 0) {
+      br[m - j] = cr[j];
+      bi[m - j] = ci[j];
+    }
+  }
+  for (int k = 0; k < m; ++k) {
+    double sr = 0.0, si = 0.0;
+    for (int j = 0; j < m; ++j) {
+      if (br[j] == 0.0 && bi[j] == 0.0) continue;
+      const long long e = ((long long)k * j) % m;
+      const double a = -2.0 * pi * (double)e / m;
+      const double ca = std::cos(a), sa = std::sin(a);
+      sr += br[j] * ca - bi[j] * sa;
+      si += br[j] * sa + bi[j] * ca;
+    }
+    out.push_back(make_float2((float)(sr / m), (float)(si / m)));
+  }
 }
 
 static int default_nq(const pat_geometry& g) {
@@ -115,9 +161,14 @@ static pat_status check_geometry(const pat_geometry* g) {
   if (g->h_dtype < PAT_H_F32 || g->h_dtype > PAT_H_F16) return fail(PAT_EINVAL, "unknown h_dtype");
   if (g->boundary != PAT_BOUNDARY_PERIODIC && g->boundary != PAT_BOUNDARY_LINEAR)
     return fail(PAT_EINVAL, "unknown boundary");
-  if (g->boundary == PAT_BOUNDARY_PERIODIC && (!fft_size(g->nx) || !fft_size(g->ny)))
+  if (g->boundary == PAT_BOUNDARY_PERIODIC &&
+      (!(fft_size(g->nx) || chirp_size(g->nx)) || !(fft_size(g->ny) || chirp_size(g->ny))))
     return fail(PAT_EUNSUPPORTED, "periodic: nx and ny must be transform sizes (16, 32, 48, 64, 72, 96, 108, 128, "
-                                  "144, 192, 216, 256, 288, 384, 432, 512, 576, 768, 864, 1024)");
+                                  "144, 192, 216, 256, 288, 384, 432, 512, 576, 768, 864, 1024) or even "
+                                  "lengths in [16, 512] (chirp-z)");
+  if (g->boundary == PAT_BOUNDARY_PERIODIC && (chirp_size(g->nx) || chirp_size(g->ny)) &&
+      (g->sx > 1 || g->sy > 1))
+    return fail(PAT_EUNSUPPORTED, "scan-grid sampling needs fast transform sizes (no chirp-z axis)");
   if (g->boundary == PAT_BOUNDARY_LINEAR && (g->nx < 4 || g->nx > 512 || g->ny < 1 || g->ny > 512))
     return fail(PAT_EUNSUPPORTED, "linear: nx must be in [4, 512] and ny in [1, 512]");
   if (g->nz > 2048 || g->nt > 2048) return fail(PAT_EUNSUPPORTED, "nz and nt must be <= 2048");
@@ -220,6 +271,7 @@ static Classes make_classes(const pat_geometry& g) {
 }
 
 struct HLayout {
+  size_t off_cz, bytes_cz;
   size_t off_members, off_items, off_kclass, off_rowmap, off_freq, off_inv, off_amax, off_ir, off_A,
       off_T, off_Ar, off_Tr, off_G, total;
   size_t bytes_A, bytes_T, bytes_Ar, bytes_Tr, bytes_G;
@@ -264,6 +316,10 @@ static HLayout h_layout(const pat_geometry& g, const Classes& C) {
   L.off_inv = o;     o = align_up(o + (size_t)g.nz * 4, 256);
   L.off_amax = o;    o = align_up(o + (size_t)g.nz * 8, 256);
   L.off_ir = o;      o = align_up(o + (size_t)g.n_ir * 8, 256);
+  L.bytes_cz = 0;  // chirp-z tables (periodic axes only: the linear periods are fast sizes)
+  if (chirp_size(g.nx)) L.bytes_cz += (size_t)(g.nx + chirp_m(g.nx)) * 8;
+  if (chirp_size(g.ny)) L.bytes_cz += (size_t)(g.ny + chirp_m(g.ny)) * 8;
+  L.off_cz = o;      o = align_up(o + L.bytes_cz, 256);
   L.sG_row = (int)align_up((size_t)g.nz, 4);
   // Gram blocks serve the normal-operator gradient, which only the periodic,
   // unsampled operator has (see pat_recon_fista)
@@ -451,19 +507,19 @@ static pat_status run_gram(pat_op* op, const float2* in, float2* out, const floa
 static pat_status run_A(pat_op* op, const float* x, float* y, int B, const float* sub, const Work& w,
                         hipStream_t st) {
   const pat_geometry& g = op->g;
-  PAT_TRY(fft2_r2c(x, w.T, w.Xs, op->fx, op->fy, g.nx, g.ny, 1, 1, B * g.nz, op->rowmap, st));
+  PAT_TRY(fft2_r2c(x, w.T, w.Xs, op->fx, op->fy, g.nx, g.ny, 1, 1, B * g.nz, op->rowmap, op->chirp, st));
   PAT_TRY(run_contract(op, false, w.Xs, w.Ds, B, st));
   return fft2_c2r(w.Ds, w.T, y, op->fx, op->fy, g.nx, g.ny, op->sx, op->sy, B * g.nt, inv_area(op), sub,
-                  op->rowmap, st);
+                  op->rowmap, op->chirp, st);
 }
 
 // x = A^T y, B data sets
 static pat_status run_AT(pat_op* op, const float* y, float* x, int B, const Work& w, hipStream_t st) {
   const pat_geometry& g = op->g;
-  PAT_TRY(fft2_r2c(y, w.T, w.Ds, op->fx, op->fy, g.nx, g.ny, op->sx, op->sy, B * g.nt, op->rowmap, st));
+  PAT_TRY(fft2_r2c(y, w.T, w.Ds, op->fx, op->fy, g.nx, g.ny, op->sx, op->sy, B * g.nt, op->rowmap, op->chirp, st));
   PAT_TRY(run_contract(op, true, w.Ds, w.Xs, B, st));
   return fft2_c2r(w.Xs, w.T, x, op->fx, op->fy, g.nx, g.ny, 1, 1, B * g.nz, inv_area(op), nullptr,
-                  op->rowmap, st);
+                  op->rowmap, op->chirp, st);
 }
 
 }  // namespace pat
@@ -609,6 +665,26 @@ pat_status pat_H_build(pat_ctx* ctx, const pat_geometry* geom, void* h_buf, size
       (s = hip_check(hipMemcpyAsync(d_ir, op->h_ir.data(), op->h_ir.size() * 8, hipMemcpyHostToDevice, st),
                      "upload sensor response")) != PAT_OK)
     return bail(s);
+  if (L.bytes_cz) {  // chirp-z tables of the transform axes that need them
+    float2* d_cz = reinterpret_cast<float2*>(op->hbuf + L.off_cz);
+    const int nxg = op->fx, nyg = op->fy;
+    if (chirp_size(nxg)) {
+      chirp_tables(nxg, chirp_m(nxg), op->h_cz);
+      op->chirp.cx = d_cz;
+      op->chirp.bx = d_cz + nxg;
+      op->chirp.mx = chirp_m(nxg);
+    }
+    if (chirp_size(nyg)) {
+      const size_t o0 = op->h_cz.size();
+      chirp_tables(nyg, chirp_m(nyg), op->h_cz);
+      op->chirp.cy = d_cz + o0;
+      op->chirp.by = d_cz + o0 + nyg;
+      op->chirp.my = chirp_m(nyg);
+    }
+    if ((s = hip_check(hipMemcpyAsync(d_cz, op->h_cz.data(), op->h_cz.size() * sizeof(float2),
+                                      hipMemcpyHostToDevice, st), "upload chirp-z tables")) != PAT_OK)
+      return bail(s);
+  }
   HBuildArgs a;
   a.ir = geom->n_ir > 0 ? d_ir : nullptr;
   a.n_ir = geom->n_ir;
@@ -742,7 +818,7 @@ pat_status pat_spectrum(pat_op* op, const float* f, float* spec, int32_t S, void
   PAT_TRY(check_ptr(f, "f"));
   PAT_TRY(check_ptr(spec, "spec"));
   return fft2_r2c(f, w.T, (float2*)spec, op->fx, op->fy, op->g.nx, op->g.ny, 1, 1, S, op->rowmap,
-                  (hipStream_t)stream);
+                  op->chirp, (hipStream_t)stream);
 }
 
 pat_status pat_inverse_spectrum(pat_op* op, const float* spec, float* f, int32_t S, const float* sub,
@@ -753,7 +829,7 @@ pat_status pat_inverse_spectrum(pat_op* op, const float* spec, float* f, int32_t
   PAT_TRY(check_ptr(spec, "spec"));
   if (sub) PAT_TRY(check_ptr(sub, "sub"));
   return fft2_c2r((const float2*)spec, w.T, f, op->fx, op->fy, op->g.nx, op->g.ny, 1, 1, S,
-                  inv_area(op), sub, op->rowmap, (hipStream_t)stream);
+                  inv_area(op), sub, op->rowmap, op->chirp, (hipStream_t)stream);
 }
 
 pat_status pat_contract(pat_op* op, int32_t adjoint, const float* in, float* out, int32_t B,
@@ -817,10 +893,10 @@ pat_status pat_recon_fista(pat_op* op, const float* d, float* x, int32_t niter, 
   const bool normal = op->gram != nullptr;
   if (normal) {
     // b^ = spectrum of A^T d (the adjoint up to its inverse transform), once
-    PAT_TRY(fft2_r2c(d, w.T, w.Ds, op->fx, op->fy, g.nx, g.ny, op->sx, op->sy, g.nt, op->rowmap, st));
+    PAT_TRY(fft2_r2c(d, w.T, w.Ds, op->fx, op->fy, g.nx, g.ny, op->sx, op->sy, g.nt, op->rowmap, op->chirp, st));
     PAT_TRY(run_contract(op, true, w.Ds, w.Bs, 1, st));
     if (trace) {
-      PAT_TRY(fft2_c2r(w.Bs, w.T, w.V, op->fx, op->fy, g.nx, g.ny, 1, 1, g.nz, inv, nullptr, op->rowmap, st));  // b = A^T d
+      PAT_TRY(fft2_c2r(w.Bs, w.T, w.V, op->fx, op->fy, g.nx, g.ny, 1, 1, g.nz, inv, nullptr, op->rowmap, op->chirp, st));  // b = A^T d
       PAT_TRY(dot_f64(d, d, nd, w.part64, w.s64 + 2, st));
     }
   } else if (trace) {
@@ -834,9 +910,9 @@ pat_status pat_recon_fista(pat_op* op, const float* d, float* x, int32_t niter, 
   for (int k = 1; k <= niter; ++k) {
     if (normal) {
       // gradient A^T (A z - d) = A^T A z - A^T d, per frequency: G z^ - b^
-      PAT_TRY(fft2_r2c(w.Z, w.T, w.Xs, op->fx, op->fy, g.nx, g.ny, 1, 1, g.nz, op->rowmap, st));
+      PAT_TRY(fft2_r2c(w.Z, w.T, w.Xs, op->fx, op->fy, g.nx, g.ny, 1, 1, g.nz, op->rowmap, op->chirp, st));
       PAT_TRY(run_gram(op, w.Xs, w.Gs, w.Bs, 1, st));
-      PAT_TRY(fft2_c2r(w.Gs, w.T, w.U, op->fx, op->fy, g.nx, g.ny, 1, 1, g.nz, inv, nullptr, op->rowmap, st));
+      PAT_TRY(fft2_c2r(w.Gs, w.T, w.U, op->fx, op->fy, g.nx, g.ny, 1, 1, g.nz, inv, nullptr, op->rowmap, op->chirp, st));
       if (trace) {
         // 1/2 ||A z - d||^2 = 1/2 (<z, g> - <z, b> + ||d||^2), float64 sums
         PAT_TRY(dot_f64(w.Z, w.U, n, w.part64, w.s64 + 0, st));
@@ -920,10 +996,10 @@ pat_status pat_fista_step_normal(pat_op* op, int32_t B, const float* atd, float*
     p.o[b].beta = (float)beta[b];
     p.o[b].nonneg = nonneg[b] ? 1 : 0;
   }
-  PAT_TRY(fft2_r2c(z, w.T, w.Xs, op->fx, op->fy, g.nx, g.ny, 1, 1, B * g.nz, op->rowmap, st));
+  PAT_TRY(fft2_r2c(z, w.T, w.Xs, op->fx, op->fy, g.nx, g.ny, 1, 1, B * g.nz, op->rowmap, op->chirp, st));
   PAT_TRY(run_gram(op, w.Xs, w.Gs, nullptr, B, st));
   PAT_TRY(fft2_c2r(w.Gs, w.T, w.U, op->fx, op->fy, g.nx, g.ny, 1, 1, B * g.nz, inv_area(op), atd,
-                   op->rowmap, st));  // U = A^T A z - A^T d
+                   op->rowmap, op->chirp, st));  // U = A^T A z - A^T d
   return fista_update(x, z, w.U, n, B, p, nonfinite, st);
 }
 

@@ -44,16 +44,30 @@ inline int spec_stride(int S) { return (S + 63) / 64 * 64 + 32; }
 //   row-transformed  T[(j*nh + m) * rs + s]   (y not yet transformed)
 // Forward transforms are unnormalised; the inverse multiplies by `scale`.
 pat_status fft_init_device();  // uploads the twiddle table to the current device
+// Chirp-z tables of an axis whose length n is not a fast FFT size: c[n]
+// (exp(i pi k^2 / n), k < n) and the m-point DFT of the chirp kernel over m
+// (m a power of two >= 2n - 1), device arrays; m = 0: the axis uses the fast
+// transforms.
+struct FftChirp {
+  const float2* cx = nullptr;
+  const float2* bx = nullptr;
+  int mx = 0;
+  const float2* cy = nullptr;
+  const float2* by = nullptr;
+  int my = 0;
+};
 // f holds S slices covering the nxw x nyw window of the fx x fy transform
-// grid (powers of two up to 512), sampled every sx columns and sy rows:
+// grid (fast sizes, or chirp-z lengths), sampled every sx columns and sy rows:
 // f[s][nyw/sy][nxw/sx].  Zero-padding and zero-filling on the way in,
 // cropping and sampling on the way out.
+// An axis with chirp-z tables (ch.mx / ch.my > 0) must be covered whole and
+// unsampled.
 pat_status fft2_r2c(const float* f, float2* T, float2* X, int fx, int fy, int nxw, int nyw, int sx,
-                    int sy, int S, const int32_t* rowmap, hipStream_t st);
+                    int sy, int S, const int32_t* rowmap, const FftChirp& ch, hipStream_t st);
 // f = scale * c2r(X) - sub (sub may be null; same layout as f)
 pat_status fft2_c2r(const float2* X, float2* T, float* f, int fx, int fy, int nxw, int nyw, int sx,
                     int sy, int S, float scale, const float* sub, const int32_t* rowmap,
-                    hipStream_t st);
+                    const FftChirp& ch, hipStream_t st);
 
 // ------------------------------------------------------ contraction (VALU)
 // out[t*G+g][obj*nj + j] = sum_i slab_s[i][j] * in[t*G+g][obj*ni + i] (* scales)

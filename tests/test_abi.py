@@ -54,13 +54,19 @@ def test_host_only_calls(lib):
     radii = {a * a + b * b for a in range(17) for b in range(a, 17)}
     assert hb.value >= len(radii) * 16 * 64 * 4 * 2
     assert hb.value < (len(radii) + 1) * 16 * 64 * 4 * 2 + (1 << 20)
-    for n in (40, 24, 54, 36, 1536, 2048, 8, 202):   # not among the transform sizes
+    # neither a fast transform size nor an even length in [16, 512] (chirp-z)
+    for n in (1536, 2048, 8, 14, 201, 514, 1000, 41):
         bad = _lib.Geometry(n, 32, 16, 64, 1e-4, 1e-4, 1e-4, 2e-8, 1500.0, 0, 0)
         assert L.pat_H_bytes(ctypes.byref(bad), ctypes.byref(hb), ctypes.byref(sb)) == -2
         assert b"transform sizes" in L.pat_last_error()
-    for n in (48, 72, 96, 108, 216, 384, 432, 576, 768, 864, 16, 1024):
+    for n in (48, 72, 96, 108, 216, 384, 432, 576, 768, 864, 16, 1024,   # fast sizes
+              18, 24, 36, 40, 54, 202, 326, 510):                          # chirp-z lengths
         ok = _lib.Geometry(n, 32, 16, 64, 1e-4, 1e-4, 1e-4, 2e-8, 1500.0, 0, 0)
         assert L.pat_H_bytes(ctypes.byref(ok), ctypes.byref(hb), ctypes.byref(sb)) == 0
+    # scan-grid sampling only on fast sizes
+    g2 = _lib.Geometry(202, 32, 16, 64, 1e-4, 1e-4, 1e-4, 2e-8, 1500.0, 0, 0)
+    g2.sx = 2
+    assert L.pat_H_bytes(ctypes.byref(g2), ctypes.byref(hb), ctypes.byref(sb)) == -2
     neg = _lib.Geometry(32, 32, 16, 64, -1e-4, 1e-4, 1e-4, 2e-8, 1500.0, 0, 0)
     assert L.pat_H_bytes(ctypes.byref(neg), ctypes.byref(hb), ctypes.byref(sb)) == -1
     small = _lib.Geometry(32, 32, 16, 64, 1e-4, 1e-4, 1e-4, 2e-8, 1500.0, 8, 0)

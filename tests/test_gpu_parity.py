@@ -137,7 +137,7 @@ def test_invalid_arguments_raise():
     assert L.pat_apply_A(op.handle, x.data_ptr(), y.data_ptr(), 1, ws.data_ptr(), 16, None) == -1
     assert L.pat_apply_A(op.handle, x.data_ptr() + 4, y.data_ptr(), 1, ws.data_ptr(), ws.numel(), None) == -1
     with pytest.raises(_lib.PatError):
-        Operator(Geometry(40, 32, 4, 4, 1e-4, 1e-4, 1e-4, 2e-8, 1500.0))
+        Operator(Geometry(41, 32, 4, 4, 1e-4, 1e-4, 1e-4, 2e-8, 1500.0))
 
 
 def test_power_iteration_matches_oracle():
