@@ -82,10 +82,13 @@ typedef enum { PAT_H_F32 = 0, PAT_H_BF16 = 1, PAT_H_F16 = 2 } pat_hdtype;
 typedef enum { PAT_BOUNDARY_PERIODIC = 0, PAT_BOUNDARY_LINEAR = 1 } pat_boundary;
 
 typedef struct {
-  int32_t nx, ny;  /* transverse grid (x fastest): transform sizes 16, 32, 48,
-                      64, 72, 96, 108, 128, 144, 192, 216, 256, 288, 384, 432,
-                      512, 576, 768, 864, 1024 (2^a 3^b, b <= 3; periodic);
-                      any nx in [4, 512], ny in [1, 512] (linear) */
+  int32_t nx, ny;  /* transverse grid (x fastest).  Periodic: the fast
+                      transform sizes 16, 32, 48, 64, 72, 96, 108, 128, 144,
+                      192, 216, 256, 288, 384, 432, 512, 576, 768, 864, 1024
+                      (2^a 3^b, b <= 3), or any other even length in [16, 512]
+                      (chirp-z transforms: a circular convolution of
+                      power-of-two length >= 2n - 1; no scan-grid sampling
+                      then).  Linear: any nx in [4, 512], ny in [1, 512] */
   int32_t nz, nt;  /* depths and time samples, >= 1 */
   double dx, dy, dz, dt, c; /* spacings [m], time step [s], sound speed [m/s]; all > 0 */
   int32_t nz_sim;  /* z-period of the simulated medium in grid points: 0 selects
