@@ -450,8 +450,11 @@ def forms(op, x, x64, args, samples: dict) -> dict:
     # the paper's grid shapes on the linear boundary (Sec. 3.3-3.4): the in vivo
     # 384 x 326 x 96 grid at 50 um (384 samples chosen here) on 768^2
     # transforms, the wire phantom 202 x 202 x 37 at 10 um (256 samples) on 432^2
+    # and the wire grid on the periodic boundary, whose 202-point axes run
+    # chirp-z transforms (512-point convolutions)
     for name, gp in (("invivo_384x326x96x384", Geometry.paper_like(384, 326, 96, 384, dx=50e-6, boundary="linear")),
-                     ("wire_202x202x37x256", Geometry.paper_like(202, 202, 37, 256, dx=10e-6, boundary="linear"))):
+                     ("wire_202x202x37x256", Geometry.paper_like(202, 202, 37, 256, dx=10e-6, boundary="linear")),
+                     ("wire_periodic_chirpz_202x202x37x256", Geometry.paper_like(202, 202, 37, 256, dx=10e-6))):
         t0 = time.perf_counter()
         op_ = Operator(gp, "f32")
         torch.cuda.synchronize()
@@ -465,7 +468,7 @@ def forms(op, x, x64, args, samples: dict) -> dict:
         res[f"{name}_contract_GBs"] = bp / ((tA + tAT) * 1e-3) / 1e9
         res[f"{name}_library_GiB"] = (inf_["slab_bytes_A"] + inf_["slab_bytes_AT"]) / 2**30
         res[f"{name}_library_build_s"] = build_s
-        log(f"{name} (linear, {op_.nk} transverse frequencies): {res[f'{name}_pairs_per_s']:.1f} pairs/s, "
+        log(f"{name} ({gp.boundary}, {op_.nk} transverse frequencies): {res[f'{name}_pairs_per_s']:.1f} pairs/s, "
             f"contraction {res[f'{name}_contract_GBs']:.0f} GB/s, library {res[f'{name}_library_GiB']:.1f} GiB, "
             f"build {build_s:.2f} s")
         del op_, xp
