@@ -15,6 +15,7 @@ pytestmark = pytest.mark.gpu
 GA = Geometry.paper_like(64, 64, 64, 256)
 GB = Geometry.paper_like(32, 32, 16, 64)
 GL = Geometry.paper_like(32, 32, 16, 64, boundary="linear")    # zero-padded, explicit step
+GC = Geometry.paper_like(34, 34, 8, 40)                          # 34-point axes: chirp-z transforms
 
 
 def _ops(g):
@@ -42,7 +43,7 @@ def rel(a, b):
 def test_results_alone_equal_results_in_the_mix(normal):
     plan = [(GA, "f32", 12), (GB, "f32", 20), (GA, "bf16", 9), (GL, "f32", 10), (GA, "f32", 15),
             (GB, "f32", 7), (GL, "bf16", 6), (GA, "bf16", 11), (GA, "f32", 5), (GL, "f32", 9),
-            (GB, "bf16", 8)]
+            (GB, "bf16", 8), (GC, "f32", 7), (GC, "f32", 10)]
     datas = [_data(g, 500 + 7 * i)[0] for i, (g, _, _) in enumerate(plan)]
     srv = Server(HipBackend(normal=normal), hbm_budget=8 << 30, max_batch=4)
     reqs = []
