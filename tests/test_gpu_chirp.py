@@ -109,3 +109,18 @@ def test_chirp_z_fista_matches_oracle():
     xs = solvers.fista(A, AT, d, (g.nz, g.ny, g.nx), 8, tau, 1e-3, nonneg=True)
     for k in (1, 8):
         assert rel(host(op.recon_fista(dev(d), k, tau, 1e-3, nonneg=True)), xs[k - 1]) < 1e-5, k
+
+
+@pytest.mark.parametrize("n", [20, 22, 26, 34, 62, 66, 98, 130, 254, 258, 386, 414, 506])
+def test_chirp_z_lengths_sweep(n):
+    # every convolution length (64 ... 1024) along x and along y, on thin
+    # grids: A against the oracle and the adjoint identity
+    for g in (Geometry(n, 16, 2, 5, 1e-4, 1e-4, 1e-4, 2e-8, 1500.0),
+              Geometry(16, n, 2, 5, 1e-4, 1e-4, 1e-4, 2e-8, 1500.0)):
+        op = Operator(g)
+        Hh = hlib.H_half(og(g))
+        x = inputs.gaussian_random((g.nz, g.ny, g.nx), seed=1240 + n)
+        y = inputs.gaussian_random((g.nt, g.ny, g.nx), seed=1241 + n)
+        assert rel(host(op.apply_A(dev(x))), ops.A_fft(Hh, x)) < 1e-5, (g.nx, g.ny)
+        assert rel(host(op.apply_AT(dev(y))), ops.AT_fft(Hh, y)) < 1e-5, (g.nx, g.ny)
+        assert op.adjoint_check(dev(x), dev(y)) < 1e-5
