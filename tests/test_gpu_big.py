@@ -60,16 +60,17 @@ def test_big_adjoint_identity(big):
     assert op.adjoint_check(x, y) < 1e-5
 
 
-@pytest.mark.parametrize("kind", ["bf16", "f16"])
-def test_big_16bit_library_batch(kind):
-    # full-size 16-bit library on the matrix cores, batch of 4: every object
-    # within the 16-bit bound of the exact oracle at sampled frequencies
+@pytest.mark.parametrize("kind,B", [("bf16", 4), ("f16", 4), ("bf16", 16)])
+def test_big_16bit_library_batch(kind, B):
+    # full-size 16-bit library on the matrix cores, batches of 4 and of 16 (the
+    # benchmark's launch shape): every object within the 16-bit bound of the
+    # exact oracle at sampled frequencies
     op = Operator(BIG, kind)
     o = OGeom(BIG.nx, BIG.ny, BIG.nz, BIG.nt, BIG.dx, BIG.dy, BIG.dz, BIG.dt, BIG.c)
     Hk = hlib.H_hat(o, M, P)
-    xs = np.stack([inputs.gaussian_random((BIG.nz, BIG.ny, BIG.nx), seed=94 + b) for b in range(4)])
+    xs = np.stack([inputs.gaussian_random((BIG.nz, BIG.ny, BIG.nx), seed=94 + b) for b in range(B)])
     ys = op.apply_A(torch.from_numpy(xs.astype(np.float32)).cuda()).cpu().numpy().astype(np.float64)
-    for b in range(4):
+    for b in (range(B) if B <= 4 else (0, 7, B - 1)):
         Dg = ops.dft_at(ys[b], M, P)
         Do = ops.A_at_freqs(Hk, xs[b], M, P)
         assert np.linalg.norm(Dg - Do) / np.linalg.norm(Do) < 5e-3
@@ -110,5 +111,19 @@ def test_paper_in_vivo_grid_full_size():
     assert op.adjoint_check(x, y) < 1e-5
     x2 = torch.stack([x, torch.flip(x, dims=(0,))])
     y2 = op.apply_A(x2)
+    y1 = op.apply_A(x)
+    assert float(torch.linalg.norm(y2[0] - y1) / torch.linalg.norm(y1)) < 1e-5
+
+
+def test_big_linear_boundary_full_size():
+    # the linear-boundary form as the benchmark runs it (256^2 window, 128 x
+    # 512, 512^2 transforms): adjoint identity with float64 dots, and an
+    # object in a batch of 2 against the same object alone
+    g = Geometry.paper_like(256, 256, 128, 512, boundary="linear")
+    op = Operator(g)
+    x = torch.from_numpy(inputs.vascular_phantom(op.x_shape, seed=97).astype(np.float32)).cuda()
+    y = torch.from_numpy(inputs.gaussian_random(op.d_shape, seed=98).astype(np.float32)).cuda()
+    assert op.adjoint_check(x, y) < 1e-5
+    y2 = op.apply_A(torch.stack([x, x.flip(0)]))
     y1 = op.apply_A(x)
     assert float(torch.linalg.norm(y2[0] - y1) / torch.linalg.norm(y1)) < 1e-5
