@@ -6,9 +6,9 @@
 // H^ is real and identical for all frequencies of one symmetry class, so the
 // library keeps one slab per class in two layouts, [l][n] for A and [n][l] for
 // A^T.  Both products then have the same shape: the summed index i runs over
-// slab rows, the kept index j runs along a row, and one workgroup streams one
-// slab exactly once while applying it to every member frequency of its work
-// item (up to eight).  Streaming the slab is the whole cost (it is >95 % of the bytes
+// slab rows, the kept index j runs along a row, and one workgroup (or, for
+// long rows, two, each taking half of every row) streams one slab exactly once
+// while applying it to every member frequency of its work item (up to eight).  Streaming the slab is the whole cost (it is >95 % of the bytes
 // an apply moves), so the kernel is built around 16-byte non-temporal loads
 // of whole rows: lanes of a row group cover one row, row groups take
 // interleaved rows, and a short LDS tree adds the row-group partial sums at
@@ -109,7 +109,9 @@ __device__ __forceinline__ void contract_item(const ContractArgs& a, int lr_log2
   // 16-byte loads along each member row when the row length is even
   if ((a.ni & 1) == 0) {
     // batches of kStage loads per thread, all issued before their LDS stores
-    // (one memory latency per batch instead of one per load)
+    // (one memory latency per batch instead of one per load); consecutive
+    // lanes take consecutive members of one k pair, so that the LDS stores
+    // are contiguous (the loads still cover whole 128-byte lines per wave)
     constexpr int kStage = 8;
     const int h = a.ni >> 1;
     const int total = GG * h;
@@ -120,7 +122,7 @@ __device__ __forceinline__ void contract_item(const ContractArgs& a, int lr_log2
         const int idx = base + q * 256;
         v[q] = make_float4(0.f, 0.f, 0.f, 0.f);
         if (idx < total) {
-          const int g = idx / h, i = 2 * (idx - g * h);
+          const int g = idx % GG, i = 2 * (idx / GG);
           int k = -1;
 #pragma unroll
           for (int gg = 0; gg < GG; ++gg) k = (gg == g) ? kg[gg] : k;
@@ -132,7 +134,7 @@ __device__ __forceinline__ void contract_item(const ContractArgs& a, int lr_log2
       for (int q = 0; q < kStage; ++q) {
         const int idx = base + q * 256;
         if (idx >= total) break;
-        const int g = idx / h, i = 2 * (idx - g * h);
+        const int g = idx % GG, i = 2 * (idx / GG);
         float4 w = v[q];
         if (a.in_scale) {
           const float s0 = a.in_scale[i], s1 = a.in_scale[i + 1];
