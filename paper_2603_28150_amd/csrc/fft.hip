@@ -170,13 +170,16 @@ __global__ __launch_bounds__(256) void k_fft_rows_r2c(const float* __restrict__ 
   const int j = blockIdx.x;
   const int s0 = blockIdx.y * 2 * Q;
   load_twiddles<N, -1>(tw, tid, NT);
-  // rows of the block: 2Q rows x N/4 float4, every load issued before any LDS store
+  // rows of the block: 2Q rows x N/4 float4, every load issued before any LDS
+  // store; adjacent lanes take the two rows of a packed pair at the same
+  // column (their re and im floats are adjacent in LDS: few bank conflicts),
+  // and each row is still read as whole lines across the wave
   constexpr int LIT = (2 * Q * (N / 4) + NT - 1) / NT;
   float4 ld[LIT];
 #pragma unroll
   for (int it = 0; it < LIT; ++it) {
     const int u = tid + it * NT;
-    const int row = u / (N / 4), c4 = u % (N / 4);
+    const int row = 2 * (u / (N / 2)) + (u & 1), c4 = (u % (N / 2)) >> 1;
     const int s = s0 + row;
     ld[it] = make_float4(0.f, 0.f, 0.f, 0.f);
     if (u < 2 * Q * (N / 4) && s < S && 4 * c4 < nxd) {
@@ -200,7 +203,7 @@ __global__ __launch_bounds__(256) void k_fft_rows_r2c(const float* __restrict__ 
   for (int it = 0; it < LIT; ++it) {
     const int u = tid + it * NT;
     if (u >= 2 * Q * (N / 4)) break;
-    const int row = u / (N / 4), c4 = u % (N / 4);
+    const int row = 2 * (u / (N / 2)) + (u & 1), c4 = (u % (N / 2)) >> 1;
     if (!GEN || sx == 1) {
       float* z = reinterpret_cast<float*>(ex + (row >> 1) * PAD + 4 * c4) + (row & 1);
       z[0] = ld[it].x;
