@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import hlib, operators as ops, solvers
+from oracle import hlib, operators as ops, quant, solvers
 from oracle.geometry import Geometry as OGeom
 from paper_2603_28150_amd import inputs
 from paper_2603_28150_amd.op import Geometry, Operator
@@ -95,8 +95,14 @@ def test_chirp_z_batches_and_16bit_library():
     for b in range(3):
         assert rel(ys[b], ops.A_fft(Hh, xs[b])) < 1e-5
         assert rel(ys[b], host(op.apply_A(dev(xs[b])))) < 1e-5
-    ob = Operator(g, "bf16")
-    assert rel(host(ob.apply_A(dev(xs[0]))), ops.A_fft(Hh, xs[0])) < 5e-3
+    for kind in ("bf16", "f16"):
+        ob = Operator(g, kind)
+        Hq, _ = quant.quantise(Hh, kind)
+        yb = host(ob.apply_A(dev(xs)))                           # 16-bit tiles, matrix cores
+        for b in range(3):
+            assert rel(yb[b], ops.A_fft(Hq, xs[b])) < 2e-5, (kind, b)
+            assert rel(yb[b], ops.A_fft(Hh, xs[b])) < 5e-3, (kind, b)
+        assert rel(host(ob.apply_A(dev(xs[0]))), ops.A_fft(Hq, xs[0])) < 2e-5
 
 
 def test_chirp_z_fista_matches_oracle():
