@@ -127,3 +127,30 @@ def test_big_linear_boundary_full_size():
     y2 = op.apply_A(torch.stack([x, x.flip(0)]))
     y1 = op.apply_A(x)
     assert float(torch.linalg.norm(y2[0] - y1) / torch.linalg.norm(y1)) < 1e-5
+
+
+def test_big_fista_gram_path_equals_explicit_path(big):
+    # at the benchmark size the FISTA iterate through the nz x nz Gram blocks
+    # (pat_recon_fista) equals the explicit A-then-A^T iteration, step by
+    # step (both checked against the oracle at small sizes; here they pin each
+    # other where the oracle cannot follow), and the data misfit falls
+    op, _ = big
+    x0 = torch.from_numpy(inputs.vascular_phantom(op.x_shape, seed=99).astype(np.float32)).cuda()
+    d = op.apply_A(x0)
+    d = d + 0.05 * float(d.std()) * torch.from_numpy(
+        inputs.noise_like(op.d_shape, seed=100).astype(np.float32)).cuda()
+    v0 = torch.from_numpy(inputs.gaussian_random(op.x_shape, seed=101).astype(np.float32)).cuda()
+    L, _ = op.power_norm(v0, 30)      # a random start: A^T A is block diagonal in k
+    tau = 0.9 / L
+    K = 4
+    xe = torch.zeros((1,) + op.x_shape, device="cuda")
+    ze = torch.zeros_like(xe)
+    tk = 1.0
+    for k in range(K):
+        tn = (1.0 + (1.0 + 4.0 * tk * tk) ** 0.5) / 2.0
+        op.fista_step(d[None], xe, ze, [(tk - 1.0) / tn], [tau], [0.0], [True])
+        tk = tn
+    xg, tr = op.recon_fista(d, K, tau, 0.0, nonneg=True, trace=True)
+    assert float(torch.linalg.norm(xg - xe[0]) / torch.linalg.norm(xe[0])) < 1e-5
+    tr = tr.cpu().numpy()
+    assert tr[-1] < 0.8 * tr[0]
