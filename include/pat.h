@@ -228,7 +228,10 @@ pat_status pat_contract(pat_op* op, int32_t adjoint, const float* in, float* out
 /* Step-size estimate by power iteration on A^T A (synchronises):
  * v = v0/||v0||; repeat niter times: w = A^T A v, L_i = <v, w>, v = w/||w||.
  * Writes L_niter to *L_out and, if L_trace != NULL, every L_i to the host
- * array L_trace[niter].  v0: device [nz][ny][nx], not modified. */
+ * array L_trace[niter].  v0: device [nz][ny][nx], not modified.  A^T A is
+ * block diagonal in the transverse frequency (Sec. 3.2), so the iteration
+ * never leaves the frequencies v0 contains: start from a random vector (a
+ * constant v0 yields the k = 0 block's norm only, an underestimate). */
 pat_status pat_power_norm(pat_op* op, const float* v0, int32_t niter, double* L_out,
                           double* L_trace, void* ws, size_t ws_bytes, void* stream);
 
