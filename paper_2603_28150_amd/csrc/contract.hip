@@ -13,6 +13,8 @@
 // of whole rows: lanes of a row group cover one row, row groups take
 // interleaved rows, and a short LDS tree adds the row-group partial sums at
 // the end.  Accumulation is float32 for every storage type.
+#include <type_traits>
+
 #include "dft.hpp"
 #include "pat_internal.hpp"
 
@@ -58,13 +60,19 @@ template <> struct Slab<f16_t> {
 
 // One work item: GG active member slots (GG <= G, the slot count of the
 // spectrum rows).  Uniform per workgroup.
+// float32 slabs with rows of one chunk per lane: two rows per register
+// buffer instead of four, so that the kernel fits 128 registers and four
+// waves per SIMD (measured faster on short rows, neutral on long ones)
+template <typename HT, int JPT>
+constexpr bool kLowRegs = std::is_same<HT, float>::value && JPT == 1;
+
 template <typename HT, int G, int GG, int JPT>
 __device__ __forceinline__ void contract_item(const ContractArgs& a, int lr_log2, int t, int b, int j0,
                                               int njl, const int (&kg)[G], float4* smem_raw) {
   typedef Slab<HT> SL;
   typedef typename SL::raw_t raw_t;
   constexpr int VEC = SL::VEC;
-  constexpr int U = 4 / JPT;                // rows per register buffer
+  constexpr int U = kLowRegs<HT, JPT> ? 2 : 4 / JPT;  // rows per register buffer
   constexpr int NS = JPT * VEC * GG * 2;    // accumulators per thread
   float2* xin = reinterpret_cast<float2*>(smem_raw);
   float* red = reinterpret_cast<float*>(smem_raw);
@@ -287,7 +295,7 @@ __device__ __forceinline__ bool item_of_block(int nitem, int B, int JS, int& t, 
 }
 
 template <typename HT, int G, int JPT>
-__global__ __launch_bounds__(256) void k_contract(ContractArgs a, int lr_log2, int B, int JS, int chpart) {
+__global__ __launch_bounds__(256, (kLowRegs<HT, JPT> ? 4 : 1)) void k_contract(ContractArgs a, int lr_log2, int B, int JS, int chpart) {
   extern __shared__ float4 smem_raw[];
   int t, b, part;
   if (!item_of_block(a.nitem, B, JS, t, b, part)) return;  // whole workgroup: padding of the last XCD round
