@@ -39,9 +39,9 @@ typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kWaves = 4;      // waves per workgroup (two workgroups share a CU)
+constexpr int kWaves = 4;      // waves per workgroup (three workgroups share a CU)
 constexpr int kKC = 8;         // k-steps (of 16) per staged chunk
-constexpr int kMT = 4;         // most 32-column tiles per launch group (64 pairs)
+constexpr int kMT = 2;         // most 32-column tiles per launch group (32 pairs)
 constexpr int kTerms = 2;      // hi + lo split of the spectra
 
 // two floats -> two bfloat16 (round to nearest even) packed low, high
@@ -165,7 +165,7 @@ const int kb = k0 + ko * 8;
 }
 
 template <int SRC, int MT>
-__global__ __launch_bounds__(kWaves * 64, 2) void k_contract_mfma(MfmaArgs a, int groups) {
+__global__ __launch_bounds__(kWaves * 64, 3) void k_contract_mfma(MfmaArgs a, int groups) {
   extern __shared__ u32x4 lds[];  // [term][ks][mt][lane] 16-byte units
   constexpr int KB = SRC == kSrcF32 ? kKC / 4 : kKC / 2;  // k-steps per batch of B loads
   const int tid = threadIdx.x;
@@ -210,8 +210,10 @@ __global__ __launch_bounds__(kWaves * 64, 2) void k_contract_mfma(MfmaArgs a, in
         staged = true;
       }
       // this wave's B operands of the chunk, in batches of KB k-steps with all
-      // loads of a batch issued before its MFMAs
-#pragma unroll
+      // loads of a batch issued before its MFMAs (the batch loop is kept rolled:
+      // unrolled, the compiler hoists later batches' loads and the registers
+      // no longer fit three waves per SIMD)
+#pragma unroll 1
       for (int s0 = 0; s0 < kKC; s0 += KB) {
         Frag fr[KB];
         u32x4 raw[KB][2];  // float32 rows: 8 floats per lane and k-step
@@ -358,10 +360,8 @@ pat_status contract_mfma(const MfmaArgs& a, int hdtype, hipStream_t st) {
   const int cols = 2 * (groups > 1 ? kMT * 16 : npairs);  // columns of the widest group
   if (cols <= 32)
     launch_mt<1>(a, src, groups, st);
-  else if (cols <= 64)
-    launch_mt<2>(a, src, groups, st);
   else
-    launch_mt<4>(a, src, groups, st);
+    launch_mt<2>(a, src, groups, st);
   PAT_LAUNCHED("contraction (MFMA)");
   return PAT_OK;
 }

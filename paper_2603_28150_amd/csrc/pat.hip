@@ -191,8 +191,8 @@ static pat_status check_geometry(const pat_geometry* g) {
 //   octant fold (nx = ny, dx = dy):    sorted (|m~|, |p~|), <= 4 members
 //   radial fold (nx = ny, dx = dy):    all frequencies with equal m~^2 + p~^2
 // The radial fold is used for float32 libraries (fewest bytes to stream); the
-// 16-bit libraries keep the octant fold so that a batch of 16 objects fits
-// one matrix-core column group.  A work item of the contraction is one slab
+// 16-bit libraries keep the octant fold so that a batch of 16 objects stays
+// in two matrix-core column groups of 32 pairs.  A work item of the contraction is one slab
 // with up to G member frequencies (a radial class with more members than G
 // is split into several items that read the same slab); its members occupy
 // spectrum rows item*G .. item*G+G-1.
