@@ -155,13 +155,16 @@ pat_status pat_H_export(pat_op* op, int32_t k0, int32_t nk, float* out, void* st
  * both as matrix-core operand tiles, padded to 32 x 16, for batches).  The
  * contraction runs over nitems work items of up to members_max frequencies;
  * each streams one slab, so one apply of one object reads read_bytes_A (or
- * read_bytes_AT) of library. */
+ * read_bytes_AT) of library.  gram_bytes: the Gram blocks kept for the
+ * normal-operator gradient (one nz x nz float32 block per class), 0 when the
+ * library has none (see pat_recon_fista). */
 typedef struct {
   int32_t nk, nclass, members_max, nz_sim;
   size_t slab_bytes_A, slab_bytes_AT;
   int32_t spec_rows; /* rows of a spectrum array (see pat_spectrum) = nitems * members_max */
   int32_t nitems;
   size_t read_bytes_A, read_bytes_AT;
+  size_t gram_bytes;
 } pat_op_info;
 pat_status pat_get_info(const pat_op* op, pat_op_info* info);
 
@@ -241,11 +244,12 @@ pat_status pat_power_norm(pat_op* op, const float* v0, int32_t niter, double* L_
  *     t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2   (beta_k = 0 if momentum == 0),
  * with prox(v) = max(v - tau*lambda, 0) if nonneg, else soft-thresholding.
  * d: device [nt][ny][nx]; x: device [nz][ny][nx], receives x_niter.
- * Periodic boundary: the gradient A^T (A z - d) = A^T A z - A^T d (eq. 15)
- * is formed per transverse frequency with the Gram blocks H^_k^T H^_k of the
- * library (built with it, float64 sums of the stored values): one spectrum
- * of z, one nz x nz contraction and one inverse spectrum per iteration,
- * A^T d once.  Linear boundary: the cropping between A and A^T couples the
+ * Periodic boundary, unsampled data: the gradient A^T (A z - d) =
+ * A^T A z - A^T d (eq. 15) is formed per transverse frequency with the Gram
+ * blocks H^_k^T H^_k of the library (built with it, float64 sums of the
+ * stored values): one spectrum of z, one nz x nz contraction and one inverse
+ * spectrum per iteration, A^T d once.  Linear boundary or scan-grid
+ * sampling: the cropping or sampling between A and A^T couples the
  * frequencies, so the gradient is A^T r with r = A z - d, two applies.
  * trace: NULL or a device float array [niter] that receives
  * 1/2 ||A z_k - d||^2, the data term at the point where the gradient of
@@ -274,9 +278,9 @@ pat_status pat_fista_step(pat_op* op, int32_t B, const float* d, float* x, float
  * A^T d of each object (one pat_apply_AT when the problem is set up), so the
  * data themselves are not needed; x, z, beta, tau, lambda, nonneg and
  * nonfinite as in pat_fista_step.  Per iteration: one spectrum of z, one
- * nz x nz contraction, one inverse spectrum and the update.  Periodic
- * boundary only (EUNSUPPORTED for the linear one, whose library has no
- * Gram blocks). */
+ * nz x nz contraction, one inverse spectrum and the update.  Only for
+ * libraries with Gram blocks: periodic boundary, unsampled data
+ * (EUNSUPPORTED otherwise). */
 pat_status pat_fista_step_normal(pat_op* op, int32_t B, const float* atd, float* x, float* z,
                                  const double* beta, const float* tau, const float* lambda,
                                  const int32_t* nonneg, int32_t* nonfinite,

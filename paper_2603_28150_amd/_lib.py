@@ -17,7 +17,8 @@ class OpInfo(C.Structure):
     _fields_ = [("nk", C.c_int32), ("nclass", C.c_int32), ("members_max", C.c_int32),
                 ("nz_sim", C.c_int32), ("slab_bytes_A", C.c_size_t), ("slab_bytes_AT", C.c_size_t),
                 ("spec_rows", C.c_int32), ("nitems", C.c_int32),
-                ("read_bytes_A", C.c_size_t), ("read_bytes_AT", C.c_size_t)]
+                ("read_bytes_A", C.c_size_t), ("read_bytes_AT", C.c_size_t),
+                ("gram_bytes", C.c_size_t)]
 
 
 class Geometry(C.Structure):

@@ -761,6 +761,7 @@ pat_status pat_get_info(const pat_op* op, pat_op_info* info) {
   info->read_bytes_A = L.bytes_Ar / op->nclass * op->nitem;
   info->read_bytes_AT = L.bytes_Tr / op->nclass * op->nitem;
   info->spec_rows = op->nrows;
+  info->gram_bytes = L.bytes_G;
   return PAT_OK;
 }
 
@@ -976,7 +977,8 @@ pat_status pat_fista_step_normal(pat_op* op, int32_t B, const float* atd, float*
                                  const int32_t* nonneg, int32_t* nonfinite, void* ws,
                                  size_t ws_bytes, void* stream) {
   if (op && !op->gram)
-    return fail(PAT_EUNSUPPORTED, "the normal-operator step needs the periodic boundary (no Gram blocks)");
+    return fail(PAT_EUNSUPPORTED,
+                "the normal-operator step needs Gram blocks: periodic boundary, unsampled data");
   Work w;
   PAT_TRY(check_op_call(op, B, ws, ws_bytes, &w));
   if (B > 32) return fail(PAT_EINVAL, "B must be <= 32");

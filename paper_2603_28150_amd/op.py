@@ -112,6 +112,9 @@ class Operator:
                   _ptr(self.scratch), sb.value, _stream(self.device), C.byref(h))
         self.handle = h
         self._ws: dict[tuple[int, int], torch.Tensor] = {}
+        # Gram blocks (periodic boundary, unsampled data): the normal-operator
+        # gradient of recon_fista and fista_step_normal
+        self.has_gram = self.info()["gram_bytes"] > 0
 
     def __del__(self):
         h = getattr(self, "handle", None)

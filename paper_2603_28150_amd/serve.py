@@ -82,9 +82,9 @@ class HipBackend:
     operator: a slot keeps A^T d (formed once at admission) instead of d, and
     an iteration costs one z-spectrum, one nz x nz contraction and one inverse
     spectrum; normal=False takes the explicit A then A^T every iteration.
-    Geometries with the linear (zero-padded) boundary always take the explicit
-    step: cropping the data between A and A^T breaks the per-frequency
-    structure of A^T A."""
+    Libraries without Gram blocks always take the explicit step: the linear
+    (zero-padded) boundary and scan-grid sampling, whose cropping or sampling
+    between A and A^T breaks the per-frequency structure of A^T A."""
 
     def __init__(self, device: int = 0, normal: bool = True):
         self.device = torch.device("cuda", device)
@@ -107,7 +107,7 @@ class HipBackend:
         return 1.0 / L
 
     def uses_normal(self, op) -> bool:
-        return self.normal and op.geom.boundary == "periodic"
+        return self.normal and op.has_gram
 
     def slot_bytes(self, op) -> int:
         g = op.geom

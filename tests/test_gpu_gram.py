@@ -1,0 +1,111 @@
+"""GPU parity of the normal-operator gradient through the Gram blocks
+H^_k H^_k^T (one nz x nz float32 block per class) across depths and folds.
+
+Depths from a two-chunk row (nz = 5) to rows that the contraction splits
+over two workgroups (nz = 520), ragged and whole 16-byte chunks, and the
+three folds (radial, octant, quadrant); the batched normal step is checked
+against the oracle's A^T A z directly and FISTA through the Gram blocks
+against the oracle's FISTA.  Libraries whose gradient couples frequencies
+(linear boundary, scan-grid sampling) keep no Gram blocks.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import hlib, operators as ops, quant, solvers
+from oracle.geometry import Geometry as OGeom
+from paper_2603_28150_amd import inputs
+from paper_2603_28150_amd.op import Geometry, Operator
+
+pytestmark = pytest.mark.gpu
+
+#        nx  ny  nz   nt  library  fold (members per item), Gram row
+CASES = {
+    "r5":    (16, 16, 5, 24, "f32"),     # radial (8); 2 chunks, ragged
+    "r24":   (16, 16, 24, 40, "f32"),    # radial; 6 chunks
+    "r61":   (16, 16, 61, 40, "bf16"),   # octant (4); 16 chunks, ragged
+    "q30":   (24, 16, 30, 36, "f32"),    # quadrant (2), non-square
+    "r256":  (16, 16, 256, 40, "f32"),   # radial; 64 chunks
+    "r520":  (16, 16, 520, 16, "f32"),   # 130 chunks: one object's rows split over two workgroups
+}
+
+
+def geom(name) -> Geometry:
+    nx, ny, nz, nt, _ = CASES[name]
+    return Geometry(nx, ny, nz, nt, 1e-4, 1.1e-4 if nx != ny else 1e-4, 1e-4, 2e-8, 1500.0)
+
+
+def og(g: Geometry) -> OGeom:
+    return OGeom(g.nx, g.ny, g.nz, g.nt, g.dx, g.dy, g.dz, g.dt, g.c, g.nz_sim)
+
+
+def dev(a) -> torch.Tensor:
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def host(t: torch.Tensor) -> np.ndarray:
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+_cache = {}
+
+
+def setup(name):
+    if name not in _cache:
+        g = geom(name)
+        kind = CASES[name][4]
+        Hh = hlib.H_half(og(g))
+        if kind != "f32":
+            Hh, _ = quant.quantise(Hh, kind)
+        _cache[name] = (g, Operator(g, kind), Hh)
+    return _cache[name]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_normal_step_is_AT_A(name):
+    # one normal step with A^T d = 0, tau = 1, no prox, no momentum:
+    # x = z - A^T A z, so z - x is the Gram product of each of 3 objects
+    g, op, Hh = setup(name)
+    assert op.has_gram
+    assert op.info()["gram_bytes"] == op.info()["nclass"] * g.nz * (-(-g.nz // 4) * 4) * 4
+    B = 3
+    z0 = np.stack([inputs.gaussian_random((g.nz, g.ny, g.nx), seed=1300 + b) for b in range(B)])
+    z = dev(z0)
+    x = torch.zeros_like(z)
+    atd = torch.zeros_like(z)
+    op.fista_step_normal(atd, x, z, [0.0] * B, [1.0] * B, [0.0] * B, [False] * B)
+    gg = z0 - host(x)
+    for b in range(B):
+        ref = ops.AT_fft(Hh, ops.A_fft(Hh, z0[b]))
+        assert rel(gg[b], ref) < 1e-5 * max(1.0, np.linalg.norm(z0[b]) / np.linalg.norm(ref)), b
+    # repeatable bits
+    x2 = torch.zeros_like(x)
+    op.fista_step_normal(atd, x2, dev(z0), [0.0] * B, [1.0] * B, [0.0] * B, [False] * B)
+    assert torch.equal(x, x2)
+
+
+@pytest.mark.parametrize("name", ["r5", "r61", "q30", "r256", "r520"])
+def test_gram_fista_matches_oracle(name):
+    # random data: with few samples, sources deeper than c * nt * dt do not
+    # reach the sensor, and the data of a random object would be nearly zero
+    g, op, Hh = setup(name)
+    d = inputs.gaussian_random((g.nt, g.ny, g.nx), seed=1311)
+    A = lambda v: ops.A_fft(Hh, v)
+    AT = lambda v: ops.AT_fft(Hh, v)
+    tau = float(np.float32(0.9 / solvers.norm_exact(Hh)))
+    xs = solvers.fista(A, AT, d, (g.nz, g.ny, g.nx), 8, tau, 1e-3, nonneg=True)
+    for k in (1, 8):
+        assert rel(host(op.recon_fista(dev(d), k, tau, 1e-3, nonneg=True)), xs[k - 1]) < 1e-5, k
+
+
+@pytest.mark.parametrize("kw", [{"boundary": "linear"}, {"sx": 2, "sy": 2}])
+def test_coupled_gradients_keep_no_gram_blocks(kw):
+    op = Operator(Geometry.paper_like(32, 32, 8, 24, **kw))
+    assert not op.has_gram and op.info()["gram_bytes"] == 0
+    x = torch.zeros((1,) + op.x_shape, device="cuda")
+    with pytest.raises(RuntimeError, match="Gram blocks"):
+        op.fista_step_normal(torch.zeros_like(x), x, torch.zeros_like(x), [0.0], [1.0], [0.0], [False])
