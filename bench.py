@@ -45,6 +45,21 @@ def contraction_bytes(info: dict, nk: int, nz: int, nt: int, adjoint: bool, B: i
     return slab + B * nk * (nz + nt) * 8
 
 
+def fista_gram_bytes(info: dict, nk: int, nz: int, nt: int, nxy: int, niter: int) -> int:
+    """Bytes that pat_recon_fista's passes move with the Gram-block gradient
+    (periodic boundary, one object, nxy = nx * ny sensor points):
+    set-up: the spectrum of d (row pass: d in, intermediate out; column pass:
+    intermediate in, spectrum out), one A^T contraction, x and z cleared;
+    per iteration: the spectrum of z (z in, two spectrum-sized
+    intermediates), the Gram contraction (blocks, z^ and (A^T d)^ in, result
+    out), the inverse spectrum (three spectrum-sized passes, gradient out)
+    and the update (x, z, gradient in; x, z out)."""
+    n = nz * nxy
+    setup = 4 * nt * nxy + 24 * nt * nk + contraction_bytes(info, nk, nz, nt, True) + 8 * n
+    per_iter = 28 * n + 72 * nz * nk + info["gram_bytes"]
+    return setup + niter * per_iter
+
+
 def time_pairs(op, x, steps, warmup, B=1):
     """Times `steps` A+A^T pairs built from stage calls; returns
     (seconds total, mean contraction ms for A, for A^T)."""
@@ -390,6 +405,9 @@ def forms(op, x, x64, args, samples: dict) -> dict:
     torch.cuda.synchronize()
     t_f = time.perf_counter() - t0
     res["fista100_fp32_s"] = t_f
+    fb = fista_gram_bytes(op.info(), op.nk, g.nz, g.nt, g.nx * g.ny, 100)
+    res["fista100_GB"] = fb / 1e9
+    res["fista100_hbm_frac"] = fb / t_f / 1e9 / HBM_PEAK_GBS
     res["power30_s"] = t_pow
     # the same iterations with the explicit gradient A^T (A z - d): two applies each
     xs = torch.zeros((1,) + op.x_shape, device="cuda")
@@ -404,7 +422,8 @@ def forms(op, x, x64, args, samples: dict) -> dict:
         tk = tn
     torch.cuda.synchronize()
     res["fista100_explicit_fp32_s"] = time.perf_counter() - t0
-    log(f"FISTA 100 it: {t_f:.3f} s (Gram), {res['fista100_explicit_fp32_s']:.3f} s (explicit); "
+    log(f"FISTA 100 it: {t_f:.3f} s (Gram; {res['fista100_GB']:.1f} GB moved, "
+        f"{res['fista100_hbm_frac']:.0%} of HBM peak), {res['fista100_explicit_fp32_s']:.3f} s (explicit); "
         f"power 30 it {t_pow:.3f} s")
     del xs, zs, d, noise, clean
     # 16-bit libraries, batch 1
