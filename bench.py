@@ -47,16 +47,19 @@ def contraction_bytes(info: dict, nk: int, nz: int, nt: int, adjoint: bool, B: i
 
 def fista_gram_bytes(info: dict, nk: int, nz: int, nt: int, nxy: int, niter: int) -> int:
     """Bytes that pat_recon_fista's passes move with the Gram-block gradient
-    (periodic boundary, one object, nxy = nx * ny sensor points):
+    (periodic boundary, one object, nxy = nx * ny sensor points, the update
+    fused into the inverse transform as at fast sizes with rows of whole
+    16-byte units):
     set-up: the spectrum of d (row pass: d in, intermediate out; column pass:
     intermediate in, spectrum out), one A^T contraction, x and z cleared;
     per iteration: the spectrum of z (z in, two spectrum-sized
     intermediates), the Gram contraction (blocks, z^ and (A^T d)^ in, result
-    out), the inverse spectrum (three spectrum-sized passes, gradient out)
-    and the update (x, z, gradient in; x, z out)."""
+    out), the inverse spectrum's column pass (two spectrum-sized passes) and
+    its row pass with the update (one spectrum-sized pass in; x, z in and
+    out)."""
     n = nz * nxy
     setup = 4 * nt * nxy + 24 * nt * nk + contraction_bytes(info, nk, nz, nt, True) + 8 * n
-    per_iter = 28 * n + 72 * nz * nk + info["gram_bytes"]
+    per_iter = 20 * n + 72 * nz * nk + info["gram_bytes"]
     return setup + niter * per_iter
 
 

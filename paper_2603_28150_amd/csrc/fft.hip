@@ -260,27 +260,29 @@ __global__ __launch_bounds__(256) void k_fft_rows_r2c(const float* __restrict__ 
 }
 
 // ---------------------------------------------------------- rows, c2r (x)
-// f[s][j][i] = scale * sum_{m=0}^{N-1} exp(+2 pi i m i / N) F[m] - sub[s][j][i],
-// F Hermitian-extended from m = 0..N/2 (imaginary parts of m = 0, N/2 dropped),
-// stored for the samples i = 0..nxc-1 at transform columns sx*i (slices
-// f[s][ny][nxc]; the rest of the period is not stored)
-template <int N, int Q, bool GEN>
-__global__ __launch_bounds__(256) void k_fft_rows_c2r(const float2* __restrict__ T,
-                                                      float* __restrict__ f, int ny, int nxd,
-                                                      int sx, int S, int rs, float scale,
-                                                      const float* __restrict__ sub) {
+// LDS of the c2r row kernels: twiddles, and one buffer for the half spectra,
+// the exchange between the two DFT stages and the real rows
+template <int N, int Q>
+struct C2rLds {
+  static constexpr int NH = N / 2 + 1;
+  static constexpr int PAD = Split<N>::N2 * (Split<N>::N1 + 1) + 1;
+  static constexpr int BUF0 = (2 * Q * NH > Q * PAD) ? 2 * Q * NH : Q * PAD;
+  static constexpr int BUF = (BUF0 * 2 > 2 * Q * (N + 4)) ? BUF0 : (2 * Q * (N + 4) + 1) / 2;
+};
+
+// Unscaled inverse transforms of row j of the block's 2Q half-spectrum
+// slices s0 .. s0+2Q-1 (F Hermitian-extended from m = 0..N/2, imaginary
+// parts of m = 0, N/2 dropped); on return (after a barrier) real row sl is
+// in LDS at rows[sl * (N + 4)].
+template <int N, int Q>
+__device__ __forceinline__ float* c2r_rows_to_lds(const float2* __restrict__ T, int j, int s0, int S,
+                                                  int rs, float2* tw, float2* buf) {
   constexpr int N1 = Split<N>::N1, N2 = Split<N>::N2;
   constexpr int PX = Split<N>::N1 + 1;  // exchange row stride, see k_fft_rows_r2c
   constexpr int PAD = Split<N>::N2 * PX + 1;
   constexpr int NT = Q * N1;
   constexpr int NH = N / 2 + 1;
-  constexpr int BUF0 = (2 * Q * NH > Q * PAD) ? 2 * Q * NH : Q * PAD;
-  constexpr int BUF = (BUF0 * 2 > 2 * Q * (N + 4)) ? BUF0 : (2 * Q * (N + 4) + 1) / 2;
-  __shared__ float2 tw[N];
-  __shared__ float2 buf[BUF];
   const int tid = threadIdx.x;
-  const int j = blockIdx.x;
-  const int s0 = blockIdx.y * 2 * Q;
   constexpr int LIT = (NH * 2 * Q + NT - 1) / NT;
   float2 ld[LIT];
 #pragma unroll
@@ -341,6 +343,24 @@ __global__ __launch_bounds__(256) void k_fft_rows_c2r(const float2* __restrict__
     rows[(2 * q + 1) * (N + 4) + i] = w[k2].y;
   }
   __syncthreads();
+  return rows;
+}
+
+// f[s][j][i] = scale * sum_{m=0}^{N-1} exp(+2 pi i m i / N) F[m] - sub[s][j][i],
+// stored for the samples i = 0..nxc-1 at transform columns sx*i (slices
+// f[s][ny][nxc]; the rest of the period is not stored)
+template <int N, int Q, bool GEN>
+__global__ __launch_bounds__(256) void k_fft_rows_c2r(const float2* __restrict__ T,
+                                                      float* __restrict__ f, int ny, int nxd,
+                                                      int sx, int S, int rs, float scale,
+                                                      const float* __restrict__ sub) {
+  constexpr int NT = Q * Split<N>::N1;
+  __shared__ float2 tw[N];
+  __shared__ float2 buf[C2rLds<N, Q>::BUF];
+  const int tid = threadIdx.x;
+  const int j = blockIdx.x;
+  const int s0 = blockIdx.y * 2 * Q;
+  float* rows = c2r_rows_to_lds<N, Q>(T, j, s0, S, rs, tw, buf);
   constexpr int SIT = (2 * Q * (N / 4) + NT - 1) / NT;
   float4 sb4[SIT];
   if (sub) {
@@ -679,6 +699,75 @@ static void rows_r2c(const float* f, float2* T, int nyc, int nxc, int sx, int S,
     k_fft_rows_r2c<N, Q, true><<<grid, Q * Split<N>::N1, 0, st>>>(f, T, nyc, nxc, sx, S, rs);
 }
 
+// The same inverse transform with the FISTA update as its epilogue: the
+// transform is the gradient g = scale * c2r(X) - sub of slice s, of object
+// b = s / per_obj (every row block lies inside one object), and on the
+// stored columns (nxd of them, whole 16-byte units)
+//     x_old = x; x = prox(z - tau_b g); z = x + beta_b (x - x_old)
+// exactly as k_fista_update, without storing g.
+template <int N, int Q>
+__global__ __launch_bounds__(256) void k_fft_rows_c2r_fista(const float2* __restrict__ T,
+                                                            float* __restrict__ z, float* __restrict__ x,
+                                                            int ny, int nxd, int S, int rs, float scale,
+                                                            const float* __restrict__ sub, int per_obj,
+                                                            FistaBatch p, int32_t* __restrict__ nonfinite) {
+  constexpr int NT = Q * Split<N>::N1;
+  constexpr int SIT = (2 * Q * (N / 4) + NT - 1) / NT;
+  __shared__ float2 tw[N];
+  __shared__ float2 buf[C2rLds<N, Q>::BUF];
+  const int tid = threadIdx.x;
+  const int j = blockIdx.x;
+  const int s0 = blockIdx.y * 2 * Q;
+  const int ob = s0 / per_obj;
+  const FistaObj o = p.o[ob];
+  float* rows = c2r_rows_to_lds<N, Q>(T, j, s0, S, rs, tw, buf);
+  // the update's operands, all loads issued before the first use
+  float4 zz[SIT], xx[SIT], sb[SIT];
+#pragma unroll
+  for (int it = 0; it < SIT; ++it) {
+    const int u = tid + it * NT;
+    const int row = u / (N / 4), c4 = u % (N / 4);
+    const int s = s0 + row;
+    zz[it] = xx[it] = sb[it] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (u < 2 * Q * (N / 4) && s < S && 4 * c4 < nxd) {
+      const size_t off = ((size_t)s * ny + j) * nxd + 4 * c4;
+      zz[it] = *reinterpret_cast<const float4*>(z + off);
+      xx[it] = *reinterpret_cast<const float4*>(x + off);
+      if (sub) sb[it] = *reinterpret_cast<const float4*>(sub + off);
+    }
+  }
+  auto upd = [&](float r, float sv, float zv, float xo, float& xn, float& zn) {
+    const float g = r * scale - sv;
+    const float v = zv - o.tau * g;
+    if (o.nonneg) {
+      xn = fmaxf(v - o.thr, 0.f);
+    } else {
+      const float m = fmaxf(fabsf(v) - o.thr, 0.f);
+      xn = copysignf(m, v);
+    }
+    zn = xn + o.beta * (xn - xo);
+  };
+  bool bad = false;
+#pragma unroll
+  for (int it = 0; it < SIT; ++it) {
+    const int u = tid + it * NT;
+    const int row = u / (N / 4), c4 = u % (N / 4);
+    const int s = s0 + row;
+    if (u >= 2 * Q * (N / 4) || s >= S || 4 * c4 >= nxd) continue;
+    const float4 r = *reinterpret_cast<const float4*>(rows + row * (N + 4) + 4 * c4);
+    float4 xn, zn;
+    upd(r.x, sb[it].x, zz[it].x, xx[it].x, xn.x, zn.x);
+    upd(r.y, sb[it].y, zz[it].y, xx[it].y, xn.y, zn.y);
+    upd(r.z, sb[it].z, zz[it].z, xx[it].z, xn.z, zn.z);
+    upd(r.w, sb[it].w, zz[it].w, xx[it].w, xn.w, zn.w);
+    bad |= !(isfinite(xn.x) && isfinite(xn.y) && isfinite(xn.z) && isfinite(xn.w));
+    const size_t off = ((size_t)s * ny + j) * nxd + 4 * c4;
+    *reinterpret_cast<float4*>(x + off) = xn;
+    *reinterpret_cast<float4*>(z + off) = zn;
+  }
+  if (bad && nonfinite) nonfinite[ob] = 1;
+}
+
 template <int N, int Q>
 static void rows_c2r(const float2* T, float* f, int nyc, int nxc, int sx, int S, int rs, float scale,
                      const float* sub, hipStream_t st) {
@@ -687,6 +776,15 @@ static void rows_c2r(const float2* T, float* f, int nyc, int nxc, int sx, int S,
     k_fft_rows_c2r<N, Q, false><<<grid, Q * Split<N>::N1, 0, st>>>(T, f, nyc, nxc, sx, S, rs, scale, sub);
   else
     k_fft_rows_c2r<N, Q, true><<<grid, Q * Split<N>::N1, 0, st>>>(T, f, nyc, nxc, sx, S, rs, scale, sub);
+}
+
+template <int N, int Q>
+static void rows_c2r_fista(const float2* T, float* z, float* x, int nyc, int nxc, int S, int rs,
+                           float scale, const float* sub, int per_obj, const FistaBatch& p,
+                           int32_t* nonfinite, hipStream_t st) {
+  dim3 grid(nyc, (S + 2 * Q - 1) / (2 * Q));
+  k_fft_rows_c2r_fista<N, Q><<<grid, Q * Split<N>::N1, 0, st>>>(T, z, x, nyc, nxc, S, rs, scale, sub,
+                                                               per_obj, p, nonfinite);
 }
 
 // 8 packed sequences (16 real slices) per row block: small enough for several
@@ -813,6 +911,39 @@ pat_status fft2_c2r(const float2* X, float2* T, float* f, int fx, int fy, int nx
     default: return fail(PAT_EUNSUPPORTED, "transform size along x is not one of the FFT sizes");
   }
   PAT_LAUNCHED("fft rows c2r");
+  return PAT_OK;
+}
+
+
+bool fft2_c2r_fista_ok(int nxw, const FftChirp& ch, int S, int per_obj) {
+  return !ch.mx && (nxw & 3) == 0 && per_obj >= 1 && (S == per_obj || per_obj % (2 * kRowQ) == 0);
+}
+
+pat_status fft2_c2r_fista(const float2* X, float2* T, float* z, float* x, int fx, int fy, int nxw,
+                          int nyw, int S, int per_obj, float scale, const float* sub,
+                          const int32_t* rowmap, const FftChirp& ch, const FistaBatch& p,
+                          int32_t* nonfinite, hipStream_t st) {
+  if (S <= 0) return PAT_OK;
+  if (!extents_ok(fx, fy, nxw, nyw, 1, 1))
+    return fail(PAT_EINVAL, "fft: data extent does not fit the transform");
+  if (!fft2_c2r_fista_ok(nxw, ch, S, per_obj))
+    return fail(PAT_EUNSUPPORTED, "fft: the fused update needs a fast x axis, rows of whole 16-byte "
+                                  "units and row blocks inside one object");
+  const int nh = fx / 2 + 1;
+  const int rs = spec_stride(S);
+  if (ch.my && nyw != fy) return fail(PAT_EUNSUPPORTED, "fft: chirp-z axes take whole, unsampled slices");
+  if (ch.my)
+    PAT_TRY(cols_cz<+1>(X, T, fy, nh, S, rs, rowmap, nullptr, ch.cy, ch.by, ch.my, st));
+  else
+    PAT_TRY(cols<+1>(X, T, fy, nh, S, rs, rowmap, nullptr, fy, 1, nyw, 1, st));
+  switch (fx) {
+#define PAT_CASE(N) \
+    case N: PAT_ROWS(rows_c2r_fista, N, T, z, x, nyw, nxw, S, rs, scale, sub, per_obj, p, nonfinite, st); break;
+    PAT_FFT_SIZES(PAT_CASE)
+#undef PAT_CASE
+    default: return fail(PAT_EUNSUPPORTED, "transform size along x is not one of the FFT sizes");
+  }
+  PAT_LAUNCHED("fft rows c2r + FISTA update");
   return PAT_OK;
 }
 

@@ -65,7 +65,6 @@ pat_status hip_check(hipError_t e, const char* what) {
 }
 
 // ---------------------------------------------------------- geometry rules
-static bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
 
 // transform sizes the FFT kernels provide: 2^a 3^b, b <= 3, multiples of 4
 // in [16, 1024], at least 48 when b > 0
@@ -522,6 +521,36 @@ static pat_status run_AT(pat_op* op, const float* y, float* x, int B, const Work
                   op->rowmap, op->chirp, st);
 }
 
+// FISTA update with the gradient A^T r of B objects (r: data-shaped), the
+// update in the last pass of A^T's inverse transform when that pass allows
+// it (fft2_c2r_fista_ok), else A^T into the workspace and a separate update
+static pat_status run_AT_update(pat_op* op, const float* r, float* x, float* z, int B,
+                                const FistaBatch& p, int32_t* nonfinite, const Work& w, hipStream_t st) {
+  const pat_geometry& g = op->g;
+  if (!fft2_c2r_fista_ok(g.nx, op->chirp, B * g.nz, g.nz)) {
+    PAT_TRY(run_AT(op, r, w.U, B, w, st));
+    return fista_update(x, z, w.U, (long long)g.nz * g.nx * g.ny, B, p, nonfinite, st);
+  }
+  PAT_TRY(fft2_r2c(r, w.T, w.Ds, op->fx, op->fy, g.nx, g.ny, op->sx, op->sy, B * g.nt, op->rowmap, op->chirp, st));
+  PAT_TRY(run_contract(op, true, w.Ds, w.Xs, B, st));
+  return fft2_c2r_fista(w.Xs, w.T, z, x, op->fx, op->fy, g.nx, g.ny, B * g.nz, g.nz, inv_area(op), nullptr,
+                        op->rowmap, op->chirp, p, nonfinite, st);
+}
+
+// FISTA update with the gradient G z^ - b^ given as spectra (Gram path):
+// fused into the inverse transform's last pass when it allows it
+static pat_status gram_update(pat_op* op, const float2* gs, const float* sub, float* x, float* z, int B,
+                              const FistaBatch& p, int32_t* nonfinite, const Work& w, hipStream_t st) {
+  const pat_geometry& g = op->g;
+  if (!fft2_c2r_fista_ok(g.nx, op->chirp, B * g.nz, g.nz)) {
+    PAT_TRY(fft2_c2r(gs, w.T, w.U, op->fx, op->fy, g.nx, g.ny, 1, 1, B * g.nz, inv_area(op), sub,
+                     op->rowmap, op->chirp, st));
+    return fista_update(x, z, w.U, (long long)g.nz * g.nx * g.ny, B, p, nonfinite, st);
+  }
+  return fft2_c2r_fista(gs, w.T, z, x, op->fx, op->fy, g.nx, g.ny, B * g.nz, g.nz, inv_area(op), sub,
+                        op->rowmap, op->chirp, p, nonfinite, st);
+}
+
 }  // namespace pat
 
 using namespace pat;
@@ -909,26 +938,6 @@ pat_status pat_recon_fista(pat_op* op, const float* d, float* x, int32_t niter, 
   FistaBatch p;
   std::memset(&p, 0, sizeof(p));
   for (int k = 1; k <= niter; ++k) {
-    if (normal) {
-      // gradient A^T (A z - d) = A^T A z - A^T d, per frequency: G z^ - b^
-      PAT_TRY(fft2_r2c(w.Z, w.T, w.Xs, op->fx, op->fy, g.nx, g.ny, 1, 1, g.nz, op->rowmap, op->chirp, st));
-      PAT_TRY(run_gram(op, w.Xs, w.Gs, w.Bs, 1, st));
-      PAT_TRY(fft2_c2r(w.Gs, w.T, w.U, op->fx, op->fy, g.nx, g.ny, 1, 1, g.nz, inv, nullptr, op->rowmap, op->chirp, st));
-      if (trace) {
-        // 1/2 ||A z - d||^2 = 1/2 (<z, g> - <z, b> + ||d||^2), float64 sums
-        PAT_TRY(dot_f64(w.Z, w.U, n, w.part64, w.s64 + 0, st));
-        PAT_TRY(dot_f64(w.Z, w.V, n, w.part64, w.s64 + 1, st));
-        PAT_TRY(trace_combine(trace + (k - 1), w.s64, st));
-      }
-    } else {
-      // explicit: residual r = A z - d (fused into the inverse transform), g = A^T r
-      PAT_TRY(run_A(op, w.Z, w.R, 1, d, w, st));
-      if (trace) {
-        PAT_TRY(dot_f64(w.R, w.R, nd, w.part64, w.s64 + 0, st));
-        PAT_TRY(trace_combine(trace + (k - 1), w.s64, st));
-      }
-      PAT_TRY(run_AT(op, w.R, w.U, 1, w, st));
-    }
     double beta = 0.0;
     if (momentum) {
       const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
@@ -939,7 +948,30 @@ pat_status pat_recon_fista(pat_op* op, const float* d, float* x, int32_t niter, 
     p.o[0].thr = tau * lambda;
     p.o[0].beta = (float)beta;
     p.o[0].nonneg = nonneg ? 1 : 0;
-    PAT_TRY(fista_update(x, w.Z, w.U, n, 1, p, nullptr, st));
+    if (normal) {
+      // gradient A^T (A z - d) = A^T A z - A^T d, per frequency: G z^ - b^
+      PAT_TRY(fft2_r2c(w.Z, w.T, w.Xs, op->fx, op->fy, g.nx, g.ny, 1, 1, g.nz, op->rowmap, op->chirp, st));
+      PAT_TRY(run_gram(op, w.Xs, w.Gs, w.Bs, 1, st));
+      if (trace) {
+        // the data term needs the gradient itself:
+        // 1/2 ||A z - d||^2 = 1/2 (<z, g> - <z, b> + ||d||^2), float64 sums
+        PAT_TRY(fft2_c2r(w.Gs, w.T, w.U, op->fx, op->fy, g.nx, g.ny, 1, 1, g.nz, inv, nullptr, op->rowmap, op->chirp, st));
+        PAT_TRY(dot_f64(w.Z, w.U, n, w.part64, w.s64 + 0, st));
+        PAT_TRY(dot_f64(w.Z, w.V, n, w.part64, w.s64 + 1, st));
+        PAT_TRY(trace_combine(trace + (k - 1), w.s64, st));
+        PAT_TRY(fista_update(x, w.Z, w.U, n, 1, p, nullptr, st));
+      } else {
+        PAT_TRY(gram_update(op, w.Gs, nullptr, x, w.Z, 1, p, nullptr, w, st));
+      }
+    } else {
+      // explicit: residual r = A z - d (fused into the inverse transform), g = A^T r
+      PAT_TRY(run_A(op, w.Z, w.R, 1, d, w, st));
+      if (trace) {
+        PAT_TRY(dot_f64(w.R, w.R, nd, w.part64, w.s64 + 0, st));
+        PAT_TRY(trace_combine(trace + (k - 1), w.s64, st));
+      }
+      PAT_TRY(run_AT_update(op, w.R, x, w.Z, 1, p, nullptr, w, st));
+    }
   }
   return PAT_OK;
 }
@@ -956,8 +988,6 @@ pat_status pat_fista_step(pat_op* op, int32_t B, const float* d, float* x, float
   PAT_TRY(check_ptr(z, "z"));
   if (!beta || !tau || !lambda || !nonneg) return fail(PAT_EINVAL, "per-object parameters are null");
   hipStream_t st = (hipStream_t)stream;
-  const pat_geometry& g = op->g;
-  const long long n = (long long)g.nz * g.nx * g.ny;
   FistaBatch p;
   std::memset(&p, 0, sizeof(p));
   for (int b = 0; b < B; ++b) {
@@ -968,8 +998,7 @@ pat_status pat_fista_step(pat_op* op, int32_t B, const float* d, float* x, float
     p.o[b].nonneg = nonneg[b] ? 1 : 0;
   }
   PAT_TRY(run_A(op, z, w.R, B, d, w, st));
-  PAT_TRY(run_AT(op, w.R, w.U, B, w, st));
-  return fista_update(x, z, w.U, n, B, p, nonfinite, st);
+  return run_AT_update(op, w.R, x, z, B, p, nonfinite, w, st);
 }
 
 pat_status pat_fista_step_normal(pat_op* op, int32_t B, const float* atd, float* x, float* z,
@@ -987,8 +1016,6 @@ pat_status pat_fista_step_normal(pat_op* op, int32_t B, const float* atd, float*
   PAT_TRY(check_ptr(z, "z"));
   if (!beta || !tau || !lambda || !nonneg) return fail(PAT_EINVAL, "per-object parameters are null");
   hipStream_t st = (hipStream_t)stream;
-  const pat_geometry& g = op->g;
-  const long long n = (long long)g.nz * g.nx * g.ny;
   FistaBatch p;
   std::memset(&p, 0, sizeof(p));
   for (int b = 0; b < B; ++b) {
@@ -998,11 +1025,10 @@ pat_status pat_fista_step_normal(pat_op* op, int32_t B, const float* atd, float*
     p.o[b].beta = (float)beta[b];
     p.o[b].nonneg = nonneg[b] ? 1 : 0;
   }
+  const pat_geometry& g = op->g;
   PAT_TRY(fft2_r2c(z, w.T, w.Xs, op->fx, op->fy, g.nx, g.ny, 1, 1, B * g.nz, op->rowmap, op->chirp, st));
   PAT_TRY(run_gram(op, w.Xs, w.Gs, nullptr, B, st));
-  PAT_TRY(fft2_c2r(w.Gs, w.T, w.U, op->fx, op->fy, g.nx, g.ny, 1, 1, B * g.nz, inv_area(op), atd,
-                   op->rowmap, op->chirp, st));  // U = A^T A z - A^T d
-  return fista_update(x, z, w.U, n, B, p, nonfinite, st);
+  return gram_update(op, w.Gs, atd, x, z, B, p, nonfinite, w, st);  // gradient A^T A z - A^T d
 }
 
 pat_status pat_adjoint_check(pat_op* op, const float* x, const float* y, double* rel_out, void* ws,

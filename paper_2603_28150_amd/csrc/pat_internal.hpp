@@ -162,6 +162,17 @@ struct FistaBatch {
 // per object b: x_old = x; x = prox(z - tau g); z = x + beta (x - x_old)
 pat_status fista_update(float* x, float* z, const float* g, long long n_per_obj, int B,
                         const FistaBatch& p, int32_t* nonfinite, hipStream_t st);
+// fft2_c2r (unsampled) and fista_update in one: the gradient of slice s is
+// g = scale * c2r(X) - sub, of object s / per_obj, and x, z (slices like
+// the inverse transform's output) are updated in its last pass without g
+// being stored.  Needs a fast x axis, nxw % 4 == 0 and per_obj a multiple
+// of 16 unless S == per_obj (EUNSUPPORTED otherwise; fft2_c2r_fista_ok says
+// beforehand).
+bool fft2_c2r_fista_ok(int nxw, const FftChirp& ch, int S, int per_obj);
+pat_status fft2_c2r_fista(const float2* X, float2* T, float* z, float* x, int fx, int fy, int nxw,
+                          int nyw, int S, int per_obj, float scale, const float* sub,
+                          const int32_t* rowmap, const FftChirp& ch, const FistaBatch& p,
+                          int32_t* nonfinite, hipStream_t st);
 
 constexpr int kRedBlocks = 512;
 

@@ -241,6 +241,38 @@ def test_batched_fista_step_isolates_objects():
     assert int(bad.sum()) == 0
 
 
+@pytest.mark.parametrize("name", ["tiny", "ragged"])  # update fused into the last transform pass (16
+def test_nonfinite_iterates_flag_only_their_object(name):  # depths) and separate (13)
+    # a step of 3e38 for object 1 overflows its iterate to +-inf wherever its
+    # gradient is not tiny (the threshold tau * lambda stays 0); the flag is
+    # raised for it alone and the other objects step as they do alone
+    # (explicit and normal step)
+    g, op, Hh = setup(name)
+    B = 3
+    ds = np.stack([inputs.gaussian_random((g.nt, g.ny, g.nx), seed=80 + b) for b in range(B)])
+    tau = float(np.float32(0.5 / solvers.norm_exact(Hh)))
+    taus = [tau, float(np.float32(3e38)), tau]
+    atd = op.apply_AT(dev(ds))
+    for normal in (False, True):
+        x = torch.zeros((B, g.nz, g.ny, g.nx), device="cuda")
+        z = dev(np.stack([inputs.gaussian_random((g.nz, g.ny, g.nx), seed=90 + b) for b in range(B)]))
+        bad = torch.zeros(B, dtype=torch.int32, device="cuda")
+        if normal:
+            op.fista_step_normal(atd, x, z, [0.5] * B, taus, [0.0] * B, [False] * B, nonfinite=bad)
+        else:
+            op.fista_step(dev(ds), x, z, [0.5] * B, taus, [0.0] * B, [False] * B, nonfinite=bad)
+        assert bad.tolist() == [0, 1, 0], normal
+        for b in (0, 2):
+            x1 = torch.zeros((1, g.nz, g.ny, g.nx), device="cuda")
+            z1 = dev(inputs.gaussian_random((g.nz, g.ny, g.nx), seed=90 + b))[None]
+            if normal:
+                op.fista_step_normal(atd[b:b + 1].contiguous(), x1, z1, [0.5], [tau], [0.0], [False])
+            else:
+                op.fista_step(dev(ds[b])[None], x1, z1, [0.5], [tau], [0.0], [False])
+            assert torch.isfinite(x[b]).all()
+            assert rel(host(x[b]), host(x1[0])) < 1e-5, (normal, b)
+
+
 @pytest.mark.parametrize("kind", ["bf16", "f16"])
 def test_quantised_library(kind):
     g = TINY
