@@ -2,7 +2,8 @@
 H^_k H^_k^T (one nz x nz float32 block per class) across depths and folds.
 
 Depths from a two-chunk row (nz = 5) to rows that the contraction splits
-over two workgroups (nz = 520), ragged and whole 16-byte chunks, and the
+over two workgroups (nz = 520) or gives two chunks per lane (nz = 1100, in
+a batch), ragged and whole 16-byte chunks, and the
 three folds (radial, octant, quadrant); the batched normal step is checked
 against the oracle's A^T A z directly and FISTA through the Gram blocks
 against the oracle's FISTA.  Libraries whose gradient couples frequencies
@@ -27,6 +28,7 @@ CASES = {
     "q30":   (24, 16, 30, 36, "f32"),    # quadrant (2), non-square
     "r256":  (16, 16, 256, 40, "f32"),   # radial; 64 chunks
     "r520":  (16, 16, 520, 16, "f32"),   # 130 chunks: one object's rows split over two workgroups
+    "r1100": (16, 16, 1100, 8, "f32"),   # 275 chunks: two per lane in a batch
 }
 
 
