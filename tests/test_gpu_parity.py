@@ -301,6 +301,21 @@ def test_quantised_library(kind):
     assert op.adjoint_check(dev(x), dev(d)) < 1e-5
 
 
+@pytest.mark.parametrize("kind", ["bf16", "f16"])
+def test_quantised_long_rows(kind):
+    # 1,100 samples: A's 16-bit rows of 138 16-byte chunks are split over two
+    # workgroups per item (the single-object path); against the oracle
+    # applying the same quantised library
+    g = Geometry(16, 16, 8, 1100, 1e-4, 1e-4, 1e-4, 2e-8, 1500.0)
+    op = Operator(g, kind)
+    Hq, _ = quant.quantise(hlib.H_half(og(g)), kind)
+    x = inputs.gaussian_random((g.nz, g.ny, g.nx), seed=85)
+    d = inputs.gaussian_random((g.nt, g.ny, g.nx), seed=86)
+    assert rel(host(op.apply_A(dev(x))), ops.A_fft(Hq, x)) < 2e-5
+    assert rel(host(op.apply_AT(dev(d))), ops.AT_fft(Hq, d)) < 2e-5
+    assert op.adjoint_check(dev(x), dev(d)) < 1e-5
+
+
 @pytest.mark.parametrize("name", ["tiny", "ragged"])
 def test_stage_calls_compose_apply_and_row_map(name):
     g, op, Hh = setup(name)
