@@ -501,15 +501,35 @@ __global__ __launch_bounds__(256) void k_fft_rows_r2c_cz(const float* __restrict
   }
   __syncthreads();
   lds_fft<M, -1>(ex + q * PAD, tw, t);
-  for (int e = tid; e < Q * M; e += NT) {
-    const int qq = e / M, n = e % M;
-    ex[qq * PAD + n] = cmul(ex[qq * PAD + n], bz[n]);
+  // pointwise passes: every table load of the pass issued before its first
+  // use (Q * M = N2 * NT elements, N2 per thread)
+  {
+    float2 c[N2];
+#pragma unroll
+    for (int it = 0; it < N2; ++it) c[it] = bz[(tid + it * NT) % M];
+#pragma unroll
+    for (int it = 0; it < N2; ++it) {
+      const int e = tid + it * NT, qq = e / M, n = e % M;
+      ex[qq * PAD + n] = cmul(ex[qq * PAD + n], c[it]);
+    }
   }
   __syncthreads();
   lds_fft<M, +1>(ex + q * PAD, tw, t);
-  for (int e = tid; e < Q * N; e += NT) {
-    const int qq = e / N, n = e % N;
-    ex[qq * PAD + n] = cmul(ex[qq * PAD + n], cconj(cz[n]));
+  {
+    float2 c[N2];
+#pragma unroll
+    for (int it = 0; it < N2; ++it) {
+      const int e = tid + it * NT;
+      c[it] = e < Q * N ? cz[e % N] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int it = 0; it < N2; ++it) {
+      const int e = tid + it * NT;
+      if (e < Q * N) {
+        const int qq = e / N, n = e % N;
+        ex[qq * PAD + n] = cmul(ex[qq * PAD + n], cconj(c[it]));
+      }
+    }
   }
   __syncthreads();
   // separate the two packed real transforms and store slice-fastest
@@ -552,52 +572,97 @@ __global__ __launch_bounds__(256) void k_fft_rows_c2r_cz(const float2* __restric
   const int j = blockIdx.x;
   const int s0 = blockIdx.y * 2 * Q;
   const int NH = N / 2 + 1;
-  for (int idx = tid; idx < NH * 2 * Q; idx += NT) {
-    const int m = idx / (2 * Q), sl = idx % (2 * Q);
-    const int s = s0 + sl;
-    float2 F = s < S ? T[(size_t)(j * NH + m) * rs + s] : make_float2(0.f, 0.f);
-    if (m == 0 || m == N / 2) F.y = 0.f;
-    hb[sl * NH + m] = F;
+  // every global load of a pass is issued before its first use: the half
+  // spectra (N <= M / 2, so NH <= M / 4 + 1), then the tables c and the
+  // kernel DFT, then c and the subtrahend of the output pass
+  {
+    constexpr int HIT = ((M / 4 + 1) * 2 * Q + NT - 1) / NT;
+    float2 hv[HIT];
+#pragma unroll
+    for (int it = 0; it < HIT; ++it) {
+      const int idx = tid + it * NT;
+      const int m = idx / (2 * Q), sl = idx % (2 * Q);
+      hv[it] = (idx < NH * 2 * Q && s0 + sl < S) ? T[(size_t)(j * NH + m) * rs + s0 + sl] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int it = 0; it < HIT; ++it) {
+      const int idx = tid + it * NT;
+      if (idx < NH * 2 * Q) {
+        const int m = idx / (2 * Q), sl = idx % (2 * Q);
+        float2 F = hv[it];
+        if (m == 0 || m == N / 2) F.y = 0.f;
+        hb[sl * NH + m] = F;
+      }
+    }
   }
   load_twiddles<M, -1>(tw, tid, NT);
   __syncthreads();
   // z = Fa + i Fb over the full period (Hermitian extension), times c
-  for (int e = tid; e < Q * M; e += NT) {
-    const int qq = e / M, i = e % M;
-    float2 v = make_float2(0.f, 0.f);
-    if (i < N) {
-      float2 fa, fb;
-      if (i <= N / 2) {
-        fa = hb[(2 * qq) * NH + i];
-        fb = hb[(2 * qq + 1) * NH + i];
-      } else {
-        fa = cconj(hb[(2 * qq) * NH + N - i]);
-        fb = cconj(hb[(2 * qq + 1) * NH + N - i]);
-      }
-      v = cmul(make_float2(fa.x - fb.y, fa.y + fb.x), cz[i]);
+  {
+    float2 c[N2];
+#pragma unroll
+    for (int it = 0; it < N2; ++it) {
+      const int i = (tid + it * NT) % M;
+      c[it] = i < N ? cz[i] : make_float2(0.f, 0.f);
     }
-    ex[qq * PAD + i] = v;
+#pragma unroll
+    for (int it = 0; it < N2; ++it) {
+      const int e = tid + it * NT, qq = e / M, i = e % M;
+      float2 v = make_float2(0.f, 0.f);
+      if (i < N) {
+        float2 fa, fb;
+        if (i <= N / 2) {
+          fa = hb[(2 * qq) * NH + i];
+          fb = hb[(2 * qq + 1) * NH + i];
+        } else {
+          fa = cconj(hb[(2 * qq) * NH + N - i]);
+          fb = cconj(hb[(2 * qq + 1) * NH + N - i]);
+        }
+        v = cmul(make_float2(fa.x - fb.y, fa.y + fb.x), c[it]);
+      }
+      ex[qq * PAD + i] = v;
+    }
   }
   __syncthreads();
   lds_fft<M, -1>(ex + q * PAD, tw, t);
-  for (int e = tid; e < Q * M; e += NT) {
-    const int qq = e / M, n = e % M;
-    ex[qq * PAD + n] = cmul(ex[qq * PAD + n], cconj(bz[n]));
+  {
+    float2 c[N2];
+#pragma unroll
+    for (int it = 0; it < N2; ++it) c[it] = bz[(tid + it * NT) % M];
+#pragma unroll
+    for (int it = 0; it < N2; ++it) {
+      const int e = tid + it * NT, qq = e / M, n = e % M;
+      ex[qq * PAD + n] = cmul(ex[qq * PAD + n], cconj(c[it]));
+    }
   }
   __syncthreads();
   lds_fft<M, +1>(ex + q * PAD, tw, t);
   // real rows 2q (re) and 2q+1 (im)
-  for (int e = tid; e < Q * N; e += NT) {
-    const int qq = e / N, n = e % N;
-    const int s = s0 + 2 * qq;
-    const float2 v = cmul(ex[qq * PAD + n], cz[n]);
-    if (s < S) {
-      const size_t o = ((size_t)s * ny + j) * N + n;
-      f[o] = v.x * scale - (sub ? sub[o] : 0.f);
+  {
+    float2 c[N2], sv[N2];
+#pragma unroll
+    for (int it = 0; it < N2; ++it) {
+      const int e = tid + it * NT;
+      c[it] = sv[it] = make_float2(0.f, 0.f);
+      if (e < Q * N) {
+        const int qq = e / N, n = e % N;
+        const int s = s0 + 2 * qq;
+        c[it] = cz[n];
+        if (sub) {
+          if (s < S) sv[it].x = sub[((size_t)s * ny + j) * N + n];
+          if (s + 1 < S) sv[it].y = sub[((size_t)(s + 1) * ny + j) * N + n];
+        }
+      }
     }
-    if (s + 1 < S) {
-      const size_t o = ((size_t)(s + 1) * ny + j) * N + n;
-      f[o] = v.y * scale - (sub ? sub[o] : 0.f);
+#pragma unroll
+    for (int it = 0; it < N2; ++it) {
+      const int e = tid + it * NT;
+      if (e >= Q * N) continue;
+      const int qq = e / N, n = e % N;
+      const int s = s0 + 2 * qq;
+      const float2 v = cmul(ex[qq * PAD + n], c[it]);
+      if (s < S) f[((size_t)s * ny + j) * N + n] = v.x * scale - sv[it].x;
+      if (s + 1 < S) f[((size_t)(s + 1) * ny + j) * N + n] = v.y * scale - sv[it].y;
     }
   }
 }
