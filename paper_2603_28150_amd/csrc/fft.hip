@@ -563,7 +563,7 @@ __global__ __launch_bounds__(256) void k_fft_rows_c2r_cz(const float2* __restric
   constexpr int N1 = Split<M>::N1, N2 = Split<M>::N2, PX = N1 + 1;
   constexpr int PAD = N2 * PX + 1;
   constexpr int NT = Q * N1;
-  constexpr int NHMAX = kChirpMaxN / 2 + 1;
+  constexpr int NHMAX = M / 4 + 1;  // N <= M / 2
   __shared__ float2 tw[M];
   __shared__ float2 ex[Q * PAD];
   __shared__ float2 hb[2 * Q * NHMAX];
