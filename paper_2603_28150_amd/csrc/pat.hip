@@ -537,8 +537,10 @@ static pat_status run_AT_update(pat_op* op, const float* r, float* x, float* z, 
                         op->rowmap, op->chirp, p, nonfinite, st);
 }
 
-// FISTA update with the gradient G z^ - b^ given as spectra (Gram path):
-// fused into the inverse transform's last pass when it allows it
+// FISTA update with the Gram-path gradient: the inverse transform of the
+// spectra gs (G z^ - b^, or G z^ with sub = A^T d subtracted after the
+// transform), the update fused into the transform's last pass when it
+// allows it
 static pat_status gram_update(pat_op* op, const float2* gs, const float* sub, float* x, float* z, int B,
                               const FistaBatch& p, int32_t* nonfinite, const Work& w, hipStream_t st) {
   const pat_geometry& g = op->g;
