@@ -49,17 +49,19 @@ def fista_gram_bytes(info: dict, nk: int, nz: int, nt: int, nxy: int, niter: int
     """Bytes that pat_recon_fista's passes move with the Gram-block gradient
     (periodic boundary, one object, nxy = nx * ny sensor points, the update
     fused into the inverse transform as at fast sizes with rows of whole
-    16-byte units):
+    16-byte units, no trace):
     set-up: the spectrum of d (row pass: d in, intermediate out; column pass:
-    intermediate in, spectrum out), one A^T contraction, x and z cleared;
-    per iteration: the spectrum of z (z in, two spectrum-sized
-    intermediates), the Gram contraction (blocks, z^ and (A^T d)^ in, result
-    out), the inverse spectrum's column pass (two spectrum-sized passes) and
-    its row pass with the update (one spectrum-sized pass in; x, z in and
-    out)."""
+    intermediate in, spectrum out), one A^T contraction, x and z cleared, and
+    z read by the first iteration's row pass;
+    per iteration: the spectrum of z (its row pass done by the previous
+    update: the column pass moves two spectrum-sized arrays), the Gram
+    contraction (blocks, z^ and (A^T d)^ in, result out), the inverse
+    spectrum's column pass (two spectrum-sized passes) and its row pass with
+    the update and the next row pass (one spectrum-sized array in and one
+    out; x, z in and out)."""
     n = nz * nxy
-    setup = 4 * nt * nxy + 24 * nt * nk + contraction_bytes(info, nk, nz, nt, True) + 8 * n
-    per_iter = 20 * n + 72 * nz * nk + info["gram_bytes"]
+    setup = 4 * nt * nxy + 24 * nt * nk + contraction_bytes(info, nk, nz, nt, True) + 8 * n + 4 * n
+    per_iter = 16 * n + 72 * nz * nk + info["gram_bytes"]
     return setup + niter * per_iter
 
 

@@ -144,6 +144,59 @@ __global__ __launch_bounds__(512) void k_fft_cols(const float2* __restrict__ in,
 }
 
 // ---------------------------------------------------------- rows, r2c (x)
+// Forward transforms of a block's Q packed sequences, in LDS at
+// ex[q * PAD + n] = f[2q][n] + i f[2q+1][n] (n < N, written before a
+// barrier; tw holds the forward twiddles), and the stores of the two real
+// half spectra of each, slice-fastest: T[(j*NH + m)*rs + s0 + sl].
+template <int N, int Q>
+__device__ __forceinline__ void r2c_rows_from_lds(float2* ex, const float2* tw, float2* __restrict__ T,
+                                                  int j, int s0, int S, int rs) {
+  constexpr int N1 = Split<N>::N1, N2 = Split<N>::N2;
+  constexpr int PX = Split<N>::N1 + 1;
+  constexpr int PAD = Split<N>::N2 * PX + 1;
+  constexpr int NT = Q * N1;
+  constexpr int NH = N / 2 + 1;
+  const int tid = threadIdx.x;
+  const int t = tid % N1, q = tid / N1;
+  float2 v[N1];
+  if (t < N2) {
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) v[n1] = ex[q * PAD + t + N2 * n1];
+  }
+  __syncthreads();
+  if (t < N2) {
+    dft<N1, -1>(v);
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) ex[q * PAD + t * PX + k1] = cmul(v[k1], tw[t * k1]);
+  }
+  __syncthreads();
+  float2 w[N2];
+#pragma unroll
+  for (int n2 = 0; n2 < N2; ++n2) w[n2] = ex[q * PAD + n2 * PX + t];
+  dft<N2, -1>(w);
+  __syncthreads();
+#pragma unroll
+  for (int k2 = 0; k2 < N2; ++k2) ex[q * PAD + t + N1 * k2] = w[k2];
+  __syncthreads();
+  // separate the two packed real transforms and store slice-fastest
+  for (int idx = tid; idx < NH * 2 * Q; idx += NT) {
+    const int m = idx / (2 * Q), sl = idx % (2 * Q);
+    const int s = s0 + sl;
+    if (s >= S) continue;
+    const int qq = sl >> 1;
+    const float2 zm = ex[qq * PAD + m];
+    const float2 zc = cconj(ex[qq * PAD + (m == 0 ? 0 : N - m)]);
+    float2 r;
+    if ((sl & 1) == 0) {
+      r = make_float2(0.5f * (zm.x + zc.x), 0.5f * (zm.y + zc.y));
+    } else {
+      const float2 d = csub(zm, zc);
+      r = make_float2(0.5f * d.y, -0.5f * d.x);
+    }
+    T[(size_t)(j * NH + m) * rs + s] = r;
+  }
+}
+
 // T[(j*nh + m)*rs + s] = sum_{i < nxc} exp(-2 pi i m sx i / N) f[s][j][i],  m = 0..N/2,
 // for the ny rows j of slices f[s][ny][nxc]: sample i sits at transform
 // column sx*i, every other column of the length-N row is zero
@@ -156,17 +209,15 @@ template <int N, int Q, bool GEN>  // Q packed complex sequences = 2Q real slice
 __global__ __launch_bounds__(256) void k_fft_rows_r2c(const float* __restrict__ f,
                                                       float2* __restrict__ T, int ny, int nxd,
                                                       int sx, int S, int rs) {
-  constexpr int N1 = Split<N>::N1, N2 = Split<N>::N2;
+  constexpr int N1 = Split<N>::N1;
   // per packed sequence: N values in natural order, or the N2 x N1 exchange
   // with rows padded to N1 + 1 (lanes write their N1 outputs to separate banks)
   constexpr int PX = Split<N>::N1 + 1;
   constexpr int PAD = Split<N>::N2 * PX + 1;
   constexpr int NT = Q * N1;
-  constexpr int NH = N / 2 + 1;
   __shared__ float2 tw[N];
   __shared__ float2 ex[Q * PAD];
   const int tid = threadIdx.x;
-  const int t = tid % N1, q = tid / N1;
   const int j = blockIdx.x;
   const int s0 = blockIdx.y * 2 * Q;
   load_twiddles<N, -1>(tw, tid, NT);
@@ -220,43 +271,7 @@ __global__ __launch_bounds__(256) void k_fft_rows_r2c(const float* __restrict__ 
     }
   }
   __syncthreads();
-  float2 v[N1];
-  if (t < N2) {
-#pragma unroll
-    for (int n1 = 0; n1 < N1; ++n1) v[n1] = ex[q * PAD + t + N2 * n1];
-  }
-  __syncthreads();
-  if (t < N2) {
-    dft<N1, -1>(v);
-#pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) ex[q * PAD + t * PX + k1] = cmul(v[k1], tw[t * k1]);
-  }
-  __syncthreads();
-  float2 w[N2];
-#pragma unroll
-  for (int n2 = 0; n2 < N2; ++n2) w[n2] = ex[q * PAD + n2 * PX + t];
-  dft<N2, -1>(w);
-  __syncthreads();
-#pragma unroll
-  for (int k2 = 0; k2 < N2; ++k2) ex[q * PAD + t + N1 * k2] = w[k2];
-  __syncthreads();
-  // separate the two packed real transforms and store slice-fastest
-  for (int idx = tid; idx < NH * 2 * Q; idx += NT) {
-    const int m = idx / (2 * Q), sl = idx % (2 * Q);
-    const int s = s0 + sl;
-    if (s >= S) continue;
-    const int qq = sl >> 1;
-    const float2 zm = ex[qq * PAD + m];
-    const float2 zc = cconj(ex[qq * PAD + (m == 0 ? 0 : N - m)]);
-    float2 r;
-    if ((sl & 1) == 0) {
-      r = make_float2(0.5f * (zm.x + zc.x), 0.5f * (zm.y + zc.y));
-    } else {
-      const float2 d = csub(zm, zc);
-      r = make_float2(0.5f * d.y, -0.5f * d.x);
-    }
-    T[(size_t)(j * NH + m) * rs + s] = r;
-  }
+  r2c_rows_from_lds<N, Q>(ex, tw, T, j, s0, S, rs);
 }
 
 // ---------------------------------------------------------- rows, c2r (x)
@@ -769,13 +784,16 @@ static void rows_r2c(const float* f, float2* T, int nyc, int nxc, int sx, int S,
 // b = s / per_obj (every row block lies inside one object), and on the
 // stored columns (nxd of them, whole 16-byte units)
 //     x_old = x; x = prox(z - tau_b g); z = x + beta_b (x - x_old)
-// exactly as k_fista_update, without storing g.
-template <int N, int Q>
-__global__ __launch_bounds__(256) void k_fft_rows_c2r_fista(const float2* __restrict__ T,
-                                                            float* __restrict__ z, float* __restrict__ x,
-                                                            int ny, int nxd, int S, int rs, float scale,
-                                                            const float* __restrict__ sub, int per_obj,
-                                                            FistaBatch p, int32_t* __restrict__ nonfinite) {
+// exactly as k_fista_update, without storing g.  NEXT: the block then runs
+// the next iteration's forward row pass on its rows of the new z (zero past
+// nxd), Tn[(j*NH + m)*rs + s] as k_fft_rows_r2c writes it; Tn may be T (the
+// block rewrites exactly the entries it read).
+template <int N, int Q, bool NEXT>
+__global__ __launch_bounds__(256) void k_fft_rows_c2r_fista(const float2* T, float* __restrict__ z,
+                                                            float* __restrict__ x, int ny, int nxd, int S,
+                                                            int rs, float scale, const float* __restrict__ sub,
+                                                            int per_obj, FistaBatch p,
+                                                            int32_t* __restrict__ nonfinite, float2* Tn) {
   constexpr int NT = Q * Split<N>::N1;
   constexpr int SIT = (2 * Q * (N / 4) + NT - 1) / NT;
   __shared__ float2 tw[N];
@@ -818,7 +836,10 @@ __global__ __launch_bounds__(256) void k_fft_rows_c2r_fista(const float2* __rest
     const int u = tid + it * NT;
     const int row = u / (N / 4), c4 = u % (N / 4);
     const int s = s0 + row;
-    if (u >= 2 * Q * (N / 4) || s >= S || 4 * c4 >= nxd) continue;
+    if (u >= 2 * Q * (N / 4) || s >= S || 4 * c4 >= nxd) {
+      zz[it] = make_float4(0.f, 0.f, 0.f, 0.f);  // the next row pass sees zeros there
+      continue;
+    }
     const float4 r = *reinterpret_cast<const float4*>(rows + row * (N + 4) + 4 * c4);
     float4 xn, zn;
     upd(r.x, sb[it].x, zz[it].x, xx[it].x, xn.x, zn.x);
@@ -829,8 +850,29 @@ __global__ __launch_bounds__(256) void k_fft_rows_c2r_fista(const float2* __rest
     const size_t off = ((size_t)s * ny + j) * nxd + 4 * c4;
     *reinterpret_cast<float4*>(x + off) = xn;
     *reinterpret_cast<float4*>(z + off) = zn;
+    zz[it] = zn;
   }
   if (bad && nonfinite) nonfinite[ob] = 1;
+  if constexpr (NEXT) {
+    // rows of the new z into LDS, packed in pairs as k_fft_rows_r2c packs
+    // them (the buffer is free once every thread has read its rows)
+    constexpr int PAD = C2rLds<N, Q>::PAD;
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < SIT; ++it) {
+      const int u = tid + it * NT;
+      if (u >= 2 * Q * (N / 4)) break;
+      const int row = u / (N / 4), c4 = u % (N / 4);
+      float* zp = reinterpret_cast<float*>(buf + (row >> 1) * PAD + 4 * c4) + (row & 1);
+      zp[0] = zz[it].x;
+      zp[2] = zz[it].y;
+      zp[4] = zz[it].z;
+      zp[6] = zz[it].w;
+    }
+    load_twiddles<N, -1>(tw, tid, NT);
+    __syncthreads();
+    r2c_rows_from_lds<N, Q>(buf, tw, Tn, j, s0, S, rs);
+  }
 }
 
 template <int N, int Q>
@@ -846,10 +888,14 @@ static void rows_c2r(const float2* T, float* f, int nyc, int nxc, int sx, int S,
 template <int N, int Q>
 static void rows_c2r_fista(const float2* T, float* z, float* x, int nyc, int nxc, int S, int rs,
                            float scale, const float* sub, int per_obj, const FistaBatch& p,
-                           int32_t* nonfinite, hipStream_t st) {
+                           int32_t* nonfinite, float2* Tn, hipStream_t st) {
   dim3 grid(nyc, (S + 2 * Q - 1) / (2 * Q));
-  k_fft_rows_c2r_fista<N, Q><<<grid, Q * Split<N>::N1, 0, st>>>(T, z, x, nyc, nxc, S, rs, scale, sub,
-                                                               per_obj, p, nonfinite);
+  if (Tn)
+    k_fft_rows_c2r_fista<N, Q, true><<<grid, Q * Split<N>::N1, 0, st>>>(T, z, x, nyc, nxc, S, rs, scale, sub,
+                                                                       per_obj, p, nonfinite, Tn);
+  else
+    k_fft_rows_c2r_fista<N, Q, false><<<grid, Q * Split<N>::N1, 0, st>>>(T, z, x, nyc, nxc, S, rs, scale, sub,
+                                                                        per_obj, p, nonfinite, nullptr);
 }
 
 // 8 packed sequences (16 real slices) per row block: small enough for several
@@ -980,6 +1026,17 @@ pat_status fft2_c2r(const float2* X, float2* T, float* f, int fx, int fy, int nx
 }
 
 
+pat_status fft2_r2c_cols(const float2* T, float2* X, int fx, int fy, int nyw, int S, const int32_t* rowmap,
+                         const FftChirp& ch, hipStream_t st) {
+  if (S <= 0) return PAT_OK;
+  if (nyw < 1 || nyw > fy || (ch.my && nyw != fy))
+    return fail(PAT_EINVAL, "fft: data extent does not fit the transform");
+  const int nh = fx / 2 + 1;
+  const int rs = spec_stride(S);
+  if (ch.my) return cols_cz<-1>(T, X, fy, nh, S, rs, nullptr, rowmap, ch.cy, ch.by, ch.my, st);
+  return cols<-1>(T, X, fy, nh, S, rs, nullptr, rowmap, nyw, 1, fy, 1, st);
+}
+
 bool fft2_c2r_fista_ok(int nxw, const FftChirp& ch, int S, int per_obj) {
   return !ch.mx && (nxw & 3) == 0 && per_obj >= 1 && (S == per_obj || per_obj % (2 * kRowQ) == 0);
 }
@@ -987,7 +1044,7 @@ bool fft2_c2r_fista_ok(int nxw, const FftChirp& ch, int S, int per_obj) {
 pat_status fft2_c2r_fista(const float2* X, float2* T, float* z, float* x, int fx, int fy, int nxw,
                           int nyw, int S, int per_obj, float scale, const float* sub,
                           const int32_t* rowmap, const FftChirp& ch, const FistaBatch& p,
-                          int32_t* nonfinite, hipStream_t st) {
+                          int32_t* nonfinite, float2* Tnext, hipStream_t st) {
   if (S <= 0) return PAT_OK;
   if (!extents_ok(fx, fy, nxw, nyw, 1, 1))
     return fail(PAT_EINVAL, "fft: data extent does not fit the transform");
@@ -1003,7 +1060,7 @@ pat_status fft2_c2r_fista(const float2* X, float2* T, float* z, float* x, int fx
     PAT_TRY(cols<+1>(X, T, fy, nh, S, rs, rowmap, nullptr, fy, 1, nyw, 1, st));
   switch (fx) {
 #define PAT_CASE(N) \
-    case N: PAT_ROWS(rows_c2r_fista, N, T, z, x, nyw, nxw, S, rs, scale, sub, per_obj, p, nonfinite, st); break;
+    case N: PAT_ROWS(rows_c2r_fista, N, T, z, x, nyw, nxw, S, rs, scale, sub, per_obj, p, nonfinite, Tnext, st); break;
     PAT_FFT_SIZES(PAT_CASE)
 #undef PAT_CASE
     default: return fail(PAT_EUNSUPPORTED, "transform size along x is not one of the FFT sizes");

@@ -503,10 +503,14 @@ static pat_status run_gram(pat_op* op, const float2* in, float2* out, const floa
 }
 
 // y = A x (- sub), B objects
+// (rows_done: the forward transform's first pass on x is already in w.T)
 static pat_status run_A(pat_op* op, const float* x, float* y, int B, const float* sub, const Work& w,
-                        hipStream_t st) {
+                        hipStream_t st, bool rows_done = false) {
   const pat_geometry& g = op->g;
-  PAT_TRY(fft2_r2c(x, w.T, w.Xs, op->fx, op->fy, g.nx, g.ny, 1, 1, B * g.nz, op->rowmap, op->chirp, st));
+  if (rows_done)
+    PAT_TRY(fft2_r2c_cols(w.T, w.Xs, op->fx, op->fy, g.ny, B * g.nz, op->rowmap, op->chirp, st));
+  else
+    PAT_TRY(fft2_r2c(x, w.T, w.Xs, op->fx, op->fy, g.nx, g.ny, 1, 1, B * g.nz, op->rowmap, op->chirp, st));
   PAT_TRY(run_contract(op, false, w.Xs, w.Ds, B, st));
   return fft2_c2r(w.Ds, w.T, y, op->fx, op->fy, g.nx, g.ny, op->sx, op->sy, B * g.nt, inv_area(op), sub,
                   op->rowmap, op->chirp, st);
@@ -524,8 +528,11 @@ static pat_status run_AT(pat_op* op, const float* y, float* x, int B, const Work
 // FISTA update with the gradient A^T r of B objects (r: data-shaped), the
 // update in the last pass of A^T's inverse transform when that pass allows
 // it (fft2_c2r_fista_ok), else A^T into the workspace and a separate update
+// (Tnext != null: also the next iteration's first forward pass on the new z,
+// see fft2_c2r_fista; only where fft2_c2r_fista_ok holds)
 static pat_status run_AT_update(pat_op* op, const float* r, float* x, float* z, int B,
-                                const FistaBatch& p, int32_t* nonfinite, const Work& w, hipStream_t st) {
+                                const FistaBatch& p, int32_t* nonfinite, const Work& w, hipStream_t st,
+                                float2* Tnext = nullptr) {
   const pat_geometry& g = op->g;
   if (!fft2_c2r_fista_ok(g.nx, op->chirp, B * g.nz, g.nz)) {
     PAT_TRY(run_AT(op, r, w.U, B, w, st));
@@ -534,7 +541,7 @@ static pat_status run_AT_update(pat_op* op, const float* r, float* x, float* z, 
   PAT_TRY(fft2_r2c(r, w.T, w.Ds, op->fx, op->fy, g.nx, g.ny, op->sx, op->sy, B * g.nt, op->rowmap, op->chirp, st));
   PAT_TRY(run_contract(op, true, w.Ds, w.Xs, B, st));
   return fft2_c2r_fista(w.Xs, w.T, z, x, op->fx, op->fy, g.nx, g.ny, B * g.nz, g.nz, inv_area(op), nullptr,
-                        op->rowmap, op->chirp, p, nonfinite, st);
+                        op->rowmap, op->chirp, p, nonfinite, Tnext, st);
 }
 
 // FISTA update with the Gram-path gradient: the inverse transform of the
@@ -542,7 +549,8 @@ static pat_status run_AT_update(pat_op* op, const float* r, float* x, float* z, 
 // transform), the update fused into the transform's last pass when it
 // allows it
 static pat_status gram_update(pat_op* op, const float2* gs, const float* sub, float* x, float* z, int B,
-                              const FistaBatch& p, int32_t* nonfinite, const Work& w, hipStream_t st) {
+                              const FistaBatch& p, int32_t* nonfinite, const Work& w, hipStream_t st,
+                              float2* Tnext = nullptr) {
   const pat_geometry& g = op->g;
   if (!fft2_c2r_fista_ok(g.nx, op->chirp, B * g.nz, g.nz)) {
     PAT_TRY(fft2_c2r(gs, w.T, w.U, op->fx, op->fy, g.nx, g.ny, 1, 1, B * g.nz, inv_area(op), sub,
@@ -550,7 +558,7 @@ static pat_status gram_update(pat_op* op, const float2* gs, const float* sub, fl
     return fista_update(x, z, w.U, (long long)g.nz * g.nx * g.ny, B, p, nonfinite, st);
   }
   return fft2_c2r_fista(gs, w.T, z, x, op->fx, op->fy, g.nx, g.ny, B * g.nz, g.nz, inv_area(op), sub,
-                        op->rowmap, op->chirp, p, nonfinite, st);
+                        op->rowmap, op->chirp, p, nonfinite, Tnext, st);
 }
 
 }  // namespace pat
@@ -939,6 +947,8 @@ pat_status pat_recon_fista(pat_op* op, const float* d, float* x, int32_t niter, 
   double t = 1.0;
   FistaBatch p;
   std::memset(&p, 0, sizeof(p));
+  const bool chain = !trace && fft2_c2r_fista_ok(g.nx, op->chirp, g.nz, g.nz);
+  bool rows_done = false;  // w.T holds the first forward pass on z
   for (int k = 1; k <= niter; ++k) {
     double beta = 0.0;
     if (momentum) {
@@ -950,9 +960,15 @@ pat_status pat_recon_fista(pat_op* op, const float* d, float* x, int32_t niter, 
     p.o[0].thr = tau * lambda;
     p.o[0].beta = (float)beta;
     p.o[0].nonneg = nonneg ? 1 : 0;
+    // Without a trace, the update of every iteration but the last also runs
+    // the next iteration's first forward pass on the new z (into w.T)
+    float2* next = (chain && k < niter) ? w.T : nullptr;
     if (normal) {
       // gradient A^T (A z - d) = A^T A z - A^T d, per frequency: G z^ - b^
-      PAT_TRY(fft2_r2c(w.Z, w.T, w.Xs, op->fx, op->fy, g.nx, g.ny, 1, 1, g.nz, op->rowmap, op->chirp, st));
+      if (rows_done)
+        PAT_TRY(fft2_r2c_cols(w.T, w.Xs, op->fx, op->fy, g.ny, g.nz, op->rowmap, op->chirp, st));
+      else
+        PAT_TRY(fft2_r2c(w.Z, w.T, w.Xs, op->fx, op->fy, g.nx, g.ny, 1, 1, g.nz, op->rowmap, op->chirp, st));
       PAT_TRY(run_gram(op, w.Xs, w.Gs, w.Bs, 1, st));
       if (trace) {
         // the data term needs the gradient itself:
@@ -963,17 +979,18 @@ pat_status pat_recon_fista(pat_op* op, const float* d, float* x, int32_t niter, 
         PAT_TRY(trace_combine(trace + (k - 1), w.s64, st));
         PAT_TRY(fista_update(x, w.Z, w.U, n, 1, p, nullptr, st));
       } else {
-        PAT_TRY(gram_update(op, w.Gs, nullptr, x, w.Z, 1, p, nullptr, w, st));
+        PAT_TRY(gram_update(op, w.Gs, nullptr, x, w.Z, 1, p, nullptr, w, st, next));
       }
     } else {
       // explicit: residual r = A z - d (fused into the inverse transform), g = A^T r
-      PAT_TRY(run_A(op, w.Z, w.R, 1, d, w, st));
+      PAT_TRY(run_A(op, w.Z, w.R, 1, d, w, st, rows_done));
       if (trace) {
         PAT_TRY(dot_f64(w.R, w.R, nd, w.part64, w.s64 + 0, st));
         PAT_TRY(trace_combine(trace + (k - 1), w.s64, st));
       }
-      PAT_TRY(run_AT_update(op, w.R, x, w.Z, 1, p, nullptr, w, st));
+      PAT_TRY(run_AT_update(op, w.R, x, w.Z, 1, p, nullptr, w, st, next));
     }
+    rows_done = next != nullptr;
   }
   return PAT_OK;
 }

@@ -167,12 +167,18 @@ pat_status fista_update(float* x, float* z, const float* g, long long n_per_obj,
 // the inverse transform's output) are updated in its last pass without g
 // being stored.  Needs a fast x axis, nxw % 4 == 0 and per_obj a multiple
 // of 16 unless S == per_obj (EUNSUPPORTED otherwise; fft2_c2r_fista_ok says
-// beforehand).
+// beforehand).  Tnext != null: also the next iteration's forward row pass on
+// the new z (unsampled slices, as fft2_r2c's first pass writes it), in the
+// layout of T; Tnext may be T.
 bool fft2_c2r_fista_ok(int nxw, const FftChirp& ch, int S, int per_obj);
 pat_status fft2_c2r_fista(const float2* X, float2* T, float* z, float* x, int fx, int fy, int nxw,
                           int nyw, int S, int per_obj, float scale, const float* sub,
                           const int32_t* rowmap, const FftChirp& ch, const FistaBatch& p,
-                          int32_t* nonfinite, hipStream_t st);
+                          int32_t* nonfinite, float2* Tnext, hipStream_t st);
+// the second (column) pass of fft2_r2c alone, for unsampled slices whose
+// first pass is already in T (from fft2_c2r_fista with Tnext)
+pat_status fft2_r2c_cols(const float2* T, float2* X, int fx, int fy, int nyw, int S, const int32_t* rowmap,
+                         const FftChirp& ch, hipStream_t st);
 
 constexpr int kRedBlocks = 512;
 
