@@ -7,7 +7,9 @@ a batch), ragged and whole 16-byte chunks, and the
 three folds (radial, octant, quadrant); the batched normal step is checked
 against the oracle's A^T A z directly and FISTA through the Gram blocks
 against the oracle's FISTA.  Libraries whose gradient couples frequencies
-(linear boundary, scan-grid sampling) keep no Gram blocks.
+(linear boundary, scan-grid sampling) keep no Gram blocks.  FISTA without a
+trace (each update also running the next forward row pass) equals FISTA
+with one (each iteration transforming z afresh) to rounding.
 """
 import numpy as np
 import pytest
@@ -111,3 +113,21 @@ def test_coupled_gradients_keep_no_gram_blocks(kw):
     x = torch.zeros((1,) + op.x_shape, device="cuda")
     with pytest.raises(RuntimeError, match="Gram blocks"):
         op.fista_step_normal(torch.zeros_like(x), x, torch.zeros_like(x), [0.0], [1.0], [0.0], [False])
+
+
+@pytest.mark.parametrize("geo", [
+    Geometry(16, 16, 256, 40, 1e-4, 1e-4, 1e-4, 2e-8, 1500.0),                     # Gram path
+    Geometry.paper_like(32, 32, 16, 24, boundary="linear"),                        # explicit gradient
+    Geometry(16, 16, 24, 40, 1e-4, 1e-4, 1e-4, 2e-8, 1500.0),                      # 24 depths: not fused
+])
+def test_chained_iterations_equal_the_traced_ones(geo):
+    # without a trace every update also runs the next iteration's first
+    # forward pass; with one, each iteration transforms z afresh: the iterates
+    # agree to rounding
+    op = Operator(geo)
+    d = dev(inputs.gaussian_random(op.d_shape, seed=1330))
+    L, _ = op.power_norm(dev(inputs.gaussian_random(op.x_shape, seed=1331)), 20)
+    for k in (1, 2, 9):
+        xa = host(op.recon_fista(d, k, 0.9 / L, 1e-3, nonneg=True))
+        xb, _ = op.recon_fista(d, k, 0.9 / L, 1e-3, nonneg=True, trace=True)
+        assert rel(xa, host(xb)) < 2e-6, k
