@@ -1,6 +1,5 @@
 """Scheduler logic of the continuous-batching server (CPU, float64 fake device)."""
 import numpy as np
-import pytest
 
 from oracle import hlib, operators as ops, solvers
 from oracle.geometry import Geometry as OGeom
