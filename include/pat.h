@@ -234,7 +234,9 @@ pat_status pat_contract(pat_op* op, int32_t adjoint, const float* in, float* out
  * array L_trace[niter].  v0: device [nz][ny][nx], not modified.  A^T A is
  * block diagonal in the transverse frequency (Sec. 3.2), so the iteration
  * never leaves the frequencies v0 contains: start from a random vector (a
- * constant v0 yields the k = 0 block's norm only, an underestimate). */
+ * constant v0 yields the k = 0 block's norm only, an underestimate).  Where
+ * the library has Gram blocks (see pat_recon_fista) w is formed through
+ * them, else as A^T (A v). */
 pat_status pat_power_norm(pat_op* op, const float* v0, int32_t niter, double* L_out,
                           double* L_trace, void* ws, size_t ws_bytes, void* stream);
 

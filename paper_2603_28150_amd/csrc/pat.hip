@@ -896,8 +896,17 @@ pat_status pat_power_norm(pat_op* op, const float* v0, int32_t niter, double* L_
   PAT_TRY(dot_f32(v0, v0, n, w.part32, w.s32, 1.f, st));
   PAT_TRY(scale_rsqrt(w.V, v0, n, w.s32, st));
   for (int i = 0; i < niter; ++i) {
-    PAT_TRY(run_A(op, w.V, w.R, 1, nullptr, w, st));
-    PAT_TRY(run_AT(op, w.R, w.U, 1, w, st));
+    if (op->gram) {
+      // A^T A v per frequency through the Gram blocks: one forward transform,
+      // one nz x nz contraction, one inverse transform
+      PAT_TRY(fft2_r2c(w.V, w.T, w.Xs, op->fx, op->fy, g.nx, g.ny, 1, 1, g.nz, op->rowmap, op->chirp, st));
+      PAT_TRY(run_gram(op, w.Xs, w.Gs, nullptr, 1, st));
+      PAT_TRY(fft2_c2r(w.Gs, w.T, w.U, op->fx, op->fy, g.nx, g.ny, 1, 1, g.nz, inv_area(op), nullptr,
+                       op->rowmap, op->chirp, st));
+    } else {
+      PAT_TRY(run_A(op, w.V, w.R, 1, nullptr, w, st));
+      PAT_TRY(run_AT(op, w.R, w.U, 1, w, st));
+    }
     PAT_TRY(dot_f32(w.V, w.U, n, w.part32, Ls + i, 1.f, st));
     PAT_TRY(dot_f32(w.U, w.U, n, w.part32, w.s32 + 1, 1.f, st));
     PAT_TRY(scale_rsqrt(w.V, w.U, n, w.s32 + 1, st));

@@ -129,6 +129,16 @@ def test_linear_16bit_library(kind):
         assert rel(yb[b], ops.A_linear(Hq, xb[b])) < 2e-5
 
 
+def test_linear_power_iteration_matches_oracle():
+    # no Gram blocks here: every power step is A^T (A v) through both transforms
+    g, op, Hh2 = linear_setup("ragged")
+    v0 = inputs.gaussian_random((g.nz, g.ny, g.nx), seed=832)
+    L, trace = op.power_norm(dev(v0), 20)
+    Lo = solvers.power_iteration(lambda v: ops.A_linear(Hh2, v), lambda v: ops.AT_linear(Hh2, v), v0, 20)
+    assert np.max(np.abs(np.array(trace) - Lo) / np.array(Lo)) < 1e-5
+    assert L == trace[-1]
+
+
 def test_linear_fista_matches_oracle_and_rejects_normal_step():
     g, op, Hh2 = linear_setup("tiny")
     A = lambda v: ops.A_linear(Hh2, v)
