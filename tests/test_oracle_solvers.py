@@ -46,6 +46,108 @@ def test_momentum_weights_closed_form():
     assert solvers.momentum_weights(3, momentum=False) == [0.0, 0.0, 0.0]
 
 
+def test_momentum_weights_asymptotics():
+    # Beck-Teboulle's sequence makes FISTA the discretisation of
+    # x'' + (3/t) x' + grad f = 0 (Su, Boyd and Candes, 2016): 1 - beta_k
+    # behaves as 3/k, with a correction of order log(k)/k.  The
+    # alternatives beta_k = (t_k - 1)/t_k or (t_{k+1} - 1)/t_{k+1} tend to
+    # 2/k, a constant weight does not vanish.
+    b = solvers.momentum_weights(100000)
+    assert b[0] == 0.0 and all(0.0 <= v < 1.0 for v in b)
+    assert all(b[k + 1] > b[k] for k in range(len(b) - 1))
+    for k in (1000, 10000, 100000):
+        assert abs(k * (1.0 - b[k - 1]) - 3.0) < 20.0 / k ** 0.75
+
+
+def _worst_case_quadratic(n):
+    # Nesterov's hard instance for first-order methods: f(x) = 1/2 ||D x - e_0||^2
+    # with D the (n+1) x n first-difference matrix (D^T D tridiagonal 2, -1),
+    # minimiser x*_i = 1 - (i+1)/(n+1), ||D||^2 < 4
+    D = np.eye(n + 1, n) - np.eye(n + 1, n, k=-1)
+    d = np.zeros(n + 1)
+    d[0] = 1.0
+    xstar = 1.0 - np.arange(1, n + 1) / (n + 1.0)
+    return D, d, xstar
+
+
+def test_fista_rate_on_the_worst_case_quadratic():
+    # Beck-Teboulle: F(x_k) - F* <= 2 L ||x_0 - x*||^2 / (k+1)^2 at every k
+    # with tau = 1/L; on this instance the unaccelerated method breaks the
+    # bound within 400 iterations, so the momentum is what meets it
+    D, d, xstar = _worst_case_quadratic(1000)
+    A = lambda v: D @ v
+    AT = lambda v: D.T @ v
+    L = 4.0
+    Fstar = 0.5 / (D.shape[0])
+    assert abs(solvers.objective(A, d, xstar) - Fstar) < 1e-15
+    R2 = float(xstar @ xstar)
+    K = 400
+    bound = [2.0 * L * R2 / (k + 1) ** 2 for k in range(1, K + 1)]
+    acc = solvers.fista(A, AT, d, (D.shape[1],), K, 1.0 / L, 0.0, nonneg=False)
+    gap = [solvers.objective(A, d, x) - Fstar for x in acc]
+    assert all(gk <= bk for gk, bk in zip(gap, bound))
+    assert min(gap) >= -1e-15
+    plain = solvers.fista(A, AT, d, (D.shape[1],), K, 1.0 / L, 0.0, nonneg=False, momentum=False)
+    assert solvers.objective(A, d, plain[-1]) - Fstar > bound[-1]
+
+
+def _lbfgsb(fun_grad, n):
+    res = scipy.optimize.minimize(fun_grad, np.zeros(n), jac=True, method="L-BFGS-B",
+                                  bounds=[(0.0, None)] * n,
+                                  options=dict(maxiter=100000, ftol=1e-16, gtol=1e-14, maxcor=50))
+    return res.fun, res.x
+
+
+def test_fista_l1_nonneg_limit_against_lbfgsb(micro):
+    # lambda > 0 with non-negativity (eq. 14): on x >= 0 the objective
+    # 1/2 ||M x - d||^2 + lambda ||x||_1 is smooth (lambda sum x), so a
+    # bound-constrained quasi-Newton solve on the dense matrix gives F*;
+    # FISTA's iterates must reach it
+    g, Hh, A, AT, M = micro
+    x_true = np.abs(inputs.gaussian_blobs((g.nz, g.ny, g.nx), seed=7))
+    d = A(x_true) + 0.05 * inputs.noise_like((g.nt, g.ny, g.nx), seed=8)
+    db = d.ravel()
+    lam = 0.05 * np.abs(M.T @ db).max()
+
+    def fg(x):
+        r = M @ x - db
+        return 0.5 * r @ r + lam * x.sum(), M.T @ r + lam
+
+    Fstar, xs_ref = _lbfgsb(fg, M.shape[1])
+    L = solvers.norm_exact(Hh)
+    x = solvers.fista(A, AT, d, (g.nz, g.ny, g.nx), 5000, 1.0 / L, lam, nonneg=True)[-1]
+    F = solvers.objective(A, d, x, lam)
+    assert x.min() >= 0.0
+    assert abs(F - Fstar) <= 1e-9 * Fstar
+    # the l1 term is active: some entries are thresholded to zero that the
+    # lambda = 0 solution keeps
+    assert (xs_ref == 0).sum() > 0 and (x == 0).sum() > 0
+
+
+def test_fista_soft_threshold_limit_against_lbfgsb(micro):
+    # lambda > 0 without the constraint: prox = soft thresholding.  F* from
+    # L-BFGS-B on the split x = u - v, u, v >= 0, objective
+    # 1/2 ||M (u - v) - d||^2 + lambda sum (u + v)
+    g, Hh, A, AT, M = micro
+    x_true = inputs.gaussian_random((g.nz, g.ny, g.nx), seed=17)
+    d = A(x_true) + 0.05 * inputs.noise_like((g.nt, g.ny, g.nx), seed=18)
+    db = d.ravel()
+    n = M.shape[1]
+    lam = 0.05 * np.abs(M.T @ db).max()
+
+    def fg(uv):
+        r = M @ (uv[:n] - uv[n:]) - db
+        gr = M.T @ r
+        return 0.5 * r @ r + lam * uv.sum(), np.concatenate([gr + lam, -gr + lam])
+
+    Fstar, _ = _lbfgsb(fg, 2 * n)
+    L = solvers.norm_exact(Hh)
+    x = solvers.fista(A, AT, d, (g.nz, g.ny, g.nx), 5000, 1.0 / L, lam, nonneg=False)[-1]
+    assert (x < 0).sum() > 0 and (x > 0).sum() > 0 and (x == 0).sum() > 0
+    F = solvers.objective(A, d, x, lam)
+    assert abs(F - Fstar) <= 1e-9 * Fstar
+
+
 def test_first_iterate_closed_form(micro):
     # x_1 = prox(0 - tau * A^T(0 - d)) = max(tau A^T d - tau lambda, 0)
     g, Hh, A, AT, M = micro
