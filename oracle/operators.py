@@ -87,13 +87,35 @@ def AT_dft(Hf: np.ndarray, d: np.ndarray) -> np.ndarray:
 
 
 # --------------------------------------------------- pocketfft, half spectrum
+def contract_A(Hk: np.ndarray, Xk: np.ndarray) -> np.ndarray:
+    """Step (ii) of A (Sec. 3.2, eq. 16): D^[k, n] = sum_l H^[k, l, n] X^[k, l]
+    for every frequency k, as one (1 x nz) by (nz x nt) matrix product per
+    frequency.  Hk: real or complex [K, nz, nt]; Xk: complex [K, nz]."""
+    if np.iscomplexobj(Hk):
+        return np.matmul(Xk[:, None, :], Hk)[:, 0, :]
+    Xs = np.stack([Xk.real, Xk.imag], axis=1)             # [K, 2, nz]
+    Ds = np.matmul(Xs, Hk)                                 # [K, 2, nt]
+    return Ds[:, 0, :] + 1j * Ds[:, 1, :]
+
+
+def contract_AT(Hk: np.ndarray, Rk: np.ndarray) -> np.ndarray:
+    """Step (ii) of A^T (eq. 11): G^[k, l] = sum_n conj(H^[k, l, n]) R^[k, n],
+    one (nz x nt) by (nt x 1) product per frequency.  Hk: [K, nz, nt]; Rk:
+    complex [K, nt]."""
+    if np.iscomplexobj(Hk):
+        return np.matmul(np.conj(Hk), Rk[:, :, None])[:, :, 0]
+    Rs = np.stack([Rk.real, Rk.imag], axis=2)             # [K, nt, 2]
+    Gs = np.matmul(Hk, Rs)                                 # [K, nz, 2]
+    return Gs[:, :, 0] + 1j * Gs[:, :, 1]
+
+
 def A_fft(Hh: np.ndarray, x: np.ndarray) -> np.ndarray:
     """A with r2c/c2r FFTs.  Hh: H^ on the half spectrum [Ny, Nx/2+1, Nz, Nt]."""
     ny, nh, nz, nt = Hh.shape
     nx = x.shape[-1]
     X = np.fft.rfft2(x, axes=(1, 2))                       # [nz, ny, nh]
-    D = np.einsum("pmln,lpm->npm", Hh, X, optimize=True)    # [nt, ny, nh]
-    return np.fft.irfft2(D, s=(ny, nx), axes=(1, 2))
+    D = contract_A(Hh.reshape(ny * nh, nz, nt), X.reshape(nz, ny * nh).T)   # [K, nt]
+    return np.fft.irfft2(D.T.reshape(nt, ny, nh), s=(ny, nx), axes=(1, 2))
 
 
 def AT_fft(Hh: np.ndarray, d: np.ndarray) -> np.ndarray:
@@ -101,8 +123,8 @@ def AT_fft(Hh: np.ndarray, d: np.ndarray) -> np.ndarray:
     ny, nh, nz, nt = Hh.shape
     nx = d.shape[-1]
     R = np.fft.rfft2(d, axes=(1, 2))                       # [nt, ny, nh]
-    G = np.einsum("pmln,npm->lpm", np.conj(Hh), R, optimize=True)
-    return np.fft.irfft2(G, s=(ny, nx), axes=(1, 2))
+    G = contract_AT(Hh.reshape(ny * nh, nz, nt), R.reshape(nt, ny * nh).T)  # [K, nz]
+    return np.fft.irfft2(G.T.reshape(nz, ny, nh), s=(ny, nx), axes=(1, 2))
 
 
 # ------------------------------------ zero-padded linear convolution (Sec. 2.3)
@@ -199,10 +221,10 @@ def dft_at(f: np.ndarray, m_idx, p_idx) -> np.ndarray:
 def A_at_freqs(Hk: np.ndarray, x: np.ndarray, m_idx, p_idx) -> np.ndarray:
     """Spectrum of A x at the given frequencies: D^[k, n] = sum_l H^[k,l,n] X^[k,l]."""
     X = dft_at(x, m_idx, p_idx)                            # [K, nz]
-    return np.einsum("kln,kl->kn", Hk, X)
+    return contract_A(Hk, X)
 
 
 def AT_at_freqs(Hk: np.ndarray, d: np.ndarray, m_idx, p_idx) -> np.ndarray:
     """Spectrum of A^T d at the given frequencies: G^[k, l] = sum_n H^[k,l,n] R^[k,n]."""
     R = dft_at(d, m_idx, p_idx)                            # [K, nt]
-    return np.einsum("kln,kn->kl", np.conj(Hk), R)
+    return contract_AT(Hk, R)
