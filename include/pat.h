@@ -189,6 +189,19 @@ pat_status pat_workspace_bytes(const pat_op* op, int32_t B, size_t* bytes);
 pat_status pat_apply_A(pat_op* op, const float* x, float* y, int32_t B,
                        void* ws, size_t ws_bytes, void* stream);
 
+/* y = A x exactly as pat_apply_A (same kernels, same results), for callers
+ * that cannot allocate device memory or pass a workspace: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation.  The
+ * spectra live in a static scratch array of 128 MiB that the library holds on
+ * every GPU it runs on until the process ends; nothing is allocated per call.
+ * EUNSUPPORTED when the B objects' spectra do not fit (pat_apply_A's
+ * workspace minus its FISTA buffers: e.g. B = 1 up to 128 x 128 x 96 x 384,
+ * B = 4 at 64 x 64 x 64 x 256); EINVAL as pat_apply_A.  All calls on one GPU
+ * share its scratch: calls that overlap in time on that GPU (several
+ * streams, several host threads) race and must be serialised by the caller;
+ * calls in sequence on one stream are safe. */
+pat_status pat_apply_A_noalloc(pat_op* op, const float* x, float* y, int32_t B, void* stream);
+
 /* x = A^T y for B data sets (eq. 11): y [B][nt][ny/sy][nx/sx] -> x [B][nz][ny][nx]. */
 pat_status pat_apply_AT(pat_op* op, const float* y, float* x, int32_t B,
                         void* ws, size_t ws_bytes, void* stream);

@@ -62,6 +62,7 @@ SIGNATURES = {
     "pat_spectrum_stride": [_i32, C.POINTER(_i32)],
     "pat_apply_A": [_vp, _vp, _vp, _i32, _vp, _sz, _vp],
     "pat_apply_AT": [_vp, _vp, _vp, _i32, _vp, _sz, _vp],
+    "pat_apply_A_noalloc": [_vp, _vp, _vp, _i32, _vp],
     "pat_power_norm": [_vp, _vp, _i32, C.POINTER(_f64), C.POINTER(_f64), _vp, _sz, _vp],
     "pat_recon_fista": [_vp, _vp, _vp, _i32, _f32, _f32, _i32, _i32, _vp, _vp, _sz, _vp],
     "pat_fista_step": [_vp, _i32, _vp, _vp, _vp, C.POINTER(_f64), C.POINTER(_f32),

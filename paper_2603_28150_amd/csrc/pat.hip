@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -12,6 +13,7 @@
 
 struct pat_ctx {
   int device;
+  void* scratch;  // this device's address of the static scratch (pat_apply_A_noalloc)
 };
 
 struct pat_op {
@@ -49,6 +51,31 @@ struct pat_op {
 };
 
 namespace pat {
+
+// Scratch of pat_apply_A_noalloc: a file-scope device array, so that the
+// entry point needs no allocation.  Each GPU the library runs on holds its
+// own copy (at its own address) until the process ends.  Host code must not
+// use the symbol itself as a device address: pat_ctx_create looks the
+// address up once per device (hipGetSymbolAddress, that device current) and
+// every use goes through the pointer kept in the context.
+constexpr size_t kNoAllocBytes = size_t(128) << 20;
+static __device__ __align__(256) unsigned char g_scratch[kNoAllocBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// address of g_scratch on `device` (which must be current)
+static pat_status scratch_address(int device, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    PAT_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(g_scratch)));
+    if (!p) return fail(PAT_EHIP, "hipGetSymbolAddress returned a null scratch address");
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return PAT_OK;
+}
 
 static thread_local std::string g_last_error;
 
@@ -374,6 +401,26 @@ static Work work_layout(const pat_op* op, int B, char* base) {
   return w;
 }
 
+// The part of the workspace one apply of A uses (the spectra of B*nz and
+// B*nt slices and the transforms' intermediate), laid out as work_layout
+// lays it out; returns its bytes.  base == nullptr: sizes only.
+static size_t apply_layout(const pat_op* op, int B, char* base, Work* w) {
+  const pat_geometry& g = op->g;
+  const size_t rz = spec_stride(B * g.nz), rt = spec_stride(B * g.nt);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    char* p = base ? base + o : nullptr;
+    o = align_up(o + bytes, 256);
+    return p;
+  };
+  std::memset(w, 0, sizeof(*w));
+  w->Xs = (float2*)take((size_t)op->nrows * rz * 8);
+  w->Ds = (float2*)take((size_t)op->nrows * rt * 8);
+  w->T = (float2*)take((size_t)g.ny * op->nh * std::max(rz, rt) * 8);
+  w->total = o;
+  return o;
+}
+
 static bool misaligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) != 0; }
 
 static pat_status check_op_call(pat_op* op, int B, void* ws, size_t ws_bytes, Work* w) {
@@ -587,16 +634,19 @@ pat_status pat_ctx_create(int device, pat_ctx** out) {
   *out = nullptr;
   int n = 0;
   PAT_HIP(hipGetDeviceCount(&n));
-  if (device < 0 || device >= n) return fail(PAT_EINVAL, "no such HIP device");
+  if (device < 0 || device >= n || device >= kMaxDevices) return fail(PAT_EINVAL, "no such HIP device");
   hipDeviceProp_t prop;
   PAT_HIP(hipGetDeviceProperties(&prop, device));
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return fail(PAT_EUNSUPPORTED, std::string("device is ") + prop.gcnArchName + ", not gfx950");
   PAT_HIP(hipSetDevice(device));
   PAT_TRY(fft_init_device());
+  void* scratch = nullptr;
+  PAT_TRY(scratch_address(device, &scratch));
   pat_ctx* c = new (std::nothrow) pat_ctx;
   if (!c) return fail(PAT_ENOMEM, "host allocation failed");
   c->device = device;
+  c->scratch = scratch;
   *out = c;
   return PAT_OK;
 }
@@ -840,6 +890,25 @@ pat_status pat_apply_AT(pat_op* op, const float* y, float* x, int32_t B, void* w
   PAT_TRY(check_ptr(x, "x"));
   PAT_TRY(check_ptr(y, "y"));
   return run_AT(op, y, x, B, w, (hipStream_t)stream);
+}
+
+pat_status pat_apply_A_noalloc(pat_op* op, const float* x, float* y, int32_t B, void* stream) {
+  if (!op) return fail(PAT_EINVAL, "operator is null");
+  if (B < 1) return fail(PAT_EINVAL, "batch B must be >= 1");
+  PAT_TRY(check_ptr(x, "x"));
+  PAT_TRY(check_ptr(y, "y"));
+  Work w;
+  const size_t need = apply_layout(op, B, nullptr, &w);
+  if (need > kNoAllocBytes)
+    return fail(PAT_EUNSUPPORTED, "this apply needs " + std::to_string(need) +
+                                      " bytes of scratch, more than the " + std::to_string(kNoAllocBytes) +
+                                      " of the static scratch: use pat_apply_A with a workspace");
+  if (!op->ctx->scratch) return fail(PAT_EHIP, "the context has no scratch address");
+  PAT_HIP(hipSetDevice(op->ctx->device));
+  // nothing in the scratch needs to start at zero: every spectrum row and
+  // intermediate element an apply reads was written earlier in the same apply
+  apply_layout(op, B, static_cast<char*>(op->ctx->scratch), &w);
+  return run_A(op, x, y, B, nullptr, w, (hipStream_t)stream);
 }
 
 // workspace rows of T (complex) available for S slices

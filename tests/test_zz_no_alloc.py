@@ -1,0 +1,46 @@
+"""pat_apply_A_noalloc (A with the library's static scratch, no allocation)
+against pat_apply_A, through the C ABI: two calls in a row, the second on a
+smaller input, then a batch too large for the scratch."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2603_28150_amd import _lib, inputs
+from paper_2603_28150_amd.op import Geometry, Operator
+
+pytestmark = pytest.mark.gpu
+
+
+def _noalloc(op, x, y, B):
+    return _lib.load().pat_apply_A_noalloc(op.handle, x.data_ptr(), y.data_ptr(), B,
+                                           torch.cuda.current_stream().cuda_stream)
+
+
+def _rel(a, b):
+    return float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+
+
+def test_noalloc_apply_equals_apply_A():
+    big = Operator(Geometry.paper_like(64, 64, 40, 130))       # several tiles, ragged rows
+    small = Operator(Geometry.paper_like(32, 32, 16, 64))
+    for op, B, seed in ((big, 2, 31), (small, 1, 32)):          # second call: smaller input
+        x = torch.from_numpy(np.stack([inputs.gaussian_random(op.x_shape, seed=seed + b)
+                                       for b in range(B)]).astype(np.float32)).cuda()
+        y = torch.full((B,) + op.d_shape, float("nan"), device="cuda")
+        assert _noalloc(op, x, y, B) == 0, _lib.load().pat_last_error()
+        ref = op.apply_A(x)
+        torch.cuda.synchronize()
+        assert torch.isfinite(y).all()
+        assert _rel(y, ref) < 1e-5
+        assert torch.equal(y, ref)            # the same kernels on the same inputs
+    # a batch whose spectra exceed the static scratch is refused before any launch
+    B = 32
+    x = torch.zeros((B,) + big.x_shape, device="cuda")
+    y = torch.zeros((B,) + big.d_shape, device="cuda")
+    assert _noalloc(big, x, y, B) == -2
+    assert b"static scratch" in _lib.load().pat_last_error()
+    assert _noalloc(big, x, y, 0) == -1
+    assert _lib.load().pat_apply_A_noalloc(big.handle, ctypes.c_void_p(x.data_ptr() + 4), y.data_ptr(), 1,
+                                           None) == -1
