@@ -110,7 +110,19 @@ typedef struct {
    * before A^T), so data arrays are [nt][ny/sy][nx/sx].  sx must divide nx
    * with nx/sx a multiple of 4, sy must divide ny; 0 or 1: every point. */
   int32_t sx, sy;
+  /* How pat_H_build computes the library (pat_build; 0 = closed form). */
+  int32_t build;
 } pat_geometry;
+
+/* Library build.  CLOSED: the time factor cos(n c dt |k|) of every wavenumber
+ * evaluated directly.  STEP: one k-space time-stepping run from a unit point
+ * source, P^0 = 1, P^1 = cos(theta) P^0, P^{n+1} = 2 cos(theta) P^n - P^{n-1}
+ * (theta = c dt |k|, the exact propagator of eq. 1-2 with zero initial
+ * velocity, float64), the field recorded on every depth plane at every step;
+ * by reciprocity (the library discussion of Sec. 3.2) the plane at depth l is
+ * the sensor-plane response to a source at depth l.  Both store the same
+ * library up to float64 rounding; STEP needs build scratch (pat_H_bytes). */
+typedef enum { PAT_BUILD_CLOSED = 0, PAT_BUILD_STEP = 1 } pat_build;
 
 /* ---------------------------------------------------------------- context */
 
@@ -122,7 +134,11 @@ void pat_ctx_destroy(pat_ctx* ctx);
 /* ----------------------------------------------------------- kernel library */
 
 /* Bytes of device memory the kernel library of `geom` needs (h_bytes), and
- * of scratch for building it (scratch_bytes; may be 0).  Host only. */
+ * of scratch for building it (scratch_bytes: 0 for the closed form; for the
+ * stepped build, the recorded fields of a block of symmetry classes, at most
+ * 256 MiB plus one class; pat_H_build accepts any scratch that holds one
+ * class's record, nt x (nz_sim/2 + 1) float64 values, and steps that many
+ * classes per pass).  Host only. */
 pat_status pat_H_bytes(const pat_geometry* geom, size_t* h_bytes, size_t* scratch_bytes);
 
 /* Builds the kernel library of `geom` into the caller's device buffer h_buf
@@ -132,8 +148,8 @@ pat_status pat_H_bytes(const pat_geometry* geom, size_t* h_bytes, size_t* scratc
  * periodic grid in float64 on the GPU (cosine phases up to c*t*|k|, then the
  * depth sum) and stored in geom->h_dtype.  H^ is real and depends on
  * (kx, ky) only through kx^2 + ky^2, so it is stored once per symmetry class
- * of transverse frequencies (|kx|, |ky|), or (min, max) of them when nx = ny
- * and dx = dy; the layout inside h_buf is private.  h_buf must stay alive
+ * of transverse frequencies: (|kx|, |ky|), or every frequency with the same
+ * kx^2 + ky^2 when nx = ny and dx = dy; the layout inside h_buf is private.  h_buf must stay alive
  * and unmodified while the operator is in use; pat_op_destroy does not free
  * it.  Asynchronous: the operator may be used on `stream` at once, on other
  * streams after `stream` has been synchronised. */

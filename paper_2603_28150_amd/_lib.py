@@ -28,12 +28,13 @@ class Geometry(C.Structure):
                 ("dt", C.c_double), ("c", C.c_double),
                 ("nz_sim", C.c_int32), ("h_dtype", C.c_int32), ("boundary", C.c_int32),
                 ("n_ir", C.c_int32), ("ir", C.POINTER(C.c_double)),
-                ("sx", C.c_int32), ("sy", C.c_int32)]
+                ("sx", C.c_int32), ("sy", C.c_int32), ("build", C.c_int32)]
 
 
 H_F32, H_BF16, H_F16 = 0, 1, 2
 HDTYPES = {"f32": H_F32, "bf16": H_BF16, "f16": H_F16}
 BOUNDARIES = {"periodic": 0, "linear": 1}
+BUILDS = {"closed": 0, "step": 1}
 
 STATUS = {0: "PAT_OK", -1: "PAT_EINVAL", -2: "PAT_EUNSUPPORTED", -3: "PAT_ENOMEM",
           -4: "PAT_EHIP", -5: "PAT_ENONFINITE"}

@@ -274,31 +274,33 @@ __device__ __forceinline__ void contract_item(const ContractArgs& a, int lr_log2
   }
 }
 
-// Workgroups -> (item t, object b, row part).  Workgroups are dealt to the
-// eight XCDs round-robin by index, so for a batch the B objects of one item
-// get indices that are equal modulo 8 and close together: they run on the
-// same XCD at about the same time and share the slab through its L2 instead
-// of each streaming it from HBM.  One object: JS workgroups per item, each
-// streaming 1/JS of every slab row (shorter workgroups, a shorter tail).
+// Workgroups -> (item t, object b, row part).  One object: JS workgroups per
+// item, each streaming 1/JS of every slab row (shorter workgroups, a shorter
+// tail); a batch: one workgroup per item and object.  Workgroups are dealt to
+// the eight XCDs round-robin by index, so the units (item, part or object),
+// in item order, are cut into eight contiguous ranges, one per XCD, each
+// taken in order: the B objects of an item, and the items a large class is
+// split into (adjacent, reading the same slab), run on one XCD at about the
+// same time, and every read of a slab after the first comes from that XCD's
+// L2 instead of HBM.
 __device__ __forceinline__ bool item_of_block(int nitem, int B, int JS, int& t, int& b, int& part) {
-  if (B == 1) {
-    t = blockIdx.x / JS;
-    part = blockIdx.x - t * JS;
-    b = 0;
-    return true;
-  }
-  part = 0;
-  const int x = blockIdx.x & 7, r = blockIdx.x >> 3;
-  b = r % B;
-  t = (r / B) * 8 + x;
-  return t < nitem;
+  const int per_item = B == 1 ? JS : B;
+  const int units = nitem * per_item;
+  const int per_xcd = (units + 7) >> 3;
+  const int u = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (u >= units) return false;
+  t = u / per_item;
+  const int rem = u - t * per_item;
+  part = B == 1 ? rem : 0;
+  b = B == 1 ? 0 : rem;
+  return true;
 }
 
 template <typename HT, int G, int JPT>
 __global__ __launch_bounds__(256, (kLowRegs<HT, JPT> ? 4 : 1)) void k_contract(ContractArgs a, int lr_log2, int B, int JS, int chpart) {
   extern __shared__ float4 smem_raw[];
   int t, b, part;
-  if (!item_of_block(a.nitem, B, JS, t, b, part)) return;  // whole workgroup: padding of the last XCD round
+  if (!item_of_block(a.nitem, B, JS, t, b, part)) return;  // whole workgroup: padding of the grid
   constexpr int VEC = Slab<HT>::VEC;
   const int j0 = part * chpart * VEC;
   const int njl = min(a.nj - j0, chpart * VEC);
@@ -335,7 +337,7 @@ static pat_status launch_t(const ContractArgs& a, int B, hipStream_t st) {
   size_t lds = red_bytes > in_bytes ? red_bytes : in_bytes;
   lds = lds > out_bytes ? lds : out_bytes;
   if (lds > 160 * 1024) return fail(PAT_EUNSUPPORTED, "contraction input vector does not fit in LDS");
-  const long long nblk = B == 1 ? (long long)a.nitem * JS : (long long)(a.nitem + 7) / 8 * 8 * B;
+  const long long nblk = ((long long)a.nitem * (B == 1 ? JS : B) + 7) / 8 * 8;
   if (nblk > 0x7fffffffLL) return fail(PAT_EUNSUPPORTED, "contraction grid too large");
   dim3 grid((unsigned)nblk);
   if (jpt == 1)

@@ -25,10 +25,10 @@
 // terms, exact for float32 significands; with the hi + lo spectra that is
 // five MFMAs per step (the two smallest products dropped, 2^-26 relative).
 //
-// Workgroups: when a batch needs several column groups per work item, the
-// groups of one item get indices equal modulo 8 and close together, so they
-// run on the same XCD at about the same time and its L2 serves the slab to
-// all of them.
+// Workgroups: the (item, column group) units are dealt to the XCDs in eight
+// contiguous ranges, so the column groups of one item, and the items a large
+// class is split into, run on the same XCD at about the same time and its L2
+// serves the slab to all of them.
 #include "pat_internal.hpp"
 
 namespace pat {
@@ -98,9 +98,20 @@ __device__ __forceinline__ void split_f16(const Frag& in, Frag& hi, Frag& lo) {
   }
 }
 
+// LDS position, within its 64-unit fragment row, of the A-operand unit that
+// lane `idx` of k-step ks reads: the unit index XOR (2 ks + idx/32), a value
+// below 16, so the bit that selects the k half is kept and each 16-lane
+// quarter of a read still covers all 16 four-bank groups.  The staging loop
+// below writes, from 16 consecutive lanes, the units of one column for every
+// (k-step, k half); unswizzled those sit 512 bytes apart, all in one bank
+// group (a 16-way conflict); swizzled they fall in 16 different groups.
+__device__ __forceinline__ int a_unit(int ks, int idx) { return idx ^ ((2 * ks + (idx >> 5)) & 15); }
+
 // Stages the spectra of k-chunk ch (the A operand) into LDS, split hi + lo.
 // Work item = (pair, 8 consecutive k): 8 complex values in, four 16-byte
-// fragment units out (re and im columns, hi and lo terms).
+// fragment units out (re and im columns, hi and lo terms).  Consecutive lanes
+// take consecutive k-octets of one pair, so the global loads of 16 lanes are
+// one contiguous kilobyte of a spectrum row.
 template <int MT>
 __device__ __forceinline__ void stage_chunk(const MfmaArgs& a, u32x4* lds, int c, int p0, int gp,
                                             int ch, int tid) {
@@ -116,7 +127,7 @@ __device__ __forceinline__ void stage_chunk(const MfmaArgs& a, u32x4* lds, int c
       const int g = pair / a.B, b = pair % a.B;
       if (a.members[c * a.G + g] >= 0) {
         const float2* src = a.in + (size_t)(c * a.G + g) * a.in_rs + (size_t)b * a.K;
-const int kb = k0 + ko * 8;
+        const int kb = k0 + ko * 8;
         if (kb + 8 <= a.K) {  // 64 aligned bytes
           const float4* s4 = reinterpret_cast<const float4*>(src + kb);
 #pragma unroll
@@ -157,7 +168,7 @@ const int kb = k0 + ko * 8;
         hi.u[j] = h;
         lo.u[j] = l;
       }
-      const int unit = (ks * MT + mt) * 64 + r + 32 * half;
+      const int unit = (ks * MT + mt) * 64 + a_unit(ks, r + 32 * half);
       lds[unit] = hi.u;
       lds[kKC * MT * 64 + unit] = lo.u;
     }
@@ -172,10 +183,16 @@ __global__ __launch_bounds__(kWaves * 64, 3) void k_contract_mfma(MfmaArgs a, in
   const int lane = tid & 63, w = tid >> 6;
   int c, cg;  // work item, column group
   {
-    const int x = blockIdx.x & 7, r = blockIdx.x >> 3;
-    cg = r % groups;
-    c = (r / groups) * 8 + x;
-    if (c >= a.nitem) return;  // whole workgroup: padding of the last XCD round
+    // units (item, column group) in item order, cut into eight contiguous
+    // ranges, one per XCD (workgroups go to the XCDs round-robin by index):
+    // the groups of an item and the items a large class is split into run
+    // on one XCD together and share the slab through its L2
+    const int units = a.nitem * groups;
+    const int per_xcd = (units + 7) >> 3;
+    const int u = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    if (u >= units) return;  // whole workgroup: padding of the grid
+    c = u / groups;
+    cg = u - c * groups;
   }
   const int npairs = a.G * a.B;
   const int p0 = cg * (kMT * 16);
@@ -254,8 +271,8 @@ __global__ __launch_bounds__(kWaves * 64, 3) void k_contract_mfma(MfmaArgs a, in
 #pragma unroll
               for (int m = 0; m < MT; ++m) {
                 Frag ah, al;
-                ah.u = lds[(ks * MT + m) * 64 + lane];
-                al.u = lds[(kKC * MT + ks * MT + m) * 64 + lane];
+                ah.u = lds[(ks * MT + m) * 64 + a_unit(ks, lane)];
+                al.u = lds[(kKC * MT + ks * MT + m) * 64 + a_unit(ks, lane)];
                 acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah.b, fr[s].b, acc[m], 0, 0, 0);
                 acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al.b, fr[s].b, acc[m], 0, 0, 0);
               }
@@ -265,8 +282,8 @@ __global__ __launch_bounds__(kWaves * 64, 3) void k_contract_mfma(MfmaArgs a, in
 #pragma unroll
               for (int m = 0; m < MT; ++m) {
                 Frag ah, al;
-                ah.u = lds[(ks * MT + m) * 64 + lane];
-                al.u = lds[(kKC * MT + ks * MT + m) * 64 + lane];
+                ah.u = lds[(ks * MT + m) * 64 + a_unit(ks, lane)];
+                al.u = lds[(kKC * MT + ks * MT + m) * 64 + a_unit(ks, lane)];
                 acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah.b, hh.b, acc[m], 0, 0, 0);
                 acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al.b, hh.b, acc[m], 0, 0, 0);
                 acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah.b, hl.b, acc[m], 0, 0, 0);
@@ -278,8 +295,8 @@ __global__ __launch_bounds__(kWaves * 64, 3) void k_contract_mfma(MfmaArgs a, in
 #pragma unroll
               for (int m = 0; m < MT; ++m) {
                 Frag ah, al;
-                ah.u = lds[(ks * MT + m) * 64 + lane];
-                al.u = lds[(kKC * MT + ks * MT + m) * 64 + lane];
+                ah.u = lds[(ks * MT + m) * 64 + a_unit(ks, lane)];
+                al.u = lds[(kKC * MT + ks * MT + m) * 64 + a_unit(ks, lane)];
                 acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah.b, b1.b, acc[m], 0, 0, 0);
                 acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah.b, b2.b, acc[m], 0, 0, 0);
                 acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al.b, b1.b, acc[m], 0, 0, 0);
@@ -340,7 +357,7 @@ static void launch_mt(const MfmaArgs& a, int src, int groups, hipStream_t st) {
   const size_t lds = (size_t)kTerms * kKC * MT * 64 * 16;
   const size_t red = (size_t)kWaves * 16 * 64 * 4;  // k-part reduction buffer
   const size_t bytes = lds > red ? lds : red;
-  dim3 grid((unsigned)((a.nitem + 7) / 8 * 8 * groups));
+  dim3 grid((unsigned)(((long long)a.nitem * groups + 7) / 8 * 8));
   if (src == kSrcF16)
     k_contract_mfma<kSrcF16, MT><<<grid, kWaves * 64, bytes, st>>>(a, groups);
   else if (src == kSrcF32)
@@ -356,7 +373,7 @@ pat_status contract_mfma(const MfmaArgs& a, int hdtype, hipStream_t st) {
   if (src != kSrcF32 && !a.frag) return fail(PAT_EINVAL, "16-bit contraction needs the operand tiles");
   const int npairs = a.G * a.B;
   const int groups = (npairs + kMT * 16 - 1) / (kMT * 16);
-  if ((long long)(a.nitem + 7) / 8 * 8 * groups > 0x7fffffffLL) return fail(PAT_EUNSUPPORTED, "contraction grid too large");
+  if (((long long)a.nitem * groups + 7) / 8 * 8 > 0x7fffffffLL) return fail(PAT_EUNSUPPORTED, "contraction grid too large");
   const int cols = 2 * (groups > 1 ? kMT * 16 : npairs);  // columns of the widest group
   if (cols <= 32)
     launch_mt<1>(a, src, groups, st);

@@ -15,6 +15,17 @@
 // whole build runs in float64 and rounds once (to float32, then to 16 bits
 // for the reduced-precision forms).  A sensor response r (causal FIR) is
 // folded in along t: H^'[l, n] = sum_j r_j H^[l, n - j].
+//
+// Two ways to obtain the time factor: evaluated directly (closed form), or
+// by one k-space time-stepping run from a unit point source at the origin,
+// P^0 = 1, P^1 = cos(theta) P^0, P^{n+1} = 2 cos(theta) P^n - P^{n-1} (the
+// exact propagator with zero initial velocity, float64), whose field on depth
+// plane l at step n is the inverse z-DFT sum above: by reciprocity the field
+// at depth l due to a source on the sensor plane is the sensor-plane
+// response to a source at depth l (the single-simulation library of
+// Sec. 3.2).  The stepper records the field of a block of classes in build
+// scratch; the depth sum then reads the record instead of the cosines.
+#include <algorithm>
 #include <cmath>
 
 #include "pat_internal.hpp"
@@ -58,7 +69,34 @@ __device__ __forceinline__ unsigned short to_f16(float f) {
 // cos(n theta_q), so the filter acts on that factor: each q-chunk also
 // evaluates it at the n_ir - 1 earlier samples (zero before t = 0) and
 // filters in LDS before the depth sum.
-template <int MODE, bool FIR>
+// Stepped time factor of class a.c0 + blockIdx.y for the wavenumbers
+// q = 0 .. nq/2 (one thread each): P^n(q) for n < nt, weighted by w_q / nq,
+// into ptab[(blockIdx.y * nt + n) * (nq/2 + 1) + q].
+__global__ __launch_bounds__(256) void k_hstep(HBuildArgs a) {
+  const int Qn = a.nq / 2 + 1;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= Qn) return;
+  const int c = a.c0 + blockIdx.y;
+  const double two_pi = 6.283185307179586476925286766559;
+  const double kx = two_pi * a.cls_freq[2 * c] / (a.nx * a.dx);
+  const double ky = two_pi * a.cls_freq[2 * c + 1] / (a.ny * a.dy);
+  const double kz = two_pi * q / (a.nq * a.dz);
+  const double theta = a.c * a.dt * sqrt(kx * kx + ky * ky + kz * kz);
+  const double two_cos = 2.0 * cos(theta);
+  const double w = ((q == 0 || 2 * q == a.nq) ? 1.0 : 2.0) / a.nq;
+  double* rec = a.ptab + (size_t)blockIdx.y * a.nt * Qn + q;
+  double prev = 1.0;             // P^0: unit point source (flat spectrum)
+  double cur = 0.5 * two_cos;    // P^1 = cos(theta) P^0: zero initial velocity
+  rec[0] = w * prev;
+  for (int n = 1; n < a.nt; ++n) {
+    rec[(size_t)n * Qn] = w * cur;
+    const double next = fma(two_cos, cur, -prev);
+    prev = cur;
+    cur = next;
+  }
+}
+
+template <int MODE, bool FIR, bool STEP>
 __global__ __launch_bounds__(256) void k_hbuild(HBuildArgs a) {
   __shared__ double ctab[kMaxNq];
   __shared__ double P[kQB * kNT];
@@ -67,8 +105,9 @@ __global__ __launch_bounds__(256) void k_hbuild(HBuildArgs a) {
   __shared__ double irs[FIR ? kMaxIr : 1];
   const int tid = threadIdx.x;
   const int nl = tid & (kNT - 1), lg = tid >> 6;
-  const int c = blockIdx.y;
+  const int c = a.c0 + blockIdx.y;
   const int n = blockIdx.x * kNT + nl;
+  const double* rec = STEP ? a.ptab + (size_t)blockIdx.y * a.nt * (a.nq / 2 + 1) : nullptr;
   const int nq = a.nq;
   const int Qn = nq / 2 + 1;
   const double two_pi = 6.283185307179586476925286766559;
@@ -101,10 +140,14 @@ __global__ __launch_bounds__(256) void k_hbuild(HBuildArgs a) {
           const int q = q0 + qq, ng = blockIdx.x * kNT + nn;
           double v = 0.0;
           if (q < Qn && ng < a.nt) {
-            const double kz = two_pi * q / (nq * a.dz);
-            const double theta = cdt * sqrt(kperp2 + kz * kz);
-            const double w = (q == 0 || 2 * q == nq) ? 1.0 : 2.0;
-            v = w * inv_nq * cos((double)ng * theta);
+            if constexpr (STEP) {
+              v = rec[(size_t)ng * Qn + q];
+            } else {
+              const double kz = two_pi * q / (nq * a.dz);
+              const double theta = cdt * sqrt(kperp2 + kz * kz);
+              const double w = (q == 0 || 2 * q == nq) ? 1.0 : 2.0;
+              v = w * inv_nq * cos((double)ng * theta);
+            }
           }
           P[e] = v;
         }
@@ -116,10 +159,14 @@ __global__ __launch_bounds__(256) void k_hbuild(HBuildArgs a) {
           const int q = q0 + qq, ng = nbase + nr;
           double v = 0.0;
           if (q < Qn && ng >= 0 && ng < a.nt) {
-            const double kz = two_pi * q / (nq * a.dz);
-            const double theta = cdt * sqrt(kperp2 + kz * kz);
-            const double w = (q == 0 || 2 * q == nq) ? 1.0 : 2.0;
-            v = w * inv_nq * cos((double)ng * theta);
+            if constexpr (STEP) {
+              v = rec[(size_t)ng * Qn + q];
+            } else {
+              const double kz = two_pi * q / (nq * a.dz);
+              const double theta = cdt * sqrt(kperp2 + kz * kz);
+              const double w = (q == 0 || 2 * q == nq) ? 1.0 : 2.0;
+              v = w * inv_nq * cos((double)ng * theta);
+            }
           }
           Praw[qq * W + nr] = v;
         }
@@ -221,23 +268,46 @@ __global__ void k_scales(const unsigned long long* amax, float* inv_scale, int n
   if (l < nz) inv_scale[l] = (float)(1.0 / depth_scale(amax, l, hdtype));
 }
 
+template <int MODE>
+static pat_status launch_depth_sum(const HBuildArgs& a, int ncls, hipStream_t st) {
+  dim3 grid((a.nt + kNT - 1) / kNT, ncls);
+  const bool fir = a.n_ir > 0, step = a.ptab != nullptr;
+  if (step && fir) k_hbuild<MODE, true, true><<<grid, 256, 0, st>>>(a);
+  else if (step) k_hbuild<MODE, false, true><<<grid, 256, 0, st>>>(a);
+  else if (fir) k_hbuild<MODE, true, false><<<grid, 256, 0, st>>>(a);
+  else k_hbuild<MODE, false, false><<<grid, 256, 0, st>>>(a);
+  PAT_LAUNCHED(MODE == 0 ? "H build (max pass)" : "H build");
+  return PAT_OK;
+}
+
+// one pass over all classes (MODE 0: per-depth maxima, 1: the slabs); the
+// stepped build records and sums one block of classes at a time
+template <int MODE>
+static pat_status build_pass(const HBuildArgs& a, hipStream_t st) {
+  if (!a.ptab) return launch_depth_sum<MODE>(a, a.nclass, st);
+  const size_t per = step_class_bytes(a.nt, a.nq);
+  const int block = (int)std::min<size_t>((size_t)a.nclass, a.ptab_bytes / per);
+  if (block < 1) return fail(PAT_EINVAL, "build scratch holds less than one class's record");
+  const int Qn = a.nq / 2 + 1;
+  for (int c0 = 0; c0 < a.nclass; c0 += block) {
+    HBuildArgs b = a;
+    b.c0 = c0;
+    const int ncls = std::min(block, a.nclass - c0);
+    k_hstep<<<dim3((Qn + 255) / 256, ncls), 256, 0, st>>>(b);
+    PAT_LAUNCHED("H build (k-space stepper)");
+    PAT_TRY(launch_depth_sum<MODE>(b, ncls, st));
+  }
+  return PAT_OK;
+}
+
 pat_status hbuild(const HBuildArgs& a, hipStream_t st) {
   if (a.nq > kMaxNq) return fail(PAT_EUNSUPPORTED, "nz_sim above 4096 is not supported");
-  dim3 grid((a.nt + kNT - 1) / kNT, a.nclass);
   if (a.n_ir < 0 || a.n_ir > kMaxIr || (a.n_ir > 0 && !a.ir))
     return fail(PAT_EINVAL, "sensor response: 0..64 taps");
-  const bool fir = a.n_ir > 0;
-  if (a.hdtype != PAT_H_F32) {
-    if (fir) k_hbuild<0, true><<<grid, 256, 0, st>>>(a);
-    else k_hbuild<0, false><<<grid, 256, 0, st>>>(a);
-    PAT_LAUNCHED("H build (max pass)");
-  }
+  if (a.hdtype != PAT_H_F32) PAT_TRY(build_pass<0>(a, st));
   k_scales<<<(a.nz + 127) / 128, 128, 0, st>>>(a.amax, a.inv_scale, a.nz, a.hdtype);
   PAT_LAUNCHED("H build (scales)");
-  if (fir) k_hbuild<1, true><<<grid, 256, 0, st>>>(a);
-  else k_hbuild<1, false><<<grid, 256, 0, st>>>(a);
-  PAT_LAUNCHED("H build");
-  return PAT_OK;
+  return build_pass<1>(a, st);
 }
 
 // ------------------------------------------------------------ export

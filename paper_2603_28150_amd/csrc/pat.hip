@@ -23,7 +23,7 @@ struct pat_op {
   int fx, fy;   // transform grid (2 nx x 2 ny for the linear boundary)
   int sx, sy;   // scan-grid sampling of the data (1: every grid point)
   int nh, nk;   // half-spectrum columns fx/2+1 and frequencies fy*nh
-  int G;        // member slots per work item (8: radial, 4: octant, 2: quadrant fold)
+  int G;        // member slots per work item (8: radial float32, 4: radial 16-bit, 2: quadrant fold)
   int nclass;   // stored slabs
   int nitem;    // contraction work items (each reads one slab)
   int vec;      // storage elements per 16-byte load
@@ -155,6 +155,15 @@ static int default_nq(const pat_geometry& g) {
   return nq;
 }
 
+// build scratch of the stepped library build: the record of as many classes
+// as fit in 256 MiB (at least one); none for the closed form
+static size_t step_scratch_bytes(const pat_geometry& g, int nclass) {
+  if (g.build != PAT_BUILD_STEP) return 0;
+  const size_t per = step_class_bytes(g.nt, g.nz_sim ? g.nz_sim : default_nq(g));
+  const size_t block = std::max<size_t>(1, std::min<size_t>((size_t)nclass, (size_t(256) << 20) / per));
+  return block * per;
+}
+
 // scan-grid sampling steps (0 in a zero-initialised geometry means 1)
 static int scan_sx(const pat_geometry& g) { return g.sx > 1 ? g.sx : 1; }
 static int scan_sy(const pat_geometry& g) { return g.sy > 1 ? g.sy : 1; }
@@ -200,6 +209,7 @@ static pat_status check_geometry(const pat_geometry* g) {
   if (g->nz > 2048 || g->nt > 2048) return fail(PAT_EUNSUPPORTED, "nz and nt must be <= 2048");
   if (g->n_ir < 0 || g->n_ir > kMaxIr) return fail(PAT_EUNSUPPORTED, "n_ir must be in [0, 64]");
   if (g->sx < 0 || g->sy < 0) return fail(PAT_EINVAL, "sx and sy must be >= 0");
+  if (g->build != PAT_BUILD_CLOSED && g->build != PAT_BUILD_STEP) return fail(PAT_EINVAL, "unknown build");
   if (g->nx % scan_sx(*g) || g->ny % scan_sy(*g))
     return fail(PAT_EUNSUPPORTED, "sx must divide nx and sy must divide ny");
   if (g->n_ir > 0) {
@@ -214,14 +224,15 @@ static pat_status check_geometry(const pat_geometry* g) {
 // H^ depends on (m, p) only through kx^2 + ky^2, so one stored slab serves a
 // whole symmetry class of half-spectrum frequencies:
 //   quadrant fold (any grid):          (|m~|, |p~|), <= 2 members
-//   octant fold (nx = ny, dx = dy):    sorted (|m~|, |p~|), <= 4 members
 //   radial fold (nx = ny, dx = dy):    all frequencies with equal m~^2 + p~^2
-// The radial fold is used for float32 libraries (fewest bytes to stream); the
-// 16-bit libraries keep the octant fold so that a batch of 16 objects stays
-// in two matrix-core column groups of 32 pairs.  A work item of the contraction is one slab
-// with up to G member frequencies (a radial class with more members than G
-// is split into several items that read the same slab); its members occupy
-// spectrum rows item*G .. item*G+G-1.
+// A work item of the contraction is one slab with up to G member
+// frequencies (a class with more members than G is split into several items
+// that read the same slab, adjacent in item order, so that the contraction
+// runs them on one XCD and the second read hits its L2); its members occupy
+// spectrum rows item*G .. item*G+G-1.  G = 8 for float32 libraries; 16-bit
+// libraries take G = 4 so that a batch of 16 objects (64 member-object
+// pairs) stays in two matrix-core column groups of 32 pairs, and the VALU
+// kernel (8 values per 16-byte load) keeps its accumulators in registers.
 struct Classes {
   int G = 2;
   std::vector<int32_t> freq;       // [nslab][2] representative |m~|, |p~|
@@ -237,7 +248,6 @@ static Classes make_classes(const pat_geometry& g) {
   Classes C;
   const int nh = g.nx / 2 + 1, hx = g.nx / 2, hy = g.ny / 2;
   const bool square = g.nx == g.ny && g.dx == g.dy;
-  const bool radial = square && g.h_dtype == PAT_H_F32;
   const int nk = g.ny * nh;
   // members of the half spectrum with |m~| = m, |p~| = pa
   auto members_of = [&](int m, int pa, std::vector<int32_t>& out) {
@@ -247,24 +257,21 @@ static Classes make_classes(const pat_geometry& g) {
   };
   std::vector<std::vector<int32_t>> groups;  // member list per slab
   if (square) {
-    std::vector<int> slot_of_r;
-    if (radial) slot_of_r.assign(2 * hx * hx + 1, -1);
+    std::vector<int> slot_of_r(2 * hx * hx + 1, -1);
     for (int a = 0; a <= hx; ++a)
       for (int b = a; b <= hx; ++b) {
-        int gi;
-        if (radial && slot_of_r[a * a + b * b] >= 0) {
-          gi = slot_of_r[a * a + b * b];
-        } else {
+        int gi = slot_of_r[a * a + b * b];
+        if (gi < 0) {
           gi = (int)groups.size();
           groups.emplace_back();
           C.freq.push_back(a);
           C.freq.push_back(b);
-          if (radial) slot_of_r[a * a + b * b] = gi;
+          slot_of_r[a * a + b * b] = gi;
         }
         members_of(a, b, groups[gi]);
         if (a != b) members_of(b, a, groups[gi]);
       }
-    C.G = radial ? 8 : 4;
+    C.G = g.h_dtype == PAT_H_F32 ? 8 : 4;
   } else {
     for (int m = 0; m <= hx; ++m)
       for (int pa = 0; pa <= hy; ++pa) {
@@ -659,14 +666,12 @@ pat_status pat_H_bytes(const pat_geometry* geom, size_t* h_bytes, size_t* scratc
   const pat_geometry tg = transform_geometry(*geom);
   Classes C = make_classes(tg);
   *h_bytes = h_layout(tg, C).total;
-  if (scratch_bytes) *scratch_bytes = 0;
+  if (scratch_bytes) *scratch_bytes = step_scratch_bytes(*geom, C.n());
   return PAT_OK;
 }
 
 pat_status pat_H_build(pat_ctx* ctx, const pat_geometry* geom, void* h_buf, size_t h_bytes,
                        void* scratch, size_t scratch_bytes, void* stream, pat_op** out) {
-  (void)scratch;
-  (void)scratch_bytes;
   if (!ctx || !out) return fail(PAT_EINVAL, "ctx or out is null");
   *out = nullptr;
   PAT_TRY(check_geometry(geom));
@@ -676,6 +681,13 @@ pat_status pat_H_build(pat_ctx* ctx, const pat_geometry* geom, void* h_buf, size
   HLayout L = h_layout(tg, C);
   if (h_bytes < L.total)
     return fail(PAT_EINVAL, "h_buf too small: need " + std::to_string(L.total) + " bytes");
+  if (geom->build == PAT_BUILD_STEP) {
+    PAT_TRY(check_ptr(scratch, "scratch"));
+    const int nq = geom->nz_sim ? geom->nz_sim : default_nq(*geom);
+    if (scratch_bytes < step_class_bytes(geom->nt, nq))
+      return fail(PAT_EINVAL, "scratch too small for the stepped build: need at least " +
+                                  std::to_string(step_class_bytes(geom->nt, nq)) + " bytes");
+  }
   for (int32_t kc : C.kclass)
     if (kc < 0) return fail(PAT_EINVAL, "internal: frequency without class");
   PAT_HIP(hipSetDevice(ctx->device));
@@ -802,6 +814,9 @@ pat_status pat_H_build(pat_ctx* ctx, const pat_geometry* geom, void* h_buf, size
   a.amax = op->amax;
   a.inv_scale = op->inv_scale;
   a.hdtype = geom->h_dtype;
+  a.ptab = geom->build == PAT_BUILD_STEP ? static_cast<double*>(scratch) : nullptr;
+  a.ptab_bytes = geom->build == PAT_BUILD_STEP ? scratch_bytes : 0;
+  a.c0 = 0;
   if ((s = hbuild(a, st)) != PAT_OK) return bail(s);
   GramArgs ga;
   ga.slabA = op->slabA;

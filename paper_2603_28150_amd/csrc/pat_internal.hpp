@@ -125,9 +125,17 @@ struct HBuildArgs {
   int hdtype;
   const double* ir;         // [n_ir] sensor response taps (device), or null
   int n_ir;                 // 0: ideal sensors
+  // stepped build: the recorded fields of classes c0 .. c0 + ncb - 1,
+  // ptab[(c - c0) * nt + n][q] (q < nq/2 + 1, weighted by w_q / nq); null:
+  // closed form
+  double* ptab;
+  size_t ptab_bytes;
+  int c0;
 };
 constexpr int kMaxIr = 64;  // longest sensor response folded into the library
 pat_status hbuild(const HBuildArgs& a, hipStream_t st);
+// bytes of the stepped build's record of one class
+inline size_t step_class_bytes(int nt, int nq) { return (size_t)nt * (nq / 2 + 1) * 8; }
 struct GramArgs {
   const void* slabA;        // stored library, [l][n] rows (FP32) or fragments (16-bit)
   const float* inv_scale;   // [nz]

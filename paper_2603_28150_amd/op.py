@@ -30,18 +30,20 @@ class Geometry:
     ir: tuple = ()                 # sensor response taps (causal FIR along t), () = ideal
     sx: int = 1                    # scan grid: data at every sx-th column ...
     sy: int = 1                    # ... and sy-th row of the sensor grid
+    build: str = "closed"          # library build: "closed" form or one k-space "step"ping run
 
     @staticmethod
     def paper_like(nx, ny, nz, nt, dx=100e-6, c=1500.0, cfl=0.3, nz_sim=0,
-                   boundary="periodic", ir=(), sx=1, sy=1) -> "Geometry":
+                   boundary="periodic", ir=(), sx=1, sy=1, build="closed") -> "Geometry":
         """dx = dy = dz, dt = cfl * dx / c (the physics of the synthetic workloads)."""
         return Geometry(nx, ny, nz, nt, dx, dx, dx, cfl * dx / c, c, nz_sim, boundary,
-                        tuple(float(v) for v in ir), sx, sy)
+                        tuple(float(v) for v in ir), sx, sy, build)
 
     def to_c(self, h_dtype: str) -> _lib.Geometry:
         g = _lib.Geometry(self.nx, self.ny, self.nz, self.nt, self.dx, self.dy, self.dz,
                           self.dt, self.c, self.nz_sim, _lib.HDTYPES[h_dtype],
-                          _lib.BOUNDARIES[self.boundary], len(self.ir), None, self.sx, self.sy)
+                          _lib.BOUNDARIES[self.boundary], len(self.ir), None, self.sx, self.sy,
+                          _lib.BUILDS[self.build])
         if self.ir:
             g.ir = (C.c_double * len(self.ir))(*self.ir)   # kept alive by the struct
         return g
@@ -106,10 +108,14 @@ class Operator:
         hb, sb = C.c_size_t(), C.c_size_t()
         _lib.call("pat_H_bytes", C.byref(g), C.byref(hb), C.byref(sb))
         self.h_buf = torch.empty(hb.value, dtype=torch.uint8, device=self.device)
-        self.scratch = torch.empty(max(sb.value, 16), dtype=torch.uint8, device=self.device)
+        # build scratch (the stepped build's record), released once the build
+        # is enqueued: the caching allocator hands it out again only to work
+        # ordered after the build on this stream
+        scratch = torch.empty(max(sb.value, 16), dtype=torch.uint8, device=self.device)
         h = C.c_void_p()
         _lib.call("pat_H_build", self.ctx.handle, C.byref(g), _ptr(self.h_buf), hb.value,
-                  _ptr(self.scratch), sb.value, _stream(self.device), C.byref(h))
+                  _ptr(scratch), sb.value, _stream(self.device), C.byref(h))
+        del scratch
         self.handle = h
         self._ws: dict[tuple[int, int], torch.Tensor] = {}
         # Gram blocks (periodic boundary, unsampled data): the normal-operator

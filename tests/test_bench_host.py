@@ -19,11 +19,15 @@ def test_more_than_one_gpu_exits_with_a_message():
     assert r.stdout == ""
 
 
-def test_contraction_bytes_counts_library_once_and_spectra_per_object():
-    info = {"read_bytes_A": 1_000_000, "read_bytes_AT": 2_000_000}
+def test_contraction_bytes_counts_each_class_slab_once_and_spectra_per_object():
+    # the method's bytes: every stored slab once (one per symmetry class),
+    # whatever the work items re-read, plus the spectra in and out
+    info = {"slab_bytes_A": 1_000_000, "slab_bytes_AT": 2_000_000,
+            "read_bytes_A": 1_100_000, "read_bytes_AT": 2_300_000}
     nk, nz, nt = 33024, 128, 512
     assert bench.contraction_bytes(info, nk, nz, nt, False) == 1_000_000 + nk * (nz + nt) * 8
     assert bench.contraction_bytes(info, nk, nz, nt, True, B=16) == 2_000_000 + 16 * nk * (nz + nt) * 8
+    assert bench.reread_bytes(info, False) == 100_000 and bench.reread_bytes(info, True) == 300_000
 
 
 def test_fista_bytes_at_the_big_size():
@@ -32,13 +36,19 @@ def test_fista_bytes_at_the_big_size():
     # bytes per voxel: x and z in and out of the update fused into the
     # inverse transform, which also runs the next forward row pass)
     nk, nz, nt, nxy = 256 * 129, 128, 512, 256 * 256
-    info = {"read_bytes_A": 0, "read_bytes_AT": 5924 * 512 * 128 * 4, "gram_bytes": 5924 * 128 * 128 * 4}
+    info = {"slab_bytes_A": 0, "slab_bytes_AT": 5924 * 512 * 128 * 4, "gram_bytes": 5924 * 128 * 128 * 4}
     one = bench.fista_gram_bytes(info, nk, nz, nt, nxy, 1)
     per = bench.fista_gram_bytes(info, nk, nz, nt, nxy, 2) - one
     assert per == 16 * nz * nxy + 72 * nz * nk + info["gram_bytes"]
     assert 0.82e9 < per < 0.83e9
     setup = one - per
     assert setup == 4 * nt * nxy + 24 * nt * nk + bench.contraction_bytes(info, nk, nz, nt, True) + 12 * nz * nxy
+    # the algorithmic floor of the same loop: A^T d once, then per iteration
+    # the Gram blocks, (A^T d)^ and the update's 16 bytes per voxel
+    a1 = bench.fista_algorithmic_bytes(info, nk, nz, nt, nxy, 1)
+    a2 = bench.fista_algorithmic_bytes(info, nk, nz, nt, nxy, 2)
+    assert a2 - a1 == info["gram_bytes"] + 8 * nz * nk + 16 * nz * nxy
+    assert a2 - a1 < per
 
 
 def test_profile_traffic_only_for_the_profiled_source(tmp_path, monkeypatch):

@@ -4,7 +4,7 @@ H^_k H^_k^T (one nz x nz float32 block per class) across depths and folds.
 Depths from a two-chunk row (nz = 5) to rows that the contraction splits
 over two workgroups (nz = 520) or gives two chunks per lane (nz = 1100, in
 a batch), ragged and whole 16-byte chunks, and the
-three folds (radial, octant, quadrant); the batched normal step is checked
+folds (radial with 8- and 4-member items, quadrant); the batched normal step is checked
 against the oracle's A^T A z directly and FISTA through the Gram blocks
 against the oracle's FISTA.  Libraries whose gradient couples frequencies
 (linear boundary, scan-grid sampling) keep no Gram blocks.  FISTA without a
@@ -26,7 +26,7 @@ pytestmark = pytest.mark.gpu
 CASES = {
     "r5":    (16, 16, 5, 24, "f32"),     # radial (8); 2 chunks, ragged
     "r24":   (16, 16, 24, 40, "f32"),    # radial; 6 chunks
-    "r61":   (16, 16, 61, 40, "bf16"),   # octant (4); 16 chunks, ragged
+    "r61":   (16, 16, 61, 40, "bf16"),   # radial, 4-member items (16-bit); 16 chunks, ragged
     "q30":   (24, 16, 30, 36, "f32"),    # quadrant (2), non-square
     "r256":  (16, 16, 256, 40, "f32"),   # radial; 64 chunks
     "r520":  (16, 16, 520, 16, "f32"),   # 130 chunks: one object's rows split over two workgroups

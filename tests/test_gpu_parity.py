@@ -16,7 +16,7 @@ from paper_2603_28150_amd.op import Geometry, Operator
 
 pytestmark = pytest.mark.gpu
 
-TINY = Geometry.paper_like(32, 32, 16, 64)                       # octant fold
+TINY = Geometry.paper_like(32, 32, 16, 64)                       # radial fold
 RAGGED = Geometry(32, 16, 13, 37, 1e-4, 1.3e-4, 1e-4, 2e-8, 1500.0)  # quadrant fold, ragged
 MID = Geometry.paper_like(64, 64, 40, 130)                       # several tiles per row
 GEOMS = {"tiny": TINY, "ragged": RAGGED, "mid": MID}
@@ -394,7 +394,7 @@ def test_float32_batched_path(name, B):
 @pytest.mark.parametrize("name,kind", [("ragged", "f32"), ("mid", "f32"), ("tiny", "bf16"), ("tiny", "f16")])
 def test_gram_fista_matches_oracle(name, kind):
     # FISTA through the per-frequency normal operator on every fold and
-    # precision: quadrant (ragged), radial (mid), octant (16-bit, against the
+    # precision: quadrant (ragged), radial (mid; tiny with 4-member items in 16 bits, against the
     # oracle applying the same quantised library)
     g = GEOMS[name]
     op = Operator(g, kind) if kind != "f32" else setup(name)[1]

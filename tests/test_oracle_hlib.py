@@ -106,3 +106,23 @@ def test_space_kernels_are_impulse_responses():
     e[0, 0] = 1.0
     assert np.abs(h[0, :, :, 0] - e).max() < 1e-14
     assert np.abs(h[1:, :, :, 0]).max() < 1e-14
+
+
+def test_library_by_reciprocity_from_one_point_source_run():
+    # one run of the independent k-space stepper from a unit point source on
+    # the sensor plane, recorded on every depth plane: by reciprocity (source
+    # and receiver depths exchanged in a homogeneous medium) the recorded
+    # planes, transformed over (x, y), are the whole library (the library
+    # construction discussed in Sec. 3.2)
+    from oracle import wave3d
+    g = paper_like(8, 12, 5, 24)
+    src = np.zeros((g.nz, g.ny, g.nx))
+    src[0, 0, 0] = 1.0
+    planes = wave3d.simulate(src, g.dx, g.dy, g.dz, g.dt, g.c, g.nt, g.nq, planes=range(g.nz))
+    Hrec = np.fft.fft2(planes, axes=(2, 3))                     # [n, l, p, m]
+    Hf = hlib.H_full(g)                                         # [p, m, l, n]
+    assert np.abs(Hrec.imag).max() < 1e-13
+    assert np.abs(np.transpose(Hrec.real, (2, 3, 1, 0)) - Hf).max() < 1e-13 * np.abs(Hf).max()
+    # the plane-0 record alone is the d'Alembert/t = 0 structure: the depth-0 kernel
+    d0 = wave3d.simulate(src, g.dx, g.dy, g.dz, g.dt, g.c, g.nt, g.nq)
+    assert np.array_equal(d0, planes[:, 0])
