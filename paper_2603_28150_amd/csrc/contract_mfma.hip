@@ -239,8 +239,11 @@ __global__ __launch_bounds__(kWaves * 64, 3) void k_contract_mfma(MfmaArgs a, in
           const int ks = kpart + (s0 + s) * kparts;
           const bool ok = has && (s0 + s) * kparts < kKC && ks < nks;
           if constexpr (SRC != kSrcF32) {
+            // plain loads: the other column groups of the item (and the
+            // other items of a split class) read the same fragments next,
+            // from the XCD's L2
             if (ok)
-              fr[s].u = __builtin_nontemporal_load(slab + ((size_t)tile * a.ksteps + ch * kKC + ks) * 64 + lane);
+              fr[s].u = slab[((size_t)tile * a.ksteps + ch * kKC + ks) * 64 + lane];
             else
               fr[s].u = u32x4(0);
           } else {
