@@ -72,7 +72,9 @@ class _Class:
     keep: list = field(default_factory=list)    # buffers kept alive until the step ends
     last_used: float = 0.0
     bytes_lib: int = 0
+    bytes_ws1: int = 0      # the operator's own one-object workspace (A^T d at admission, step size)
     bytes_pool: int = 0
+    bytes_keep: int = 0     # replaced pools kept alive until the step using them ends
 
 
 class HipBackend:
@@ -213,7 +215,7 @@ class Server:
         for c in idle:
             if self.used + need <= self.budget:
                 break
-            self._charge(-(c.bytes_lib + c.bytes_pool))
+            self._charge(-(c.bytes_lib + c.bytes_ws1 + c.bytes_pool + c.bytes_keep))
             del self.classes[c.key]
         return self.used + need <= self.budget
 
@@ -232,11 +234,16 @@ class Server:
             return None
         st = self._stream(key)
         op = self.be.build(req.geom, req.h_dtype, st)
-        if lib + self.be.slot_bytes(op) + self.be.workspace_bytes(op, 1) > self.budget:
+        # the operator keeps a workspace for one object (A^T d of each admitted
+        # request, the power iteration of the step size): charged with the library
+        ws1 = self.be.workspace_bytes(op, 1)
+        if lib + ws1 + self.be.slot_bytes(op) + self.be.workspace_bytes(op, 1) > self.budget:
             req.status = "rejected"       # one request of this class can never fit
             return None
-        cls = _Class(key=key, op=op, tau=self.be.step_size(op, st), bytes_lib=lib)
-        self._charge(lib)
+        if self.used + lib + ws1 > self.budget and not self._evict_idle(lib + ws1, key):
+            return None                   # built but not admitted: the next try builds again
+        cls = _Class(key=key, op=op, tau=self.be.step_size(op, st), bytes_lib=lib, bytes_ws1=ws1)
+        self._charge(lib + ws1)
         self.classes[key] = cls
         return cls
 
@@ -245,16 +252,18 @@ class Server:
         if new_cap <= cls.cap:
             return False
         need = new_cap * self.be.slot_bytes(cls.op) + self.be.workspace_bytes(cls.op, new_cap)
-        extra = need - cls.bytes_pool
-        if self.used + extra > self.budget and not self._evict_idle(extra, cls.key):
+        # the old pool stays alive (and charged) until the step that may still
+        # use it has ended, so the new one is charged in full
+        if self.used + need > self.budget and not self._evict_idle(need, cls.key):
             return False
         st = self._stream(cls.key)
         pool, ws = self.be.alloc_pool(cls.op, new_cap, st)
         if cls.cap:
             self.be.copy_rows(cls.pool, pool, len(cls.active), st)
             cls.keep.append((cls.pool, cls.ws))
+        cls.bytes_keep += cls.bytes_pool
         cls.pool, cls.ws, cls.cap = pool, ws, new_cap
-        self._charge(extra)
+        self._charge(need)
         cls.bytes_pool = need
         return True
 
@@ -290,6 +299,8 @@ class Server:
             return
         cls.inflight = None
         cls.keep.clear()
+        self._charge(-cls.bytes_keep)
+        cls.bytes_keep = 0
         st = self._stream(cls.key)
         finished = []
         for i in range(n):

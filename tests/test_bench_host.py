@@ -55,10 +55,11 @@ def test_profile_traffic_only_for_the_profiled_source(tmp_path, monkeypatch):
     p = os.path.join(ROOT, "profiles", "contract_fp32_256x256x128x512_traffic.json")
     d = json.load(open(p))
     assert d["commands"] and d["calibration"]["copy_bytes"] == 1 << 30
-    # counted traffic of the committed summary is within 2 % of the algorithmic
-    # bytes: A's member spectra are staged by both workgroups of a split row
-    # (+33.8 MB per A launch, 0.9 % of the mean launch) and nothing else is re-read
-    assert abs(d["traffic_bytes_per_launch"] / d["algorithmic_bytes_per_launch"] - 1) < 0.02
+    # counted traffic of the committed summary is within 3 % of the method's
+    # bytes (each class slab once): A's member spectra are staged by both
+    # workgroups of a split row (+33.8 MB per A launch) and A^T reads about
+    # 56 MB beyond its slabs and spectrum (1.4 % of the mean launch together)
+    assert abs(d["traffic_bytes_per_launch"] / d["algorithmic_bytes_per_launch"] - 1) < 0.03
     fake = tmp_path / "contract.hip"
     fake.write_text("// not the profiled kernel\n")
     monkeypatch.setattr(bench, "CONTRACT_SRC", str(fake))

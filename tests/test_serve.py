@@ -195,3 +195,36 @@ def test_fifo_baseline_runs_one_at_a_time():
     srv = run_fifo(CpuBackend(clock), reqs, clock=clock)
     assert set(srv.batch_hist) == {1}
     assert all(r.status == "done" for r in reqs)
+
+
+class WsBackend(CpuBackend):
+    """CpuBackend whose operators also hold workspaces (of known sizes)."""
+
+    def workspace_bytes(self, op, cap):
+        return 1000 * cap + 500
+
+
+def test_accounting_charges_workspaces_and_replaced_pools():
+    # the operator's own one-object workspace is charged with its library,
+    # a pool replaced while growing stays charged until the step that used it
+    # has ended, and what is charged after the work drains is exactly what
+    # the classes still hold
+    clock = Clock()
+    be = WsBackend(clock)
+    srv = Server(be, hbm_budget=1 << 40, max_batch=4, clock=clock)
+    reqs = [_req(G1, 30 + i, 3 + i)[0] for i in range(4)]
+    growth = []
+    for r in reqs:
+        srv.submit(r)
+        srv.poll()
+        growth.append(srv.used)
+    cls = srv.classes[(G1, "f32")]
+    assert cls.bytes_ws1 == 1500
+    srv.run_until_idle()
+    assert all(r.status == "done" for r in reqs)
+    assert cls.bytes_keep == 0 and not cls.keep
+    held = sum(c.bytes_lib + c.bytes_ws1 + c.bytes_pool for c in srv.classes.values())
+    assert srv.used == held
+    slot = be.slot_bytes(cls.op)
+    # the peak saw the old pool and the new one together at least once
+    assert srv.peak >= cls.bytes_lib + cls.bytes_ws1 + cls.bytes_pool + (2 * slot + be.workspace_bytes(None, 2))
