@@ -113,3 +113,13 @@ def test_stepped_build_in_blocks_of_classes():
     Hc = host(Operator(g).export_H())
     assert np.abs(host(out) - Hc).max() <= 1e-7 * np.abs(Hc).max()
     assert L.pat_op_destroy(h) == 0
+
+
+@pytest.mark.parametrize("g", [Geometry.paper_like(24, 16, 6, 30, boundary="linear"),      # 48 x 32 periods
+                               Geometry.paper_like(34, 34, 8, 40)],                       # chirp-z axes
+                         ids=["linear", "chirpz"])
+def test_stepped_build_on_other_transform_grids(g):
+    # the stepped build is a property of the library alone: the same on the
+    # padded grid of the linear boundary and on chirp-z axes
+    Hs, Hc = host(Operator(stepped(g)).export_H()), host(Operator(g).export_H())
+    assert np.abs(Hs - Hc).max() <= 1e-7 * np.abs(Hc).max()

@@ -35,6 +35,17 @@ def test_noalloc_apply_equals_apply_A():
         assert torch.isfinite(y).all()
         assert _rel(y, ref) < 1e-5
         assert torch.equal(y, ref)            # the same kernels on the same inputs
+    # the padded grid of the linear boundary (window rows only in the
+    # intermediate) and chirp-z axes: the same as pat_apply_A
+    for g in (Geometry.paper_like(24, 16, 6, 30, boundary="linear"), Geometry.paper_like(34, 34, 8, 40)):
+        op = Operator(g)
+        x = torch.from_numpy(np.stack([inputs.gaussian_random(op.x_shape, seed=50 + b)
+                                       for b in range(2)]).astype(np.float32)).cuda()
+        y = torch.full((2,) + op.d_shape, float("nan"), device="cuda")
+        assert _noalloc(op, x, y, 2) == 0, _lib.load().pat_last_error()
+        ref = op.apply_A(x)
+        torch.cuda.synchronize()
+        assert torch.equal(y, ref)
     # a batch whose spectra exceed the static scratch is refused before any launch
     B = 32
     x = torch.zeros((B,) + big.x_shape, device="cuda")
