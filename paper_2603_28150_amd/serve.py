@@ -190,6 +190,7 @@ class Server:
         self.peak = 0
         self.batch_hist: dict[int, int] = {}
         self.streams: dict[tuple, object] = {}
+        self._ws1: dict[tuple, int] = {}   # one-object workspace of each class built so far
         self._rid = 0
 
     # ------------------------------------------------------------ submit
@@ -230,18 +231,20 @@ class Server:
         if lib > self.budget:
             req.status = "rejected"
             return None
-        if self.used + lib > self.budget and not self._evict_idle(lib, key):
+        # the operator keeps a workspace for one object (A^T d of each admitted
+        # request, the power iteration of the step size), charged with the
+        # library; its size is known once the class has been built
+        need = lib + self._ws1.get(key, 0)
+        if self.used + need > self.budget and not self._evict_idle(need, key):
             return None
         st = self._stream(key)
         op = self.be.build(req.geom, req.h_dtype, st)
-        # the operator keeps a workspace for one object (A^T d of each admitted
-        # request, the power iteration of the step size): charged with the library
-        ws1 = self.be.workspace_bytes(op, 1)
+        ws1 = self._ws1[key] = self.be.workspace_bytes(op, 1)
         if lib + ws1 + self.be.slot_bytes(op) + self.be.workspace_bytes(op, 1) > self.budget:
             req.status = "rejected"       # one request of this class can never fit
             return None
         if self.used + lib + ws1 > self.budget and not self._evict_idle(lib + ws1, key):
-            return None                   # built but not admitted: the next try builds again
+            return None                   # built but not admitted (first build only)
         cls = _Class(key=key, op=op, tau=self.be.step_size(op, st), bytes_lib=lib, bytes_ws1=ws1)
         self._charge(lib + ws1)
         self.classes[key] = cls

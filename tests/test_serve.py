@@ -228,3 +228,28 @@ def test_accounting_charges_workspaces_and_replaced_pools():
     slot = be.slot_bytes(cls.op)
     # the peak saw the old pool and the new one together at least once
     assert srv.peak >= cls.bytes_lib + cls.bytes_ws1 + cls.bytes_pool + (2 * slot + be.workspace_bytes(None, 2))
+
+
+def test_class_waiting_for_memory_is_not_rebuilt_every_tick():
+    # the budget fits G1's class and G2's library, but not G2's library with
+    # its workspace: G2 is built once, found not to fit, and then waits without
+    # being built again each tick until G1 goes idle and is evicted
+    clock = Clock()
+    be = WsBackend(clock)
+    lib1, lib2 = be.library_bytes(G1, "f32"), be.library_bytes(G2, "f32")
+    slot1 = 4 * 16 * 16 * (2 * 8 + 24)
+    held1 = lib1 + 1500 + slot1 + 1500               # library, own workspace, one slot + its workspace
+    budget = held1 + lib2 + 700                       # G2's library fits, with its 1,500-byte workspace not
+    srv = Server(be, hbm_budget=budget, max_batch=1, clock=clock)
+    r1, _ = _req(G1, 40, 12)
+    srv.submit(r1)
+    srv.poll()
+    r2, _ = _req(G2, 41, 3)
+    srv.submit(r2)
+    for _ in range(8):
+        srv.poll()
+    assert r2.status == "pending" and r1.status == "running"
+    assert be.built.count((G2, "f32")) == 1
+    srv.run_until_idle()
+    assert r1.status == "done" and r2.status == "done"
+    assert be.built.count((G2, "f32")) == 2 and srv.peak <= budget
