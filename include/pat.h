@@ -195,7 +195,9 @@ pat_status pat_spectrum_rows(const pat_op* op, int32_t* k_of_row);
  * HBM channels.  EINVAL for S outside [1, 2^30].  Host only. */
 pat_status pat_spectrum_stride(int32_t S, int32_t* stride);
 
-/* Workspace bytes every call below needs for a batch of B objects. */
+/* Workspace bytes every call below needs for a batch of B objects.  Here and
+ * in every call taking B: EINVAL unless 1 <= B and B * max(nz, nt) <= 2^30
+ * (slices per spectrum row). */
 pat_status pat_workspace_bytes(const pat_op* op, int32_t B, size_t* bytes);
 
 /* ------------------------------------------------------------- operators */

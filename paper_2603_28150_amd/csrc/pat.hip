@@ -430,9 +430,17 @@ static size_t apply_layout(const pat_op* op, int B, char* base, Work* w) {
 
 static bool misaligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) != 0; }
 
+// a batch of B objects: B >= 1 and at most 2^30 slices per spectrum row
+static pat_status check_batch(const pat_op* op, int B) {
+  if (B < 1) return fail(PAT_EINVAL, "batch B must be >= 1");
+  if ((long long)B * std::max(op->g.nz, op->g.nt) > (1LL << 30))
+    return fail(PAT_EINVAL, "batch too large: B * max(nz, nt) must be <= 2^30");
+  return PAT_OK;
+}
+
 static pat_status check_op_call(pat_op* op, int B, void* ws, size_t ws_bytes, Work* w) {
   if (!op) return fail(PAT_EINVAL, "operator is null");
-  if (B < 1) return fail(PAT_EINVAL, "batch B must be >= 1");
+  PAT_TRY(check_batch(op, B));
   if (!ws || misaligned(ws)) return fail(PAT_EINVAL, "workspace is null or not 16-byte aligned");
   *w = work_layout(op, B, (char*)ws);
   if (ws_bytes < w->total)
@@ -884,7 +892,7 @@ pat_status pat_spectrum_stride(int32_t S, int32_t* stride) {
 
 pat_status pat_workspace_bytes(const pat_op* op, int32_t B, size_t* bytes) {
   if (!op || !bytes) return fail(PAT_EINVAL, "null argument");
-  if (B < 1) return fail(PAT_EINVAL, "batch B must be >= 1");
+  PAT_TRY(check_batch(op, B));
   *bytes = work_layout(op, B, nullptr).total;
   return PAT_OK;
 }
@@ -909,7 +917,7 @@ pat_status pat_apply_AT(pat_op* op, const float* y, float* x, int32_t B, void* w
 
 pat_status pat_apply_A_noalloc(pat_op* op, const float* x, float* y, int32_t B, void* stream) {
   if (!op) return fail(PAT_EINVAL, "operator is null");
-  if (B < 1) return fail(PAT_EINVAL, "batch B must be >= 1");
+  PAT_TRY(check_batch(op, B));
   PAT_TRY(check_ptr(x, "x"));
   PAT_TRY(check_ptr(y, "y"));
   Work w;
@@ -929,7 +937,7 @@ pat_status pat_apply_A_noalloc(pat_op* op, const float* x, float* y, int32_t B, 
 // workspace rows of T (complex) available for S slices
 static pat_status check_stage(pat_op* op, int S, void* ws, size_t ws_bytes, Work* w) {
   if (!op) return fail(PAT_EINVAL, "operator is null");
-  if (S < 1) return fail(PAT_EINVAL, "S must be >= 1");
+  if (S < 1 || S > (1 << 30)) return fail(PAT_EINVAL, "S must be in [1, 2^30]");
   const int per = std::max(op->g.nz, op->g.nt);
   const int B = (S + per - 1) / per;
   return check_op_call(op, B, ws, ws_bytes, w);
@@ -959,7 +967,7 @@ pat_status pat_inverse_spectrum(pat_op* op, const float* spec, float* f, int32_t
 pat_status pat_contract(pat_op* op, int32_t adjoint, const float* in, float* out, int32_t B,
                         void* stream) {
   if (!op) return fail(PAT_EINVAL, "operator is null");
-  if (B < 1) return fail(PAT_EINVAL, "batch B must be >= 1");
+  PAT_TRY(check_batch(op, B));
   PAT_TRY(check_ptr(in, "in"));
   PAT_TRY(check_ptr(out, "out"));
   PAT_HIP(hipSetDevice(op->ctx->device));

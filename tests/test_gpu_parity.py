@@ -136,6 +136,12 @@ def test_invalid_arguments_raise():
     assert L.pat_apply_A(op.handle, x.data_ptr(), y.data_ptr(), 0, ws.data_ptr(), ws.numel(), None) == -1
     assert L.pat_apply_A(op.handle, x.data_ptr(), y.data_ptr(), 1, ws.data_ptr(), 16, None) == -1
     assert L.pat_apply_A(op.handle, x.data_ptr() + 4, y.data_ptr(), 1, ws.data_ptr(), ws.numel(), None) == -1
+    # batches whose spectrum rows would exceed 2^30 slices are refused on the host
+    import ctypes
+    n = ctypes.c_size_t()
+    assert L.pat_workspace_bytes(op.handle, 1 << 24, ctypes.byref(n)) == 0
+    assert L.pat_workspace_bytes(op.handle, 1 << 25, ctypes.byref(n)) == -1
+    assert L.pat_contract(op.handle, 0, x.data_ptr(), y.data_ptr(), 1 << 25, None) == -1
     with pytest.raises(_lib.PatError):
         Operator(Geometry(41, 32, 4, 4, 1e-4, 1e-4, 1e-4, 2e-8, 1500.0))
 
