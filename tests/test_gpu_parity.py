@@ -438,3 +438,27 @@ def test_normal_step_matches_explicit_step_and_oracle():
         xo = solvers.fista(A, AT, ds[b], (g.nz, g.ny, g.nx), 6, taus[b], lams[b], nonneg=nn[b])[-1]
         assert rel(host(xn[b]), xo) < 1e-5, b
         assert rel(host(xn[b]), host(xe[b])) < 1e-5, b
+
+
+@pytest.mark.parametrize("nz,nt", [(8, 2048), (2048, 8)], ids=["nt2048", "nz2048"])
+@pytest.mark.parametrize("kind", ["f32", "bf16"])
+def test_longest_depth_and_time_axes(nz, nt, kind):
+    # the longest axes the library accepts (2048 samples or depths; nz_sim
+    # 1024 and 4096 by the default rule), one object and a batch of two
+    g = Geometry.paper_like(16, 16, nz, nt)
+    op = Operator(g, kind)
+    Hh = hlib.H_half(og(g))
+    if kind != "f32":
+        Hh, _ = quant.quantise(Hh, kind)
+    bar = 1e-5 if kind == "f32" else 2e-5
+    xs = np.stack([inputs.gaussian_random((nz, 16, 16), seed=900 + b) for b in range(2)])
+    ds = np.stack([inputs.gaussian_random((nt, 16, 16), seed=910 + b) for b in range(2)])
+    y1 = host(op.apply_A(dev(xs[0])))
+    g1 = host(op.apply_AT(dev(ds[0])))
+    assert rel(y1, ops.A_fft(Hh, xs[0])) < bar
+    assert rel(g1, ops.AT_fft(Hh, ds[0])) < bar
+    y2 = host(op.apply_A(dev(xs)))
+    g2 = host(op.apply_AT(dev(ds)))
+    for b in range(2):
+        assert rel(y2[b], ops.A_fft(Hh, xs[b])) < bar, b
+        assert rel(g2[b], ops.AT_fft(Hh, ds[b])) < bar, b
