@@ -379,11 +379,15 @@ struct Work {
 };
 constexpr int kMaxPowerIter = 4096;
 
-static Work work_layout(const pat_op* op, int B, char* base) {
+// Workspace of a batch of B objects.  The spectra of B*nz and B*nt slices
+// and the transforms' intermediate come first: they are all one apply of A
+// uses (apply_only: the layout stops there, the other buffers are null).
+static Work work_layout(const pat_op* op, int B, char* base, bool apply_only = false) {
   const pat_geometry& g = op->g;
   const size_t nxy = (size_t)g.nx * g.ny;
   const size_t Sz = (size_t)B * g.nz, St = (size_t)B * g.nt;
   Work w;
+  std::memset(&w, 0, sizeof(w));
   size_t o = 0;
   auto take = [&](size_t bytes) {
     char* p = base ? base + o : nullptr;
@@ -394,6 +398,10 @@ static Work work_layout(const pat_op* op, int B, char* base) {
   w.Xs = (float2*)take((size_t)op->nrows * rz * 8);  // nrows = nitem * G
   w.Ds = (float2*)take((size_t)op->nrows * rt * 8);
   w.T = (float2*)take((size_t)g.ny * op->nh * std::max(rz, rt) * 8);
+  if (apply_only) {
+    w.total = o;
+    return w;
+  }
   w.Bs = (float2*)take((size_t)op->nrows * rz * 8);
   w.Gs = (float2*)take((size_t)op->nrows * rz * 8);
   w.V = (float*)take(Sz * nxy * 4);
@@ -406,26 +414,6 @@ static Work work_layout(const pat_op* op, int B, char* base) {
   w.s32 = (float*)take((8 + kMaxPowerIter) * 4);
   w.total = o;
   return w;
-}
-
-// The part of the workspace one apply of A uses (the spectra of B*nz and
-// B*nt slices and the transforms' intermediate), laid out as work_layout
-// lays it out; returns its bytes.  base == nullptr: sizes only.
-static size_t apply_layout(const pat_op* op, int B, char* base, Work* w) {
-  const pat_geometry& g = op->g;
-  const size_t rz = spec_stride(B * g.nz), rt = spec_stride(B * g.nt);
-  size_t o = 0;
-  auto take = [&](size_t bytes) {
-    char* p = base ? base + o : nullptr;
-    o = align_up(o + bytes, 256);
-    return p;
-  };
-  std::memset(w, 0, sizeof(*w));
-  w->Xs = (float2*)take((size_t)op->nrows * rz * 8);
-  w->Ds = (float2*)take((size_t)op->nrows * rt * 8);
-  w->T = (float2*)take((size_t)g.ny * op->nh * std::max(rz, rt) * 8);
-  w->total = o;
-  return o;
 }
 
 static bool misaligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) != 0; }
@@ -920,8 +908,7 @@ pat_status pat_apply_A_noalloc(pat_op* op, const float* x, float* y, int32_t B, 
   PAT_TRY(check_batch(op, B));
   PAT_TRY(check_ptr(x, "x"));
   PAT_TRY(check_ptr(y, "y"));
-  Work w;
-  const size_t need = apply_layout(op, B, nullptr, &w);
+  const size_t need = work_layout(op, B, nullptr, true).total;
   if (need > kNoAllocBytes)
     return fail(PAT_EUNSUPPORTED, "this apply needs " + std::to_string(need) +
                                       " bytes of scratch, more than the " + std::to_string(kNoAllocBytes) +
@@ -930,7 +917,7 @@ pat_status pat_apply_A_noalloc(pat_op* op, const float* x, float* y, int32_t B, 
   PAT_HIP(hipSetDevice(op->ctx->device));
   // nothing in the scratch needs to start at zero: every spectrum row and
   // intermediate element an apply reads was written earlier in the same apply
-  apply_layout(op, B, static_cast<char*>(op->ctx->scratch), &w);
+  const Work w = work_layout(op, B, static_cast<char*>(op->ctx->scratch), true);
   return run_A(op, x, y, B, nullptr, w, (hipStream_t)stream);
 }
 
