@@ -111,52 +111,81 @@ __device__ __forceinline__ int a_unit(int ks, int idx) { return idx ^ ((2 * ks +
 // Work item = (pair, 8 consecutive k): 8 complex values in, four 16-byte
 // fragment units out (re and im columns, hi and lo terms).  Consecutive lanes
 // take consecutive k-octets of one pair, so the global loads of 16 lanes are
-// one contiguous kilobyte of a spectrum row.
+// one contiguous kilobyte of a spectrum row.  Every load of a thread's items
+// (and of the per-depth scales) is issued before the first is used: one
+// memory latency per chunk.  gmask: bit g set when member slot g of the item
+// holds a frequency.
 template <int MT>
-__device__ __forceinline__ void stage_chunk(const MfmaArgs& a, u32x4* lds, int c, int p0, int gp,
-                                            int ch, int tid) {
+__device__ __forceinline__ void stage_chunk(const MfmaArgs& a, u32x4* lds, int c, unsigned gmask, int p0,
+                                            int gp, int ch, int tid) {
   const int k0 = ch * kKC * 16;
   constexpr int items = MT * 16 * kKC * 2;  // pairs x k-octets
-  for (int it = tid; it < items; it += kWaves * 64) {
+  constexpr int per = items / (kWaves * 64);  // items per thread
+  static_assert(items % (kWaves * 64) == 0, "whole items per thread");
+  float4 q[per][4];  // 8 complex values per item
+  float4 sq[per][2];  // their 8 scales
+#pragma unroll
+  for (int r = 0; r < per; ++r) {
+    const int it = tid + r * kWaves * 64;
+    const int pl = it / (kKC * 2), ko = it % (kKC * 2);
+    const int kb = k0 + ko * 8;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) q[r][e] = make_float4(0.f, 0.f, 0.f, 0.f);
+    sq[r][0] = sq[r][1] = make_float4(1.f, 1.f, 1.f, 1.f);
+    if (pl >= gp) continue;
+    const int pair = p0 + pl;
+    const int g = pair / a.B, b = pair % a.B;
+    if (!((gmask >> g) & 1u)) continue;
+    const float2* src = a.in + (size_t)(c * a.G + g) * a.in_rs + (size_t)b * a.K;
+    if (kb + 8 <= a.K) {  // 64 aligned bytes
+      const float4* s4 = reinterpret_cast<const float4*>(src + kb);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) q[r][e] = s4[e];
+      if (a.in_scale) {
+        const float4* c4 = reinterpret_cast<const float4*>(a.in_scale + kb);
+        sq[r][0] = c4[0];
+        sq[r][1] = c4[1];
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        if (kb + e < a.K) {
+          const float2 v = src[kb + e];
+          const float sc = a.in_scale ? a.in_scale[kb + e] : 1.f;
+          if (e & 1) {
+            q[r][e >> 1].z = v.x;
+            q[r][e >> 1].w = v.y;
+          } else {
+            q[r][e >> 1].x = v.x;
+            q[r][e >> 1].y = v.y;
+          }
+          sq[r][e >> 2][e & 3] = sc;
+        }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < per; ++r) {
+    const int it = tid + r * kWaves * 64;
     const int pl = it / (kKC * 2), ko = it % (kKC * 2);
     float2 v[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = make_float2(0.f, 0.f);
-    if (pl < gp) {
-      const int pair = p0 + pl;
-      const int g = pair / a.B, b = pair % a.B;
-      if (a.members[c * a.G + g] >= 0) {
-        const float2* src = a.in + (size_t)(c * a.G + g) * a.in_rs + (size_t)b * a.K;
-        const int kb = k0 + ko * 8;
-        if (kb + 8 <= a.K) {  // 64 aligned bytes
-          const float4* s4 = reinterpret_cast<const float4*>(src + kb);
+    for (int e = 0; e < 4; ++e) {
+      v[2 * e] = make_float2(q[r][e].x, q[r][e].y);
+      v[2 * e + 1] = make_float2(q[r][e].z, q[r][e].w);
+    }
+    if (a.in_scale) {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const float4 q = s4[e];
-            v[2 * e] = make_float2(q.x, q.y);
-            v[2 * e + 1] = make_float2(q.z, q.w);
-          }
-        } else {
-#pragma unroll
-          for (int e = 0; e < 8; ++e)
-            if (kb + e < a.K) v[e] = src[kb + e];
-        }
-        if (a.in_scale) {
-#pragma unroll
-          for (int e = 0; e < 8; ++e)
-            if (kb + e < a.K) {
-              const float sc = a.in_scale[kb + e];
-              v[e].x *= sc;
-              v[e].y *= sc;
-            }
-        }
+      for (int e = 0; e < 8; ++e) {
+        const float sc = sq[r][e >> 2][e & 3];
+        v[e].x *= sc;
+        v[e].y *= sc;
       }
     }
     const int ks = ko >> 1, half = ko & 1;
 #pragma unroll
     for (int part = 0; part < 2; ++part) {
       const int col = 2 * pl + part;
-      const int mt = col >> 5, r = col & 31;
+      const int mt = col >> 5, rr = col & 31;
       Frag hi, lo;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
@@ -168,7 +197,7 @@ __device__ __forceinline__ void stage_chunk(const MfmaArgs& a, u32x4* lds, int c
         hi.u[j] = h;
         lo.u[j] = l;
       }
-      const int unit = (ks * MT + mt) * 64 + a_unit(ks, r + 32 * half);
+      const int unit = (ks * MT + mt) * 64 + a_unit(ks, rr + 32 * half);
       lds[unit] = hi.u;
       lds[kKC * MT * 64 + unit] = lo.u;
     }
@@ -194,6 +223,13 @@ __global__ __launch_bounds__(kWaves * 64, 3) void k_contract_mfma(MfmaArgs a, in
     c = u / groups;
     cg = u - c * groups;
   }
+  // filled member slots of the item, in a register: the loops below test
+  // this mask instead of reading the member table between their stores
+  // (a load after a store waits for that store on the in-order counter)
+  unsigned gmask = 0;
+#pragma unroll
+  for (int g = 0; g < 8; ++g)
+    if (g < a.G && a.members[c * a.G + g] >= 0) gmask |= 1u << g;
   const int npairs = a.G * a.B;
   const int p0 = cg * (kMT * 16);
   const int gp = min(MT * 16, npairs - p0);  // pairs in this launch group
@@ -214,6 +250,9 @@ __global__ __launch_bounds__(kWaves * 64, 3) void k_contract_mfma(MfmaArgs a, in
   for (int tile0 = 0; tile0 < a.ntiles; tile0 += wstride) {
     const int tile = tile0 + wslot;
     const bool has = tile < a.ntiles;
+    // output row of this lane and its scale, read before the tile's loads
+    const int row = tile * 32 + (lane & 31);
+    const float sc = a.out_scale && has && row < a.N ? a.out_scale[row] : 1.f;
     f32x16 acc[MT];
 #pragma unroll
     for (int m = 0; m < MT; ++m) acc[m] = f32x16(0.f);
@@ -222,7 +261,7 @@ __global__ __launch_bounds__(kWaves * 64, 3) void k_contract_mfma(MfmaArgs a, in
       const int nks = min(kKC, a.ksteps - ch * kKC);
       if (!(staged && nchunks == 1)) {
         __syncthreads();
-        stage_chunk<MT>(a, lds, c, p0, gp, ch, tid);
+        stage_chunk<MT>(a, lds, c, gmask, p0, gp, ch, tid);
         __syncthreads();
         staged = true;
       }
@@ -330,10 +369,19 @@ __global__ __launch_bounds__(kWaves * 64, 3) void k_contract_mfma(MfmaArgs a, in
       }
     }
 
+    // per-row output scale (1 when there is none), applied here on
+    // straight-line code (the empty asm keeps the compiler from sinking the
+    // products into the conditional stores below, where each store would
+    // first wait for the scale's load and so for every earlier store)
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[m][v] *= sc;
+      asm volatile("" : "+v"(acc[m]));
+    }
+
     // store (re, im) pairs along the output index
-    const int row = tile * 32 + (lane & 31);
     if (has && kpart == 0 && row < a.N) {
-      const float sc = a.out_scale ? a.out_scale[row] : 1.f;
 #pragma unroll
       for (int m = 0; m < MT; ++m) {
 #pragma unroll
@@ -343,10 +391,10 @@ __global__ __launch_bounds__(kWaves * 64, 3) void k_contract_mfma(MfmaArgs a, in
           if (pl >= gp) continue;
           const int pair = p0 + pl;
           const int g = pair / a.B, b = pair % a.B;
-          if (a.members[c * a.G + g] < 0) continue;
+          if (!((gmask >> g) & 1u)) continue;
           // streamed out: not read again by this kernel
           typedef float v2f __attribute__((ext_vector_type(2)));
-          __builtin_nontemporal_store(v2f{acc[m][v] * sc, acc[m][v + 1] * sc},
+          __builtin_nontemporal_store(v2f{acc[m][v], acc[m][v + 1]},
                                       reinterpret_cast<v2f*>(a.out + (size_t)(c * a.G + g) * a.out_rs +
                                                              (size_t)b * a.N + row));
         }
@@ -374,6 +422,7 @@ pat_status contract_mfma(const MfmaArgs& a, int hdtype, hipStream_t st) {
   const int src = hdtype == PAT_H_F16 ? kSrcF16 : hdtype == PAT_H_F32 ? kSrcF32 : kSrcBf16;
   if (src == kSrcF32 && !a.krows) return fail(PAT_EINVAL, "float32 contraction on the matrix cores needs the k rows");
   if (src != kSrcF32 && !a.frag) return fail(PAT_EINVAL, "16-bit contraction needs the operand tiles");
+  if (a.G < 1 || a.G > 8) return fail(PAT_EINVAL, "work items hold 1 to 8 member slots");
   const int npairs = a.G * a.B;
   const int groups = (npairs + kMT * 16 - 1) / (kMT * 16);
   if (((long long)a.nitem * groups + 7) / 8 * 8 > 0x7fffffffLL) return fail(PAT_EUNSUPPORTED, "contraction grid too large");
