@@ -125,10 +125,12 @@ __device__ __forceinline__ void contract_item(const ContractArgs& a, int lr_log2
     const int total = GG * h;
     for (int base = tid; base < total; base += 256 * kStage) {
       float4 v[kStage];
+      float2 sv[kStage];  // the per-row scales of the pair, loaded with it
 #pragma unroll
       for (int q = 0; q < kStage; ++q) {
         const int idx = base + q * 256;
         v[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+        sv[q] = make_float2(1.f, 1.f);
         if (idx < total) {
           const int g = idx % GG, i = 2 * (idx / GG);
           int k = -1;
@@ -136,6 +138,7 @@ __device__ __forceinline__ void contract_item(const ContractArgs& a, int lr_log2
           for (int gg = 0; gg < GG; ++gg) k = (gg == g) ? kg[gg] : k;
           if (k >= 0)
             v[q] = *reinterpret_cast<const float4*>(a.in + (size_t)(t * G + g) * a.in_rs + (size_t)b * a.ni + i);
+          if (a.in_scale) sv[q] = *reinterpret_cast<const float2*>(a.in_scale + i);
         }
       }
 #pragma unroll
@@ -144,10 +147,7 @@ __device__ __forceinline__ void contract_item(const ContractArgs& a, int lr_log2
         if (idx >= total) break;
         const int g = idx % GG, i = 2 * (idx / GG);
         float4 w = v[q];
-        if (a.in_scale) {
-          const float s0 = a.in_scale[i], s1 = a.in_scale[i + 1];
-          w = make_float4(w.x * s0, w.y * s0, w.z * s1, w.w * s1);
-        }
+        if (a.in_scale) w = make_float4(w.x * sv[q].x, w.y * sv[q].x, w.z * sv[q].y, w.w * sv[q].y);
         xin[i * GG + g] = make_float2(w.x, w.y);
         xin[(i + 1) * GG + g] = make_float2(w.z, w.w);
       }
@@ -225,13 +225,22 @@ __device__ __forceinline__ void contract_item(const ContractArgs& a, int lr_log2
   __syncthreads();
   float2* ob = reinterpret_cast<float2*>(smem_raw);
   if (rg == 0) {
+    // per-row output scales: every load issued before the first is used
+    float scv[JPT][VEC];
+#pragma unroll
+    for (int jj = 0; jj < JPT; ++jj)
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        const int j = (lr + jj * Lr) * VEC + v;
+        scv[jj][v] = a.out_scale ? a.out_scale[j0 + min(j, njl - 1)] : 1.f;
+      }
 #pragma unroll
     for (int jj = 0; jj < JPT; ++jj) {
 #pragma unroll
       for (int v = 0; v < VEC; ++v) {
         const int j = (lr + jj * Lr) * VEC + v;
         if (j >= njl) continue;
-        const float sc = a.out_scale ? a.out_scale[j0 + j] : 1.f;
+        const float sc = scv[jj][v];
 #pragma unroll
         for (int g = 0; g < GG; ++g) {
           const float* p = &acc[((jj * VEC + v) * GG + g) * 2];
@@ -244,20 +253,49 @@ __device__ __forceinline__ void contract_item(const ContractArgs& a, int lr_log2
   if ((njl & 1) == 0 && (a.nj & 1) == 0) {
     // two complex values (16 bytes) per store, non-temporal: the rows are
     // not read again by this kernel
+    // groups of kOut elements per thread: the values of a group (and the
+    // subtracted ones) are all read into separate registers before its
+    // first store; a load issued after a store, or a register rewritten
+    // while a store still reads it, waits for that store on the in-order
+    // memory counter
+    constexpr int kOut = 4;
     const int h = njl >> 1;
-    for (int e = tid; e < GG * h; e += 256) {
-      const int g = e / h, j = 2 * (e - g * h);
-      int k = -1;
+    for (int e0 = tid; e0 < GG * h; e0 += 256 * kOut) {
+      float4 val[kOut], sub[kOut];
+      bool ok[kOut];
 #pragma unroll
-      for (int gg = 0; gg < GG; ++gg) k = (gg == g) ? kg[gg] : k;
-      if (k >= 0) {
-        const size_t o = (size_t)(t * G + g) * a.out_rs + (size_t)b * a.nj + j0 + j;
-        float4 v = *reinterpret_cast<const float4*>(ob + g * njl + j);
-        if (a.out_sub) {
-          const float4 s = *reinterpret_cast<const float4*>(a.out_sub + o);
-          v = make_float4(v.x - s.x, v.y - s.y, v.z - s.z, v.w - s.w);
+      for (int q = 0; q < kOut; ++q) {
+        const int e = e0 + q * 256;
+        const int g = e / h, j = 2 * (e - g * h);
+        int k = -1;
+#pragma unroll
+        for (int gg = 0; gg < GG; ++gg) k = (gg == g) ? kg[gg] : k;
+        ok[q] = e < GG * h && k >= 0;
+        sub[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+        val[q] = sub[q];
+        if (ok[q]) {
+          val[q] = *reinterpret_cast<const float4*>(ob + g * njl + j);
+          if (a.out_sub)
+            sub[q] = *reinterpret_cast<const float4*>(a.out_sub + (size_t)(t * G + g) * a.out_rs +
+                                                      (size_t)b * a.nj + j0 + j);
         }
-        __builtin_nontemporal_store(v4f{v.x, v.y, v.z, v.w}, reinterpret_cast<v4f*>(a.out + o));
+      }
+      // differences on straight-line code (the empty asm keeps them out of
+      // the conditional stores, where each store would wait again)
+      v4f d[kOut];
+#pragma unroll
+      for (int q = 0; q < kOut; ++q) {
+        d[q] = v4f{val[q].x - sub[q].x, val[q].y - sub[q].y, val[q].z - sub[q].z, val[q].w - sub[q].w};
+        asm volatile("" : "+v"(d[q]));
+      }
+#pragma unroll
+      for (int q = 0; q < kOut; ++q) {
+        const int e = e0 + q * 256;
+        const int g = e / h, j = 2 * (e - g * h);
+        if (ok[q]) {
+          const size_t o = (size_t)(t * G + g) * a.out_rs + (size_t)b * a.nj + j0 + j;
+          __builtin_nontemporal_store(d[q], reinterpret_cast<v4f*>(a.out + o));
+        }
       }
     }
   } else {
