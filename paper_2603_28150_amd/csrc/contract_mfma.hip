@@ -43,6 +43,7 @@ constexpr int kWaves = 4;      // waves per workgroup (three workgroups share a 
 constexpr int kKC = 8;         // k-steps (of 16) per staged chunk
 constexpr int kMT = 2;         // most 32-column tiles per launch group (32 pairs)
 constexpr int kTerms = 2;      // hi + lo split of the spectra
+constexpr int kMinBlocks = 3;  // workgroups per CU the registers are sized for
 
 // two floats -> two bfloat16 (round to nearest even) packed low, high
 __device__ __forceinline__ unsigned pk_bf16(float a, float b) {
@@ -98,6 +99,15 @@ __device__ __forceinline__ void split_f16(const Frag& in, Frag& hi, Frag& lo) {
   }
 }
 
+// Workgroup barrier that orders LDS accesses only: waves share nothing
+// through global memory here, so a barrier need not wait for the wave's
+// outstanding global loads and stores (a full __syncthreads() would).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // LDS position, within its 64-unit fragment row, of the A-operand unit that
 // lane `idx` of k-step ks reads: the unit index XOR (2 ks + idx/32), a value
 // below 16, so the bit that selects the k half is kept and each 16-lane
@@ -114,8 +124,8 @@ __device__ __forceinline__ int a_unit(int ks, int idx) { return idx ^ ((2 * ks +
 // one contiguous kilobyte of a spectrum row.  Every load of a thread's items
 // (and of the per-depth scales) is issued before the first is used: one
 // memory latency per chunk.  gmask: bit g set when member slot g of the item
-// holds a frequency.
-template <int MT>
+// holds a frequency.  SCALED: the library has per-depth scales (16-bit).
+template <int MT, bool SCALED>
 __device__ __forceinline__ void stage_chunk(const MfmaArgs& a, u32x4* lds, int c, unsigned gmask, int p0,
                                             int gp, int ch, int tid) {
   const int k0 = ch * kKC * 16;
@@ -123,7 +133,7 @@ __device__ __forceinline__ void stage_chunk(const MfmaArgs& a, u32x4* lds, int c
   constexpr int per = items / (kWaves * 64);  // items per thread
   static_assert(items % (kWaves * 64) == 0, "whole items per thread");
   float4 q[per][4];  // 8 complex values per item
-  float4 sq[per][2];  // their 8 scales
+  float4 sq[SCALED ? per : 1][2];  // their 8 scales
 #pragma unroll
   for (int r = 0; r < per; ++r) {
     const int it = tid + r * kWaves * 64;
@@ -131,7 +141,7 @@ __device__ __forceinline__ void stage_chunk(const MfmaArgs& a, u32x4* lds, int c
     const int kb = k0 + ko * 8;
 #pragma unroll
     for (int e = 0; e < 4; ++e) q[r][e] = make_float4(0.f, 0.f, 0.f, 0.f);
-    sq[r][0] = sq[r][1] = make_float4(1.f, 1.f, 1.f, 1.f);
+    if constexpr (SCALED) sq[r][0] = sq[r][1] = make_float4(1.f, 1.f, 1.f, 1.f);
     if (pl >= gp) continue;
     const int pair = p0 + pl;
     const int g = pair / a.B, b = pair % a.B;
@@ -141,17 +151,18 @@ __device__ __forceinline__ void stage_chunk(const MfmaArgs& a, u32x4* lds, int c
       const float4* s4 = reinterpret_cast<const float4*>(src + kb);
 #pragma unroll
       for (int e = 0; e < 4; ++e) q[r][e] = s4[e];
-      if (a.in_scale) {
-        const float4* c4 = reinterpret_cast<const float4*>(a.in_scale + kb);
-        sq[r][0] = c4[0];
-        sq[r][1] = c4[1];
+      if constexpr (SCALED) {
+        if (a.in_scale) {
+          const float4* c4 = reinterpret_cast<const float4*>(a.in_scale + kb);
+          sq[r][0] = c4[0];
+          sq[r][1] = c4[1];
+        }
       }
     } else {
 #pragma unroll
       for (int e = 0; e < 8; ++e)
         if (kb + e < a.K) {
           const float2 v = src[kb + e];
-          const float sc = a.in_scale ? a.in_scale[kb + e] : 1.f;
           if (e & 1) {
             q[r][e >> 1].z = v.x;
             q[r][e >> 1].w = v.y;
@@ -159,7 +170,7 @@ __device__ __forceinline__ void stage_chunk(const MfmaArgs& a, u32x4* lds, int c
             q[r][e >> 1].x = v.x;
             q[r][e >> 1].y = v.y;
           }
-          sq[r][e >> 2][e & 3] = sc;
+          if constexpr (SCALED) sq[r][e >> 2][e & 3] = a.in_scale ? a.in_scale[kb + e] : 1.f;
         }
     }
   }
@@ -173,10 +184,10 @@ __device__ __forceinline__ void stage_chunk(const MfmaArgs& a, u32x4* lds, int c
       v[2 * e] = make_float2(q[r][e].x, q[r][e].y);
       v[2 * e + 1] = make_float2(q[r][e].z, q[r][e].w);
     }
-    if (a.in_scale) {
+    if (SCALED && a.in_scale) {
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const float sc = sq[r][e >> 2][e & 3];
+        const float sc = sq[SCALED ? r : 0][e >> 2][e & 3];
         v[e].x *= sc;
         v[e].y *= sc;
       }
@@ -204,8 +215,10 @@ __device__ __forceinline__ void stage_chunk(const MfmaArgs& a, u32x4* lds, int c
   }
 }
 
-template <int SRC, int MT>
-__global__ __launch_bounds__(kWaves * 64, 3) void k_contract_mfma(MfmaArgs a, int groups) {
+// ALIGNED: K a multiple of 16 and N of 32 (float32 rows read without bounds
+// branches)
+template <int SRC, int MT, bool ALIGNED>
+__global__ __launch_bounds__(kWaves * 64, kMinBlocks) void k_contract_mfma(MfmaArgs a, int groups) {
   extern __shared__ u32x4 lds[];  // [term][ks][mt][lane] 16-byte units
   constexpr int KB = SRC == kSrcF32 ? kKC / 4 : kKC / 2;  // k-steps per batch of B loads
   const int tid = threadIdx.x;
@@ -247,107 +260,158 @@ __global__ __launch_bounds__(kWaves * 64, 3) void k_contract_mfma(MfmaArgs a, in
   const float* krow = SRC == kSrcF32 ? a.krows + (size_t)a.item_slab[c] * a.k_slab : nullptr;
   bool staged = false;  // LDS holds chunk 0 (kept only when there is one chunk)
 
+  // The B operands of one batch of KB k-steps (16-bit fragments, or float32
+  // rows: 8 floats per lane and k-step).
+  struct BBatch {
+    Frag fr[KB];
+    u32x4 raw[KB][2];
+  };
+  // Issues the loads of batch (tile, chunk ch, first k-step s0) of this wave;
+  // a tile past the end loads nothing (zeros).
+  auto load_batch = [&](BBatch& o, int tile, int ch, int s0) {
+    const bool has = tile < a.ntiles;
+    const int nks = min(kKC, a.ksteps - ch * kKC);
+#pragma unroll
+    for (int s = 0; s < KB; ++s) {
+      const int ks = kpart + (s0 + s) * kparts;
+      const bool ok = has && (s0 + s) * kparts < kKC && ks < nks;
+      if constexpr (SRC != kSrcF32) {
+        // plain loads: the other column groups of the item (and the other
+        // items of a split class) read the same fragments next, from the
+        // XCD's L2.  (Loaded under a branch: branch-free, the compiler
+        // moves the last load of a batch behind the first products, and the
+        // wave then waits twice per batch.)
+        if (ok)
+          o.fr[s].u = slab[((size_t)tile * a.ksteps + ch * kKC + ks) * 64 + lane];
+        else
+          o.fr[s].u = u32x4(0);
+      } else if constexpr (ALIGNED) {
+        // K a multiple of 16 and N of 32: every in-range row segment is a
+        // whole 32 bytes; out of range, row 0 is read and never used (no
+        // branch hides a load from the wait counter, and no select forces
+        // a wait right after the load)
+        const int n = tile * 32 + (lane & 31);
+        const int k0 = (ch * kKC + ks) * 16 + 8 * (lane >> 5);
+        const u32x4* src = reinterpret_cast<const u32x4*>(krow + (ok ? (size_t)n * a.k_srow + k0 : (size_t)0));
+        o.raw[s][0] = src[0];
+        o.raw[s][1] = src[1];
+      } else {
+        const int n = tile * 32 + (lane & 31);
+        const int k0 = (ch * kKC + ks) * 16 + 8 * (lane >> 5);
+        o.raw[s][0] = u32x4(0);
+        o.raw[s][1] = u32x4(0);
+        if (ok && n < a.N) {
+          const float* src = krow + (size_t)n * a.k_srow + k0;
+          if (k0 + 8 <= a.K) {
+            // plain loads: the 128-byte lines serve two k-steps
+            o.raw[s][0] = *reinterpret_cast<const u32x4*>(src);
+            o.raw[s][1] = *(reinterpret_cast<const u32x4*>(src) + 1);
+          } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+              if (k0 + e < a.K) o.raw[s][e >> 2][e & 3] = __float_as_uint(src[e]);
+          }
+        }
+      }
+    }
+  };
+  // The products of one loaded batch with the staged spectra.
+  auto mma_batch = [&](const BBatch& o, int ch, int s0, f32x16 (&acc)[MT]) {
+    const int nks = min(kKC, a.ksteps - ch * kKC);
+#pragma unroll
+    for (int s = 0; s < KB; ++s) {
+      const int ks = kpart + (s0 + s) * kparts;
+      if ((s0 + s) * kparts >= kKC || ks >= nks) break;
+      if constexpr (SRC == kSrcBf16) {
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+          Frag ah, al;
+          ah.u = lds[(ks * MT + m) * 64 + a_unit(ks, lane)];
+          al.u = lds[(kKC * MT + ks * MT + m) * 64 + a_unit(ks, lane)];
+          acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah.b, o.fr[s].b, acc[m], 0, 0, 0);
+          acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al.b, o.fr[s].b, acc[m], 0, 0, 0);
+        }
+      } else if constexpr (SRC == kSrcF16) {
+        Frag hh, hl;
+        split_f16(o.fr[s], hh, hl);
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+          Frag ah, al;
+          ah.u = lds[(ks * MT + m) * 64 + a_unit(ks, lane)];
+          al.u = lds[(kKC * MT + ks * MT + m) * 64 + a_unit(ks, lane)];
+          acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah.b, hh.b, acc[m], 0, 0, 0);
+          acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al.b, hh.b, acc[m], 0, 0, 0);
+          acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah.b, hl.b, acc[m], 0, 0, 0);
+          acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al.b, hl.b, acc[m], 0, 0, 0);
+        }
+      } else {
+        Frag b1, b2, b3;
+        split_f32(o.raw[s], b1, b2, b3);
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+          Frag ah, al;
+          ah.u = lds[(ks * MT + m) * 64 + a_unit(ks, lane)];
+          al.u = lds[(kKC * MT + ks * MT + m) * 64 + a_unit(ks, lane)];
+          acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah.b, b1.b, acc[m], 0, 0, 0);
+          acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah.b, b2.b, acc[m], 0, 0, 0);
+          acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al.b, b1.b, acc[m], 0, 0, 0);
+          acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah.b, b3.b, acc[m], 0, 0, 0);
+          acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al.b, b2.b, acc[m], 0, 0, 0);
+        }
+      }
+    }
+  };
+
+  // float32 rows: two batches in flight per wave, the loads of the next
+  // batch (in the next chunk, or the next tile at the end of one) issued
+  // before the products of the current one, and a tile's stores after the
+  // loads of the next tile's first batch, so that waiting for those loads
+  // does not wait for the stores.  16-bit tiles: one batch at a time (the
+  // second buffer, with the depth scales of the staging, would spill).
+  constexpr bool kPipe = SRC == kSrcF32;
+  static_assert(kKC % (2 * KB) == 0, "an even number of batches per chunk");
+  BBatch bA, bB;
+  if constexpr (kPipe) load_batch(bA, wslot, 0, 0);
   for (int tile0 = 0; tile0 < a.ntiles; tile0 += wstride) {
     const int tile = tile0 + wslot;
     const bool has = tile < a.ntiles;
     // output row of this lane and its scale, read before the tile's loads
     const int row = tile * 32 + (lane & 31);
-    const float sc = a.out_scale && has && row < a.N ? a.out_scale[row] : 1.f;
+    const float sc = SRC != kSrcF32 && a.out_scale && has && row < a.N ? a.out_scale[row] : 1.f;
     f32x16 acc[MT];
 #pragma unroll
     for (int m = 0; m < MT; ++m) acc[m] = f32x16(0.f);
 
     for (int ch = 0; ch < nchunks; ++ch) {
-      const int nks = min(kKC, a.ksteps - ch * kKC);
       if (!(staged && nchunks == 1)) {
-        __syncthreads();
-        stage_chunk<MT>(a, lds, c, gmask, p0, gp, ch, tid);
-        __syncthreads();
+        lds_barrier();
+        stage_chunk<MT, SRC != kSrcF32>(a, lds, c, gmask, p0, gp, ch, tid);
+        lds_barrier();
         staged = true;
       }
-      // this wave's B operands of the chunk, in batches of KB k-steps with all
-      // loads of a batch issued before its MFMAs (the batch loop is kept rolled:
-      // unrolled, the compiler hoists later batches' loads and the registers
-      // no longer fit three waves per SIMD)
+      if constexpr (!kPipe) {
 #pragma unroll 1
-      for (int s0 = 0; s0 < kKC; s0 += KB) {
-        Frag fr[KB];
-        u32x4 raw[KB][2];  // float32 rows: 8 floats per lane and k-step
-#pragma unroll
-        for (int s = 0; s < KB; ++s) {
-          const int ks = kpart + (s0 + s) * kparts;
-          const bool ok = has && (s0 + s) * kparts < kKC && ks < nks;
-          if constexpr (SRC != kSrcF32) {
-            // plain loads: the other column groups of the item (and the
-            // other items of a split class) read the same fragments next,
-            // from the XCD's L2
-            if (ok)
-              fr[s].u = slab[((size_t)tile * a.ksteps + ch * kKC + ks) * 64 + lane];
-            else
-              fr[s].u = u32x4(0);
-          } else {
-            const int n = tile * 32 + (lane & 31);
-            const int k0 = (ch * kKC + ks) * 16 + 8 * (lane >> 5);
-            raw[s][0] = u32x4(0);
-            raw[s][1] = u32x4(0);
-            if (ok && n < a.N) {
-              const float* src = krow + (size_t)n * a.k_srow + k0;
-              if (k0 + 8 <= a.K) {
-                // plain loads: the 128-byte lines serve two k-steps
-                raw[s][0] = *reinterpret_cast<const u32x4*>(src);
-                raw[s][1] = *(reinterpret_cast<const u32x4*>(src) + 1);
-              } else {
-#pragma unroll
-                for (int e = 0; e < 8; ++e)
-                  if (k0 + e < a.K) raw[s][e >> 2][e & 3] = __float_as_uint(src[e]);
-              }
-            }
+        for (int s0 = 0; s0 < kKC; s0 += KB) {
+          load_batch(bA, tile, ch, s0);
+          if (has) mma_batch(bA, ch, s0, acc);
+        }
+        continue;
+      }
+#pragma unroll 1
+      for (int s0 = 0; s0 < kKC; s0 += 2 * KB) {
+        // bA holds batch s0
+        load_batch(bB, tile, ch, s0 + KB);
+        if (has) mma_batch(bA, ch, s0, acc);
+        int nt = tile, nc = ch, ns = s0 + 2 * KB;
+        if (ns >= kKC) {
+          ns = 0;
+          if (++nc >= nchunks) {
+            nc = 0;
+            nt = tile + wstride;
           }
         }
-        if (has) {
-#pragma unroll
-          for (int s = 0; s < KB; ++s) {
-            const int ks = kpart + (s0 + s) * kparts;
-            if ((s0 + s) * kparts >= kKC || ks >= nks) break;
-            if constexpr (SRC == kSrcBf16) {
-#pragma unroll
-              for (int m = 0; m < MT; ++m) {
-                Frag ah, al;
-                ah.u = lds[(ks * MT + m) * 64 + a_unit(ks, lane)];
-                al.u = lds[(kKC * MT + ks * MT + m) * 64 + a_unit(ks, lane)];
-                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah.b, fr[s].b, acc[m], 0, 0, 0);
-                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al.b, fr[s].b, acc[m], 0, 0, 0);
-              }
-            } else if constexpr (SRC == kSrcF16) {
-              Frag hh, hl;
-              split_f16(fr[s], hh, hl);
-#pragma unroll
-              for (int m = 0; m < MT; ++m) {
-                Frag ah, al;
-                ah.u = lds[(ks * MT + m) * 64 + a_unit(ks, lane)];
-                al.u = lds[(kKC * MT + ks * MT + m) * 64 + a_unit(ks, lane)];
-                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah.b, hh.b, acc[m], 0, 0, 0);
-                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al.b, hh.b, acc[m], 0, 0, 0);
-                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah.b, hl.b, acc[m], 0, 0, 0);
-                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al.b, hl.b, acc[m], 0, 0, 0);
-              }
-            } else {
-              Frag b1, b2, b3;
-              split_f32(raw[s], b1, b2, b3);
-#pragma unroll
-              for (int m = 0; m < MT; ++m) {
-                Frag ah, al;
-                ah.u = lds[(ks * MT + m) * 64 + a_unit(ks, lane)];
-                al.u = lds[(kKC * MT + ks * MT + m) * 64 + a_unit(ks, lane)];
-                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah.b, b1.b, acc[m], 0, 0, 0);
-                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah.b, b2.b, acc[m], 0, 0, 0);
-                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al.b, b1.b, acc[m], 0, 0, 0);
-                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah.b, b3.b, acc[m], 0, 0, 0);
-                acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al.b, b2.b, acc[m], 0, 0, 0);
-              }
-            }
-          }
-        }
+        load_batch(bA, nt, nc, ns);
+        if (has) mma_batch(bB, ch, s0 + KB, acc);
       }
     }
 
@@ -357,10 +421,10 @@ __global__ __launch_bounds__(kWaves * 64, 3) void k_contract_mfma(MfmaArgs a, in
       staged = false;
 #pragma unroll
       for (int m = 0; m < MT; ++m) {
-        __syncthreads();
+        lds_barrier();
 #pragma unroll
         for (int v = 0; v < 16; ++v) red[(w * 16 + v) * 64 + lane] = acc[m][v];
-        __syncthreads();
+        lds_barrier();
         if (kpart == 0) {
           for (int p = 1; p < kparts; ++p)
 #pragma unroll
@@ -410,11 +474,13 @@ static void launch_mt(const MfmaArgs& a, int src, int groups, hipStream_t st) {
   const size_t bytes = lds > red ? lds : red;
   dim3 grid((unsigned)(((long long)a.nitem * groups + 7) / 8 * 8));
   if (src == kSrcF16)
-    k_contract_mfma<kSrcF16, MT><<<grid, kWaves * 64, bytes, st>>>(a, groups);
+    k_contract_mfma<kSrcF16, MT, false><<<grid, kWaves * 64, bytes, st>>>(a, groups);
+  else if (src == kSrcF32 && a.K % 16 == 0 && a.N % 32 == 0)
+    k_contract_mfma<kSrcF32, MT, true><<<grid, kWaves * 64, bytes, st>>>(a, groups);
   else if (src == kSrcF32)
-    k_contract_mfma<kSrcF32, MT><<<grid, kWaves * 64, bytes, st>>>(a, groups);
+    k_contract_mfma<kSrcF32, MT, false><<<grid, kWaves * 64, bytes, st>>>(a, groups);
   else
-    k_contract_mfma<kSrcBf16, MT><<<grid, kWaves * 64, bytes, st>>>(a, groups);
+    k_contract_mfma<kSrcBf16, MT, false><<<grid, kWaves * 64, bytes, st>>>(a, groups);
 }
 
 pat_status contract_mfma(const MfmaArgs& a, int hdtype, hipStream_t st) {
