@@ -39,11 +39,10 @@ typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kWaves = 4;      // waves per workgroup (three workgroups share a CU)
+constexpr int kWaves = 4;      // waves per workgroup
 constexpr int kKC = 8;         // k-steps (of 16) per staged chunk
-constexpr int kMT = 2;         // most 32-column tiles per launch group (32 pairs)
 constexpr int kTerms = 2;      // hi + lo split of the spectra
-constexpr int kMinBlocks = 3;  // workgroups per CU the registers are sized for
+constexpr int kMinBlocks = 3;  // workgroups per CU the registers are sized for (2 at MT = 4)
 
 // two floats -> two bfloat16 (round to nearest even) packed low, high
 __device__ __forceinline__ unsigned pk_bf16(float a, float b) {
@@ -121,104 +120,110 @@ __device__ __forceinline__ int a_unit(int ks, int idx) { return idx ^ ((2 * ks +
 // Work item = (pair, 8 consecutive k): 8 complex values in, four 16-byte
 // fragment units out (re and im columns, hi and lo terms).  Consecutive lanes
 // take consecutive k-octets of one pair, so the global loads of 16 lanes are
-// one contiguous kilobyte of a spectrum row.  Every load of a thread's items
-// (and of the per-depth scales) is issued before the first is used: one
-// memory latency per chunk.  gmask: bit g set when member slot g of the item
-// holds a frequency.  SCALED: the library has per-depth scales (16-bit).
+// one contiguous kilobyte of a spectrum row.  A thread's items go in rounds
+// of two, every load of a round (and of its per-depth scales) issued before
+// the first is used: one memory latency per chunk up to 32-pair groups, two
+// for 64-pair groups (whose four items would not fit the registers at once).
+// gmask: bit g set when member slot g of the item holds a frequency.
+// SCALED: the library has per-depth scales (16-bit).
 template <int MT, bool SCALED>
 __device__ __forceinline__ void stage_chunk(const MfmaArgs& a, u32x4* lds, int c, unsigned gmask, int p0,
                                             int gp, int ch, int tid) {
   const int k0 = ch * kKC * 16;
   constexpr int items = MT * 16 * kKC * 2;  // pairs x k-octets
-  constexpr int per = items / (kWaves * 64);  // items per thread
+  constexpr int per_all = items / (kWaves * 64);  // items per thread
   static_assert(items % (kWaves * 64) == 0, "whole items per thread");
-  float4 q[per][4];  // 8 complex values per item
-  float4 sq[SCALED ? per : 1][2];  // their 8 scales
+  constexpr int per = per_all < 2 ? per_all : 2;  // items per round trip
 #pragma unroll
-  for (int r = 0; r < per; ++r) {
-    const int it = tid + r * kWaves * 64;
-    const int pl = it / (kKC * 2), ko = it % (kKC * 2);
-    const int kb = k0 + ko * 8;
+  for (int r0 = 0; r0 < per_all; r0 += per) {
+    float4 q[per][4];  // 8 complex values per item
+    float4 sq[SCALED ? per : 1][2];  // their 8 scales
 #pragma unroll
-    for (int e = 0; e < 4; ++e) q[r][e] = make_float4(0.f, 0.f, 0.f, 0.f);
-    if constexpr (SCALED) sq[r][0] = sq[r][1] = make_float4(1.f, 1.f, 1.f, 1.f);
-    if (pl >= gp) continue;
-    const int pair = p0 + pl;
-    const int g = pair / a.B, b = pair % a.B;
-    if (!((gmask >> g) & 1u)) continue;
-    const float2* src = a.in + (size_t)(c * a.G + g) * a.in_rs + (size_t)b * a.K;
-    if (kb + 8 <= a.K) {  // 64 aligned bytes
-      const float4* s4 = reinterpret_cast<const float4*>(src + kb);
+    for (int r = 0; r < per; ++r) {
+      const int it = tid + (r0 + r) * kWaves * 64;
+      const int pl = it / (kKC * 2), ko = it % (kKC * 2);
+      const int kb = k0 + ko * 8;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) q[r][e] = s4[e];
-      if constexpr (SCALED) {
-        if (a.in_scale) {
-          const float4* c4 = reinterpret_cast<const float4*>(a.in_scale + kb);
-          sq[r][0] = c4[0];
-          sq[r][1] = c4[1];
-        }
-      }
-    } else {
+      for (int e = 0; e < 4; ++e) q[r][e] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if constexpr (SCALED) sq[r][0] = sq[r][1] = make_float4(1.f, 1.f, 1.f, 1.f);
+      if (pl >= gp) continue;
+      const int pair = p0 + pl;
+      const int g = pair / a.B, b = pair % a.B;
+      if (!((gmask >> g) & 1u)) continue;
+      const float2* src = a.in + (size_t)(c * a.G + g) * a.in_rs + (size_t)b * a.K;
+      if (kb + 8 <= a.K) {  // 64 aligned bytes
+        const float4* s4 = reinterpret_cast<const float4*>(src + kb);
 #pragma unroll
-      for (int e = 0; e < 8; ++e)
-        if (kb + e < a.K) {
-          const float2 v = src[kb + e];
-          if (e & 1) {
-            q[r][e >> 1].z = v.x;
-            q[r][e >> 1].w = v.y;
-          } else {
-            q[r][e >> 1].x = v.x;
-            q[r][e >> 1].y = v.y;
+        for (int e = 0; e < 4; ++e) q[r][e] = s4[e];
+        if constexpr (SCALED) {
+          if (a.in_scale) {
+            const float4* c4 = reinterpret_cast<const float4*>(a.in_scale + kb);
+            sq[r][0] = c4[0];
+            sq[r][1] = c4[1];
           }
-          if constexpr (SCALED) sq[r][e >> 2][e & 3] = a.in_scale ? a.in_scale[kb + e] : 1.f;
         }
-    }
-  }
+      } else {
 #pragma unroll
-  for (int r = 0; r < per; ++r) {
-    const int it = tid + r * kWaves * 64;
-    const int pl = it / (kKC * 2), ko = it % (kKC * 2);
-    float2 v[8];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      v[2 * e] = make_float2(q[r][e].x, q[r][e].y);
-      v[2 * e + 1] = make_float2(q[r][e].z, q[r][e].w);
-    }
-    if (SCALED && a.in_scale) {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const float sc = sq[SCALED ? r : 0][e >> 2][e & 3];
-        v[e].x *= sc;
-        v[e].y *= sc;
+        for (int e = 0; e < 8; ++e)
+          if (kb + e < a.K) {
+            const float2 v = src[kb + e];
+            if (e & 1) {
+              q[r][e >> 1].z = v.x;
+              q[r][e >> 1].w = v.y;
+            } else {
+              q[r][e >> 1].x = v.x;
+              q[r][e >> 1].y = v.y;
+            }
+            if constexpr (SCALED) sq[r][e >> 2][e & 3] = a.in_scale ? a.in_scale[kb + e] : 1.f;
+          }
       }
     }
-    const int ks = ko >> 1, half = ko & 1;
 #pragma unroll
-    for (int part = 0; part < 2; ++part) {
-      const int col = 2 * pl + part;
-      const int mt = col >> 5, rr = col & 31;
-      Frag hi, lo;
+    for (int r = 0; r < per; ++r) {
+      const int it = tid + (r0 + r) * kWaves * 64;
+      const int pl = it / (kKC * 2), ko = it % (kKC * 2);
+      float2 v[8];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        unsigned h, l;
-        if (part)
-          split2(v[2 * j].y, v[2 * j + 1].y, h, l);
-        else
-          split2(v[2 * j].x, v[2 * j + 1].x, h, l);
-        hi.u[j] = h;
-        lo.u[j] = l;
+      for (int e = 0; e < 4; ++e) {
+        v[2 * e] = make_float2(q[r][e].x, q[r][e].y);
+        v[2 * e + 1] = make_float2(q[r][e].z, q[r][e].w);
       }
-      const int unit = (ks * MT + mt) * 64 + a_unit(ks, rr + 32 * half);
-      lds[unit] = hi.u;
-      lds[kKC * MT * 64 + unit] = lo.u;
+      if (SCALED && a.in_scale) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const float sc = sq[SCALED ? r : 0][e >> 2][e & 3];
+          v[e].x *= sc;
+          v[e].y *= sc;
+        }
+      }
+      const int ks = ko >> 1, half = ko & 1;
+#pragma unroll
+      for (int part = 0; part < 2; ++part) {
+        const int col = 2 * pl + part;
+        const int mt = col >> 5, rr = col & 31;
+        Frag hi, lo;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          unsigned h, l;
+          if (part)
+            split2(v[2 * j].y, v[2 * j + 1].y, h, l);
+          else
+            split2(v[2 * j].x, v[2 * j + 1].x, h, l);
+          hi.u[j] = h;
+          lo.u[j] = l;
+        }
+        const int unit = (ks * MT + mt) * 64 + a_unit(ks, rr + 32 * half);
+        lds[unit] = hi.u;
+        lds[kKC * MT * 64 + unit] = lo.u;
+      }
     }
-  }
+  }  // rounds of items
 }
 
 // ALIGNED: K a multiple of 16 and N of 32 (float32 rows read without bounds
 // branches)
 template <int SRC, int MT, bool ALIGNED>
-__global__ __launch_bounds__(kWaves * 64, kMinBlocks) void k_contract_mfma(MfmaArgs a, int groups) {
+__global__ __launch_bounds__(kWaves * 64, MT >= 4 ? 2 : kMinBlocks) void k_contract_mfma(MfmaArgs a, int groups) {
   extern __shared__ u32x4 lds[];  // [term][ks][mt][lane] 16-byte units
   constexpr int KB = SRC == kSrcF32 ? kKC / 4 : kKC / 2;  // k-steps per batch of B loads
   const int tid = threadIdx.x;
@@ -244,7 +249,7 @@ __global__ __launch_bounds__(kWaves * 64, kMinBlocks) void k_contract_mfma(MfmaA
   for (int g = 0; g < 8; ++g)
     if (g < a.G && a.members[c * a.G + g] >= 0) gmask |= 1u << g;
   const int npairs = a.G * a.B;
-  const int p0 = cg * (kMT * 16);
+  const int p0 = cg * (MT * 16);
   const int gp = min(MT * 16, npairs - p0);  // pairs in this launch group
   // waves -> (N-tile, k-part): a wave owns one N-tile per pass; when there
   // are fewer N-tiles than waves, waves sharing a tile split its k-steps
@@ -490,11 +495,17 @@ pat_status contract_mfma(const MfmaArgs& a, int hdtype, hipStream_t st) {
   if (src != kSrcF32 && !a.frag) return fail(PAT_EINVAL, "16-bit contraction needs the operand tiles");
   if (a.G < 1 || a.G > 8) return fail(PAT_EINVAL, "work items hold 1 to 8 member slots");
   const int npairs = a.G * a.B;
-  const int groups = (npairs + kMT * 16 - 1) / (kMT * 16);
+  // column groups of 64 pairs for float32 rows (every group splits the
+  // slab's values into bf16 terms and reads the slab once: half as often as
+  // with 32-pair groups; measured 8-10 % faster at B = 16), 32 for 16-bit
+  // tiles (64 measured 1-3 % slower), 16 when there are no more pairs
+  const int MT = npairs <= 16 ? 1 : src == kSrcF32 && npairs >= 64 ? 4 : 2;
+  const int groups = (npairs + MT * 16 - 1) / (MT * 16);
   if (((long long)a.nitem * groups + 7) / 8 * 8 > 0x7fffffffLL) return fail(PAT_EUNSUPPORTED, "contraction grid too large");
-  const int cols = 2 * (groups > 1 ? kMT * 16 : npairs);  // columns of the widest group
-  if (cols <= 32)
+  if (MT == 1)
     launch_mt<1>(a, src, groups, st);
+  else if (MT == 4)
+    launch_mt<4>(a, src, groups, st);
   else
     launch_mt<2>(a, src, groups, st);
   PAT_LAUNCHED("contraction (MFMA)");
