@@ -20,6 +20,9 @@ TINY = Geometry.paper_like(32, 32, 16, 64)                       # radial fold
 RAGGED = Geometry(32, 16, 13, 37, 1e-4, 1.3e-4, 1e-4, 2e-8, 1500.0)  # quadrant fold, ragged
 MID = Geometry.paper_like(64, 64, 40, 130)                       # several tiles per row
 GEOMS = {"tiny": TINY, "ragged": RAGGED, "mid": MID}
+# depth and time axes that are multiples of 32: both products of the batched
+# float32 path take the branch-free operand loads (K a multiple of 16, N of 32)
+EXTRA = {"square": Geometry.paper_like(32, 32, 32, 64)}
 
 
 def og(g: Geometry) -> OGeom:
@@ -44,7 +47,7 @@ _cache = {}
 def setup(name, h_dtype="f32"):
     key = (name, h_dtype)
     if key not in _cache:
-        g = GEOMS[name]
+        g = GEOMS[name] if name in GEOMS else EXTRA[name]
         Hh = hlib.H_half(og(g))
         _cache[key] = (g, Operator(g, h_dtype), Hh)
     return _cache[key]
@@ -374,14 +377,17 @@ def test_quantised_batched_matrix_core_path(kind, name, B):
     assert op.adjoint_check(dev(xs[0]), dev(ds[0])) < 1e-5
 
 
-@pytest.mark.parametrize("name,B", [("tiny", 16), ("ragged", 4), ("mid", 5), ("ragged", 2), ("tiny", 9), ("mid", 11)])
+@pytest.mark.parametrize("name,B", [("tiny", 16), ("ragged", 4), ("mid", 5), ("ragged", 2), ("tiny", 9), ("mid", 11),
+                                    ("tiny", 5), ("square", 3), ("square", 8), ("square", 13)])
 def test_float32_batched_path(name, B):
     # float32 batches run on the matrix cores (library rows split into three
     # bf16 terms, spectra into two): every object matches the oracle to the
     # float32 bar, and its own single-object apply (the VALU kernel) to 1e-5;
     # the ragged shapes (13 and 37 along k) end in a partial k-step, the mid
-    # one spans two k-chunks for A^T; 9 and 11 objects (72 and 88 member-object
-    # pairs) need a second, partial column group of 64 pairs
+    # one spans two k-chunks for A^T; 9, 11 and 13 objects (72, 88 and 104
+    # member-object pairs) need a second, partial column group of 64 pairs,
+    # 3 and 5 objects (24 and 40 pairs) one group of 32 pairs; the square
+    # shape takes the branch-free operand loads for A and A^T (tiny for A)
     g, op, Hh = setup(name)
     xs = np.stack([inputs.gaussian_blobs((g.nz, g.ny, g.nx), seed=500 + b) for b in range(B)])
     ds = np.stack([inputs.gaussian_random((g.nt, g.ny, g.nx), seed=600 + b) for b in range(B)])
