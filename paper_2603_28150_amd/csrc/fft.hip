@@ -101,13 +101,6 @@ __device__ __forceinline__ void row_block(int tj, int& j, int& sb) {
 // 128-byte line (8 or 4 slices ran the 512- to 1024-point passes 1.3-1.7x
 // slower); up to 16 * 32 threads and 147 KB of LDS at 1024 points
 template <int N> struct ColSB { static constexpr int value = 16; };
-// The exchange between the two DFT stages goes through LDS in this many
-// rounds of SB / phases slices: at 256 points one round for all 16 slices
-// needs 37 KB of LDS and four workgroups per CU, and a 256-point pass over
-// 512 slices (4,128 workgroups) then takes five rounds of workgroups for
-// 4.03 rounds of work; in two rounds of 8 slices (20.5 KB) seven workgroups
-// share a CU and the same pass takes three
-template <int N> struct ColPhases { static constexpr int value = N == 256 ? 2 : 1; };
 
 template <int N, int DIR>
 __global__ __launch_bounds__(512) void k_fft_cols(const float2* __restrict__ in,
@@ -119,11 +112,8 @@ __global__ __launch_bounds__(512) void k_fft_cols(const float2* __restrict__ in,
   constexpr int SB = ColSB<N>::value;
   constexpr int PAD = N + 1;   // LDS stride per slice (complex)
   constexpr int NT = SB * N1;  // threads
-  constexpr int PH = ColPhases<N>::value;
-  constexpr int SBP = SB / PH;  // slices per exchange round
-  static_assert(SB % PH == 0, "whole slices per exchange round");
   __shared__ float2 tw[N];
-  __shared__ float2 ex[SBP * PAD];
+  __shared__ float2 ex[SB * PAD];
   __shared__ int rin[N], rout[N];
   const int tid = threadIdx.x;
   const int s = tid % SB, t = tid / SB;
@@ -140,33 +130,21 @@ __global__ __launch_bounds__(512) void k_fft_cols(const float2* __restrict__ in,
     rout[y] = !ov ? -1 : omap ? omap[y * nh + m] : (y / ostride) * nh + m;
   }
   __syncthreads();
-  float2 w[N1];
   if (t < N2) {
+    float2 v[N1];
 #pragma unroll
     for (int n1 = 0; n1 < N1; ++n1) {
       const int y = t + N2 * n1;
-      w[n1] = (live && rin[y] >= 0) ? in[(size_t)rin[y] * rs + sg] : make_float2(0.f, 0.f);
+      v[n1] = (live && rin[y] >= 0) ? in[(size_t)rin[y] * rs + sg] : make_float2(0.f, 0.f);
     }
-    dft<N1, DIR>(w);
+    dft<N1, DIR>(v);
 #pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) w[k1] = cmul(w[k1], tw[t * k1]);
+    for (int k1 = 0; k1 < N1; ++k1) ex[s * PAD + t * N1 + k1] = cmul(v[k1], tw[t * k1]);
   }
+  __syncthreads();
   float2 v[N2];
 #pragma unroll
-  for (int ph = 0; ph < PH; ++ph) {
-    if (ph > 0) __syncthreads();  // the previous round's reads are done
-    const bool mine = s / SBP == ph;
-    const int sl = s % SBP;
-    if (mine && t < N2) {
-#pragma unroll
-      for (int k1 = 0; k1 < N1; ++k1) ex[sl * PAD + t * N1 + k1] = w[k1];
-    }
-    __syncthreads();
-    if (mine) {
-#pragma unroll
-      for (int n2 = 0; n2 < N2; ++n2) v[n2] = ex[sl * PAD + n2 * N1 + t];
-    }
-  }
+  for (int n2 = 0; n2 < N2; ++n2) v[n2] = ex[s * PAD + n2 * N1 + t];
   dft<N2, DIR>(v);
   if (live) {
 #pragma unroll
