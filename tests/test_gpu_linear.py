@@ -114,6 +114,29 @@ def test_linear_batch_equals_single_objects():
         assert rel(ys[b], ops.A_linear(Hh2, xs[b])) < 1e-5
 
 
+def test_wide_transforms_match_narrow_ones_bit_for_bit():
+    # 2,112 slices on the 202 x 202 window (432^2 transforms): the row passes
+    # take their workgroups in tiles of 4 rows (202 rows: a partial last
+    # tile) and the column passes slice blocks fastest; every slice's spectrum
+    # is the one a call on 640 of the slices computes (row-major order),
+    # bit for bit, and the inverse returns the slices
+    g = LINEAR["wire202"]
+    op = Operator(g, "f32")
+    S, Sn = 2112, 640
+    x = dev(inputs.gaussian_random((S, g.ny, g.nx), seed=821))
+    B_ws = -(-S // g.nt)
+    wide = op.spectrum_buffer(S)
+    op.spectrum(x, S, wide, B_ws=B_ws)
+    narrow = op.spectrum_buffer(Sn)
+    used = torch.tensor([r for r, k in enumerate(op.spectrum_rows()) if k >= 0], device="cuda")
+    for s0 in (0, S - Sn):
+        op.spectrum(x[s0:s0 + Sn].contiguous(), Sn, narrow, B_ws=B_ws)
+        assert torch.equal(wide[used, s0:s0 + Sn], narrow[used, :Sn]), s0
+    back = torch.empty_like(x)
+    op.inverse_spectrum(wide, S, back, B_ws=B_ws)
+    assert rel(host(back), host(x)) < 1e-6
+
+
 @pytest.mark.parametrize("kind", ["bf16", "f16"])
 def test_linear_16bit_library(kind):
     g, op, Hh2 = linear_setup("tiny", kind)
