@@ -271,8 +271,10 @@ __global__ __launch_bounds__(kWaves * 64, MT >= 4 ? 2 : kMinBlocks) void k_contr
     Frag fr[KB];
     u32x4 raw[KB][2];
   };
-  // Issues the loads of batch (tile, chunk ch, first k-step s0) of this wave;
-  // a tile past the end loads nothing (zeros).
+  // Issues the loads of batch (tile, chunk ch, first k-step s0) of this wave.
+  // K-steps out of range (and every k-step of a tile past the end) get zeros
+  // (16-bit tiles, unaligned rows) or row 0 (aligned rows); mma_batch skips
+  // them either way.
   auto load_batch = [&](BBatch& o, int tile, int ch, int s0) {
     const bool has = tile < a.ntiles;
     const int nks = min(kKC, a.ksteps - ch * kKC);
