@@ -480,14 +480,16 @@ static void launch_mt(const MfmaArgs& a, int src, int groups, hipStream_t st) {
   const size_t red = (size_t)kWaves * 16 * 64 * 4;  // k-part reduction buffer
   const size_t bytes = lds > red ? lds : red;
   dim3 grid((unsigned)(((long long)a.nitem * groups + 7) / 8 * 8));
-  if (src == kSrcF16)
-    k_contract_mfma<kSrcF16, MT, false><<<grid, kWaves * 64, bytes, st>>>(a, groups);
-  else if (src == kSrcF32 && a.K % 16 == 0 && a.N % 32 == 0)
+  if (src == kSrcF32 && a.K % 16 == 0 && a.N % 32 == 0)
     k_contract_mfma<kSrcF32, MT, true><<<grid, kWaves * 64, bytes, st>>>(a, groups);
   else if (src == kSrcF32)
     k_contract_mfma<kSrcF32, MT, false><<<grid, kWaves * 64, bytes, st>>>(a, groups);
-  else
-    k_contract_mfma<kSrcBf16, MT, false><<<grid, kWaves * 64, bytes, st>>>(a, groups);
+  else if constexpr (MT < 4) {  // 16-bit tiles take groups of up to 32 pairs
+    if (src == kSrcF16)
+      k_contract_mfma<kSrcF16, MT, false><<<grid, kWaves * 64, bytes, st>>>(a, groups);
+    else
+      k_contract_mfma<kSrcBf16, MT, false><<<grid, kWaves * 64, bytes, st>>>(a, groups);
+  }
 }
 
 pat_status contract_mfma(const MfmaArgs& a, int hdtype, hipStream_t st) {
