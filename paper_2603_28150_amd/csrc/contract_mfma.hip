@@ -23,7 +23,8 @@
 // rows that run along k (the [n][l] rows for A, the [l][n] rows for A^T):
 // each lane reads 8 consecutive floats and splits each into three bfloat16
 // terms, exact for float32 significands; with the hi + lo spectra that is
-// five MFMAs per step (the two smallest products dropped, 2^-26 relative).
+// five MFMAs per step: five of the six products, the one left out (lo times
+// the third term) below 2^-25 of the step's largest.
 //
 // Workgroups: the (item, column group) units are dealt to the XCDs in eight
 // contiguous ranges, so the column groups of one item, and the items a large
