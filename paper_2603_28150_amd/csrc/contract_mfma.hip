@@ -19,12 +19,19 @@
 // Output columns come out of the accumulators as (re, im) pairs along the
 // slab's output index: 256-byte contiguous stores.
 //
-// Float32 libraries (batches of objects) take the B operand from the stored
-// rows that run along k (the [n][l] rows for A, the [l][n] rows for A^T):
-// each lane reads 8 consecutive floats and splits each into three bfloat16
-// terms, exact for float32 significands; with the hi + lo spectra that is
-// five MFMAs per step: five of the six products, the one left out (lo times
-// the third term) below 2^-25 of the step's largest.
+// Float32 libraries (batches of objects) run on v_mfma_f32_32x32x16_f16
+// instead.  The B operand comes from the stored rows that run along k (the
+// [n][l] rows for A, the [l][n] rows for A^T): each lane reads 8 consecutive
+// floats, scales them by its row's power of two (computed with the library,
+// so that the row's largest magnitude lies in [2^14, 2^15)) and splits each
+// into two float16 terms, h = h1 + h2 to 2^-22 relative.  The spectra are
+// staged as float16 hi + lo pairs in the same way, scaled by a power of two
+// per (member, object) pair: the smallest exponent over the k-chunks staged
+// so far, so no value overflows; when a later chunk lowers it, the pair's
+// accumulated sums are scaled down by the same power of two first (exact).
+// Three MFMAs per step: hi h1, hi h2 and lo h1; the product left out (lo
+// h2) is below 2^-22 of the step's largest.  Both scales come off in the
+// epilogue (exact powers of two).
 //
 // Workgroups: the (item, column group) units are dealt to the XCDs in eight
 // contiguous ranges, so the column groups of one item, and the items a large
@@ -36,6 +43,8 @@ namespace pat {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
@@ -64,24 +73,34 @@ __device__ __forceinline__ void split2(float a, float b, unsigned& hi, unsigned&
 union Frag {
   u32x4 u;
   bf16x8 b;
+  f16x8 h;
   unsigned short s[8];
 };
 
+// (a, b) -> hi + lo float16 pairs (round to nearest even): a = hi.a + lo.a
+// to 2^-22 relative while |a| < 2^15 and hi.a is a normal number
+__device__ __forceinline__ void split2_f16(float a, float b, unsigned& hi, unsigned& lo) {
+  const f32x2 x = {a, b};
+  const f16x2 h = __builtin_convertvector(x, f16x2);
+  const f32x2 hf = __builtin_convertvector(h, f32x2);
+  const f16x2 l = __builtin_convertvector((f32x2){x[0] - hf[0], x[1] - hf[1]}, f16x2);
+  __builtin_memcpy(&hi, &h, 4);
+  __builtin_memcpy(&lo, &l, 4);
+}
+
 enum { kSrcBf16 = 0, kSrcF16 = 1, kSrcF32 = 2 };
 
-// 8 float32 values (two 16-byte units) -> three bfloat16 fragments whose sum
-// is exact (24 significant bits in three 8-bit pieces)
-__device__ __forceinline__ void split_f32(const u32x4 (&raw)[2], Frag& b1, Frag& b2, Frag& b3) {
+// 8 float32 values (two 16-byte units) times 2^e -> two float16 fragments,
+// h1 + h2 = h 2^e to 2^-22 relative
+__device__ __forceinline__ void split_f32(const u32x4 (&raw)[2], int e, Frag& b1, Frag& b2) {
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const float x0 = __uint_as_float(raw[j >> 1][2 * (j & 1)]);
-    const float x1 = __uint_as_float(raw[j >> 1][2 * (j & 1) + 1]);
-    const unsigned u1 = pk_bf16(x0, x1);
-    const float r0 = x0 - lo_f(u1), r1 = x1 - hi_f(u1);
-    const unsigned u2 = pk_bf16(r0, r1);
-    b1.u[j] = u1;
-    b2.u[j] = u2;
-    b3.u[j] = pk_bf16(r0 - lo_f(u2), r1 - hi_f(u2));
+    const float x0 = ldexpf(__uint_as_float(raw[j >> 1][2 * (j & 1)]), e);
+    const float x1 = ldexpf(__uint_as_float(raw[j >> 1][2 * (j & 1) + 1]), e);
+    unsigned h, l;
+    split2_f16(x0, x1, h, l);
+    b1.u[j] = h;
+    b2.u[j] = l;
   }
 }
 
@@ -126,10 +145,16 @@ __device__ __forceinline__ int a_unit(int ks, int idx) { return idx ^ ((2 * ks +
 // the first is used: one memory latency per chunk up to 32-pair groups, two
 // for 64-pair groups (whose four items would not fit the registers at once).
 // gmask: bit g set when member slot g of the item holds a frequency.
-// SCALED: the library has per-depth scales (16-bit).
-template <int MT, bool SCALED>
+// 16-bit libraries: bfloat16 terms, the spectra times the library's
+// per-depth scales when it has them.  Float32 libraries: float16 terms of
+// the spectra times 2^e, e per pair the running minimum over the chunks of
+// the tile (reset by `first`) of the exponent that takes the chunk's largest
+// magnitude of the pair into [2^14, 2^15); etab[pair] receives e and
+// etab[MT*16 + pair] the change of e from the last chunk (0 or negative).
+template <int MT, int SRC>
 __device__ __forceinline__ void stage_chunk(const MfmaArgs& a, u32x4* lds, int c, unsigned gmask, int p0,
-                                            int gp, int ch, int tid) {
+                                            int gp, int ch, int tid, int* etab, bool first) {
+  constexpr bool SCALED = SRC != kSrcF32;
   const int k0 = ch * kKC * 16;
   constexpr int items = MT * 16 * kKC * 2;  // pairs x k-octets
   constexpr int per_all = items / (kWaves * 64);  // items per thread
@@ -197,6 +222,28 @@ __device__ __forceinline__ void stage_chunk(const MfmaArgs& a, u32x4* lds, int c
           v[e].y *= sc;
         }
       }
+      if constexpr (SRC == kSrcF32) {
+        // the pair's largest magnitude in this chunk: its 16 k-octets are
+        // the items of 16 consecutive lanes (one round, aligned to 16)
+        float mx = 0.f;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) mx = fmaxf(mx, fmaxf(fabsf(v[e].x), fabsf(v[e].y)));
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+        int E;
+        (void)frexpf(mx, &E);  // mx < 2^E (E = 0 for zero)
+        const int eo = first ? 15 - E : etab[pl];
+        const int en = min(eo, 15 - E);
+        if ((tid & 15) == 0) {
+          etab[pl] = en;
+          etab[MT * 16 + pl] = en - eo;
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          v[e].x = ldexpf(v[e].x, en);
+          v[e].y = ldexpf(v[e].y, en);
+        }
+      }
       const int ks = ko >> 1, half = ko & 1;
 #pragma unroll
       for (int part = 0; part < 2; ++part) {
@@ -206,10 +253,12 @@ __device__ __forceinline__ void stage_chunk(const MfmaArgs& a, u32x4* lds, int c
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           unsigned h, l;
-          if (part)
-            split2(v[2 * j].y, v[2 * j + 1].y, h, l);
+          const float x0 = part ? v[2 * j].y : v[2 * j].x;
+          const float x1 = part ? v[2 * j + 1].y : v[2 * j + 1].x;
+          if constexpr (SRC == kSrcF32)
+            split2_f16(x0, x1, h, l);
           else
-            split2(v[2 * j].x, v[2 * j + 1].x, h, l);
+            split2(x0, x1, h, l);
           hi.u[j] = h;
           lo.u[j] = l;
         }
@@ -221,11 +270,23 @@ __device__ __forceinline__ void stage_chunk(const MfmaArgs& a, u32x4* lds, int c
   }  // rounds of items
 }
 
+// LDS: the staged chunk (or the k-part reduction buffer, whichever is
+// larger), then for float32 libraries the exponent table of stage_chunk
+template <int MT>
+constexpr size_t table_offset() {
+  constexpr size_t units = (size_t)kTerms * kKC * MT * 64 * 16;
+  constexpr size_t red = (size_t)kWaves * 16 * 64 * 4;
+  return units > red ? units : red;
+}
+template <int MT>
+constexpr size_t table_bytes() { return (size_t)2 * MT * 16 * sizeof(int); }
+
 // ALIGNED: K a multiple of 16 and N of 32 (float32 rows read without bounds
 // branches)
 template <int SRC, int MT, bool ALIGNED>
 __global__ __launch_bounds__(kWaves * 64, MT >= 4 ? 2 : kMinBlocks) void k_contract_mfma(MfmaArgs a, int groups) {
   extern __shared__ u32x4 lds[];  // [term][ks][mt][lane] 16-byte units
+  int* etab = reinterpret_cast<int*>(reinterpret_cast<char*>(lds) + table_offset<MT>());
   constexpr int KB = SRC == kSrcF32 ? kKC / 4 : kKC / 2;  // k-steps per batch of B loads
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
@@ -265,6 +326,7 @@ __global__ __launch_bounds__(kWaves * 64, MT >= 4 ? 2 : kMinBlocks) void k_contr
                                             (size_t)a.item_slab[c] * a.ntiles * a.ksteps * 64;
   const float* krow = SRC == kSrcF32 ? a.krows + (size_t)a.item_slab[c] * a.k_slab : nullptr;
   bool staged = false;  // LDS holds chunk 0 (kept only when there is one chunk)
+  int lsx = 0;  // float32: exponent of this lane's library row in the current tile
 
   // The B operands of one batch of KB k-steps (16-bit fragments, or float32
   // rows: 8 floats per lane and k-step).
@@ -353,18 +415,16 @@ __global__ __launch_bounds__(kWaves * 64, MT >= 4 ? 2 : kMinBlocks) void k_contr
           acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al.b, hl.b, acc[m], 0, 0, 0);
         }
       } else {
-        Frag b1, b2, b3;
-        split_f32(o.raw[s], b1, b2, b3);
+        Frag b1, b2;
+        split_f32(o.raw[s], lsx, b1, b2);
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
           Frag ah, al;
           ah.u = lds[(ks * MT + m) * 64 + a_unit(ks, lane)];
           al.u = lds[(kKC * MT + ks * MT + m) * 64 + a_unit(ks, lane)];
-          acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah.b, b1.b, acc[m], 0, 0, 0);
-          acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah.b, b2.b, acc[m], 0, 0, 0);
-          acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al.b, b1.b, acc[m], 0, 0, 0);
-          acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah.b, b3.b, acc[m], 0, 0, 0);
-          acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al.b, b2.b, acc[m], 0, 0, 0);
+          acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah.h, b1.h, acc[m], 0, 0, 0);
+          acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah.h, b2.h, acc[m], 0, 0, 0);
+          acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_f16(al.h, b1.h, acc[m], 0, 0, 0);
         }
       }
     }
@@ -386,6 +446,7 @@ __global__ __launch_bounds__(kWaves * 64, MT >= 4 ? 2 : kMinBlocks) void k_contr
     // output row of this lane and its scale, read before the tile's loads
     const int row = tile * 32 + (lane & 31);
     const float sc = SRC != kSrcF32 && a.out_scale && has && row < a.N ? a.out_scale[row] : 1.f;
+    if constexpr (SRC == kSrcF32) lsx = has && row < a.N ? a.kexp[(size_t)a.item_slab[c] * a.N + row] : 0;
     f32x16 acc[MT];
 #pragma unroll
     for (int m = 0; m < MT; ++m) acc[m] = f32x16(0.f);
@@ -393,9 +454,24 @@ __global__ __launch_bounds__(kWaves * 64, MT >= 4 ? 2 : kMinBlocks) void k_contr
     for (int ch = 0; ch < nchunks; ++ch) {
       if (!(staged && nchunks == 1)) {
         lds_barrier();
-        stage_chunk<MT, SRC != kSrcF32>(a, lds, c, gmask, p0, gp, ch, tid);
+        stage_chunk<MT, SRC>(a, lds, c, gmask, p0, gp, ch, tid, etab, ch == 0);
         lds_barrier();
         staged = true;
+      }
+      if (SRC == kSrcF32 && ch > 0) {
+        // a pair whose exponent this chunk lowered: its sums so far times
+        // the same power of two (accumulator row i of tile m is column
+        // 32 m + i, pair 16 m + i/2; lane half h holds rows 8 q + 4 h + 0..3)
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int2 d = *reinterpret_cast<const int2*>(etab + MT * 16 + m * 16 + 4 * q + 2 * (lane >> 5));
+            acc[m][4 * q] = ldexpf(acc[m][4 * q], d.x);
+            acc[m][4 * q + 1] = ldexpf(acc[m][4 * q + 1], d.x);
+            acc[m][4 * q + 2] = ldexpf(acc[m][4 * q + 2], d.y);
+            acc[m][4 * q + 3] = ldexpf(acc[m][4 * q + 3], d.y);
+          }
       }
       if constexpr (!kPipe) {
 #pragma unroll 1
@@ -441,14 +517,26 @@ __global__ __launch_bounds__(kWaves * 64, MT >= 4 ? 2 : kMinBlocks) void k_contr
       }
     }
 
-    // per-row output scale (1 when there is none), applied here on
-    // straight-line code (the empty asm keeps the compiler from sinking the
-    // products into the conditional stores below, where each store would
-    // first wait for the scale's load and so for every earlier store)
+    // per-row output scale (1 when there is none; float32: 2^-(pair's
+    // exponent + library row's exponent)), applied here on straight-line
+    // code (the empty asm keeps the compiler from sinking the products into
+    // the conditional stores below, where each store would first wait for
+    // the scale's load and so for every earlier store)
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
+      if constexpr (SRC == kSrcF32) {
 #pragma unroll
-      for (int v = 0; v < 16; ++v) acc[m][v] *= sc;
+        for (int q = 0; q < 4; ++q) {
+          const int2 e = *reinterpret_cast<const int2*>(etab + m * 16 + 4 * q + 2 * (lane >> 5));
+          acc[m][4 * q] = ldexpf(acc[m][4 * q], -(e.x + lsx));
+          acc[m][4 * q + 1] = ldexpf(acc[m][4 * q + 1], -(e.x + lsx));
+          acc[m][4 * q + 2] = ldexpf(acc[m][4 * q + 2], -(e.y + lsx));
+          acc[m][4 * q + 3] = ldexpf(acc[m][4 * q + 3], -(e.y + lsx));
+        }
+      } else {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[m][v] *= sc;
+      }
       asm volatile("" : "+v"(acc[m]));
     }
 
@@ -477,9 +565,7 @@ __global__ __launch_bounds__(kWaves * 64, MT >= 4 ? 2 : kMinBlocks) void k_contr
 
 template <int MT>
 static void launch_mt(const MfmaArgs& a, int src, int groups, hipStream_t st) {
-  const size_t lds = (size_t)kTerms * kKC * MT * 64 * 16;
-  const size_t red = (size_t)kWaves * 16 * 64 * 4;  // k-part reduction buffer
-  const size_t bytes = lds > red ? lds : red;
+  const size_t bytes = table_offset<MT>() + (src == kSrcF32 ? table_bytes<MT>() : 0);
   dim3 grid((unsigned)(((long long)a.nitem * groups + 7) / 8 * 8));
   if (src == kSrcF32 && a.K % 16 == 0 && a.N % 32 == 0)
     k_contract_mfma<kSrcF32, MT, true><<<grid, kWaves * 64, bytes, st>>>(a, groups);
@@ -493,10 +579,39 @@ static void launch_mt(const MfmaArgs& a, int src, int groups, hipStream_t st) {
   }
 }
 
+// one wave per row: the row's largest magnitude m, then e = 15 - E with
+// m = f 2^E, 1/2 <= f < 1 (E = 0 when m is zero)
+__global__ __launch_bounds__(256) void k_row_exp(const float* rows, long long nrows, int K, int srow, int32_t* ex) {
+  const long long r = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= nrows) return;  // whole wave
+  const int lane = threadIdx.x & 63;
+  const float* p = rows + r * srow;
+  float mx = 0.f;
+  for (int k = lane; k < K; k += 64) mx = fmaxf(mx, fabsf(p[k]));
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+  if (lane == 0) {
+    int E;
+    (void)frexpf(mx, &E);
+    ex[r] = 15 - E;
+  }
+}
+
+pat_status row_exponents(const float* rows, long long nrows, int K, int srow, int32_t* ex, hipStream_t st) {
+  if (nrows == 0) return PAT_OK;
+  if (!rows || !ex || K < 0 || srow < K) return fail(PAT_EINVAL, "row exponents: bad rows");
+  const long long blocks = (nrows + 3) / 4;
+  if (blocks > 0x7fffffffLL) return fail(PAT_EUNSUPPORTED, "row exponents: too many rows");
+  k_row_exp<<<dim3((unsigned)blocks), 256, 0, st>>>(rows, nrows, K, srow, ex);
+  PAT_LAUNCHED("row exponents");
+  return PAT_OK;
+}
+
 pat_status contract_mfma(const MfmaArgs& a, int hdtype, hipStream_t st) {
   if (a.nitem == 0 || a.B == 0) return PAT_OK;
   const int src = hdtype == PAT_H_F16 ? kSrcF16 : hdtype == PAT_H_F32 ? kSrcF32 : kSrcBf16;
-  if (src == kSrcF32 && !a.krows) return fail(PAT_EINVAL, "float32 contraction on the matrix cores needs the k rows");
+  if (src == kSrcF32 && (!a.krows || !a.kexp))
+    return fail(PAT_EINVAL, "float32 contraction on the matrix cores needs the k rows and their exponents");
   if (src != kSrcF32 && !a.frag) return fail(PAT_EINVAL, "16-bit contraction needs the operand tiles");
   if (a.G < 1 || a.G > 8) return fail(PAT_EINVAL, "work items hold 1 to 8 member slots");
   const int npairs = a.G * a.B;

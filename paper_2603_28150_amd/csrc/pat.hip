@@ -43,6 +43,8 @@ struct pat_op {
   void* rowA;         // [nclass][nz][sA_row] rows of the storage type (= slabA for FP32)
   void* rowT;         // [nclass][nt][sT_row] rows of the storage type (= slabT for FP32)
   float* gram;        // [nclass][nz][sG_row]  Gram blocks of the library
+  int32_t* kexpA;     // FP32: [nclass][nt] exponent of each [n][l] row (A's k rows), else null
+  int32_t* kexpT;     // FP32: [nclass][nz] exponent of each [l][n] row (A^T's k rows), else null
   int sG_row;
   pat::FftChirp chirp;  // chirp-z tables of axes that are not fast FFT sizes
   std::vector<float2> h_cz;  // their host copy: c and the kernel DFT, x then y
@@ -306,8 +308,8 @@ static Classes make_classes(const pat_geometry& g) {
 struct HLayout {
   size_t off_cz, bytes_cz;
   size_t off_members, off_items, off_kclass, off_rowmap, off_freq, off_inv, off_amax, off_ir, off_A,
-      off_T, off_Ar, off_Tr, off_G, total;
-  size_t bytes_A, bytes_T, bytes_Ar, bytes_Tr, bytes_G;
+      off_T, off_Ar, off_Tr, off_G, off_X, total;
+  size_t bytes_A, bytes_T, bytes_Ar, bytes_Tr, bytes_G, bytes_X;
   int sG_row;
   int nclass, nitem, G, vec, sA_row, sT_row;
   int ntA, ksA, ntT, ksT;
@@ -363,6 +365,11 @@ static HLayout h_layout(const pat_geometry& g, const Classes& C) {
   L.off_A = o;       o = align_up(o + L.bytes_A, 256);
   L.off_T = o;       o = align_up(o + L.bytes_T, 256);
   L.off_G = o;       o = align_up(o + L.bytes_G, 256);
+  // float32 libraries: the power-of-two exponent of every k row of both
+  // layouts ([n][l] rows for A, [l][n] rows for A^T), for the batched
+  // contraction's float16 terms
+  L.bytes_X = g.h_dtype == PAT_H_F32 ? (size_t)L.nclass * (g.nt + g.nz) * 4 : 0;
+  L.off_X = o;       o = align_up(o + L.bytes_X, 256);
   L.total = o;
   return L;
 }
@@ -460,13 +467,15 @@ static pat_status run_contract(pat_op* op, bool adjoint, const float2* in, float
   const float* sc = g.h_dtype == PAT_H_F32 ? nullptr : op->inv_scale;
   // one object: the VALU kernel on the row layouts streams the library at
   // the FP32 kernel's rate; batches go to the matrix cores (one slab read
-  // serves every object; FP32 values enter as three bf16 terms)
+  // serves every object; FP32 values enter as two float16 terms, scaled by
+  // a power of two per row)
   const bool f32 = g.h_dtype == PAT_H_F32;
   if (B > 1) {
     MfmaArgs m;
     m.krows = nullptr;
     m.k_srow = 0;
     m.k_slab = 0;
+    m.kexp = nullptr;
     m.frag = nullptr;
     m.members = op->members;
     m.item_slab = op->item_slab;
@@ -480,6 +489,7 @@ static pat_status run_contract(pat_op* op, bool adjoint, const float2* in, float
         m.krows = static_cast<const float*>(op->rowT);  // [n][l]: runs along k = l
         m.k_srow = op->sT_row;
         m.k_slab = (long long)g.nt * op->sT_row;
+        m.kexp = op->kexpA;
       } else {
         m.frag = op->slabA;
       }
@@ -494,6 +504,7 @@ static pat_status run_contract(pat_op* op, bool adjoint, const float2* in, float
         m.krows = static_cast<const float*>(op->rowA);  // [l][n]: runs along k = n
         m.k_srow = op->sA_row;
         m.k_slab = (long long)g.nz * op->sA_row;
+        m.kexp = op->kexpT;
       } else {
         m.frag = op->slabT;
       }
@@ -728,6 +739,8 @@ pat_status pat_H_build(pat_ctx* ctx, const pat_geometry* geom, void* h_buf, size
   op->slabA = f32 ? op->rowA : op->hbuf + L.off_A;
   op->slabT = f32 ? op->rowT : op->hbuf + L.off_T;
   op->gram = L.bytes_G ? (float*)(op->hbuf + L.off_G) : nullptr;
+  op->kexpA = L.bytes_X ? (int32_t*)(op->hbuf + L.off_X) : nullptr;
+  op->kexpT = L.bytes_X ? op->kexpA + (size_t)L.nclass * geom->nt : nullptr;
   op->sG_row = L.sG_row;
   op->h_members = std::move(C.members);
   op->h_kclass = std::move(C.kclass);
@@ -814,6 +827,14 @@ pat_status pat_H_build(pat_ctx* ctx, const pat_geometry* geom, void* h_buf, size
   a.ptab_bytes = geom->build == PAT_BUILD_STEP ? scratch_bytes : 0;
   a.c0 = 0;
   if ((s = hbuild(a, st)) != PAT_OK) return bail(s);
+  if (f32) {
+    if ((s = row_exponents(static_cast<const float*>(op->rowT), (long long)op->nclass * geom->nt, geom->nz,
+                           op->sT_row, op->kexpA, st)) != PAT_OK)
+      return bail(s);
+    if ((s = row_exponents(static_cast<const float*>(op->rowA), (long long)op->nclass * geom->nz, geom->nt,
+                           op->sA_row, op->kexpT, st)) != PAT_OK)
+      return bail(s);
+  }
   GramArgs ga;
   ga.slabA = op->slabA;
   ga.inv_scale = op->inv_scale;

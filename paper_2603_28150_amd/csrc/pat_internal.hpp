@@ -106,8 +106,13 @@ struct MfmaArgs {
   const float* krows;        // float32 libraries: [nslab][N][k_srow] rows along k (else null)
   int k_srow;
   long long k_slab;          // N * k_srow
+  const int32_t* kexp;       // float32 libraries: [nslab][N] exponent e of each k row, max |row| 2^e < 2^15
 };
 pat_status contract_mfma(const MfmaArgs& a, int hdtype, hipStream_t st);
+// exponent e of each of nrows rows of K floats (row stride srow): the power
+// of two that takes the row's largest magnitude m to m 2^e in [2^14, 2^15)
+// (0 for all-zero rows)
+pat_status row_exponents(const float* rows, long long nrows, int K, int srow, int32_t* ex, hipStream_t st);
 
 // ------------------------------------------------------------- H^ build
 struct HBuildArgs {

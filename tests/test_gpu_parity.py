@@ -22,7 +22,9 @@ MID = Geometry.paper_like(64, 64, 40, 130)                       # several tiles
 GEOMS = {"tiny": TINY, "ragged": RAGGED, "mid": MID}
 # depth and time axes that are multiples of 32: both products of the batched
 # float32 path take the branch-free operand loads (K a multiple of 16, N of 32)
-EXTRA = {"square": Geometry.paper_like(32, 32, 32, 64)}
+EXTRA = {"square": Geometry.paper_like(32, 32, 32, 64),
+         # A^T's k axis (time) over three chunks of 128, the last partial
+         "long": Geometry.paper_like(32, 32, 32, 320)}
 
 
 def og(g: Geometry) -> OGeom:
@@ -380,8 +382,9 @@ def test_quantised_batched_matrix_core_path(kind, name, B):
 @pytest.mark.parametrize("name,B", [("tiny", 16), ("ragged", 4), ("mid", 5), ("ragged", 2), ("tiny", 9), ("mid", 11),
                                     ("tiny", 5), ("square", 3), ("square", 8), ("square", 13)])
 def test_float32_batched_path(name, B):
-    # float32 batches run on the matrix cores (library rows split into three
-    # bf16 terms, spectra into two): every object matches the oracle to the
+    # float32 batches run on the matrix cores (library rows and spectra each
+    # split into two float16 terms under power-of-two scales): every object
+    # matches the oracle to the
     # float32 bar, and its own single-object apply (the VALU kernel) to 1e-5;
     # the ragged shapes (13 and 37 along k) end in a partial k-step, the mid
     # one spans two k-chunks for A^T; 9, 11 and 13 objects (72, 88 and 104
@@ -401,6 +404,29 @@ def test_float32_batched_path(name, B):
     for b in (0, B - 1):
         assert rel(ys[b], host(op.apply_A(dev(xs[b])))) < 1e-5
         assert rel(gs[b], host(op.apply_AT(dev(ds[b])))) < 1e-5
+
+
+@pytest.mark.parametrize("name,B", [("long", 5), ("long", 9), ("mid", 5), ("mid", 9)])
+def test_float32_batched_path_scales(name, B):
+    # the float16 terms of the batched float32 path carry a power of two per
+    # (member, object) pair and per library row: objects 2^-40 to 2^40 in
+    # one batch each keep the float32 bar, and data that grow (or shrink)
+    # by 2^30 along time, or start with all-zero chunks, make later k-chunks
+    # lower a pair's exponent, which rescales its partial sums of A^T;
+    # 5 objects take 40-pair column groups, 9 objects 64-pair groups; the long
+    # shape takes the branch-free operand loads, the mid one the bounded ones
+    g, op, Hh = setup(name)
+    e = [(-40, -20, 0, 20, 40)[b % 5] for b in range(B)]
+    xs = np.stack([inputs.gaussian_blobs((g.nz, g.ny, g.nx), seed=700 + b) * 2.0 ** e[b] for b in range(B)])
+    t = np.arange(g.nt, dtype=np.float64) / g.nt
+    shapes = [2.0 ** (30 * t), 2.0 ** (-30 * t), (t >= 0.5).astype(np.float64), np.ones_like(t)]
+    ds = np.stack([inputs.gaussian_random((g.nt, g.ny, g.nx), seed=800 + b) * shapes[b % 4][:, None, None]
+                   * 2.0 ** e[b] for b in range(B)])
+    ys, gs = host(op.apply_A(dev(xs))), host(op.apply_AT(dev(ds)))
+    for b in range(B):
+        assert rel(ys[b], ops.A_fft(Hh, xs[b])) < 1e-5, b
+        assert rel(gs[b], ops.AT_fft(Hh, ds[b])) < 1e-5, b
+        assert np.isfinite(ys[b]).all() and np.isfinite(gs[b]).all()
 
 
 @pytest.mark.parametrize("name,kind", [("ragged", "f32"), ("mid", "f32"), ("tiny", "bf16"), ("tiny", "f16")])
