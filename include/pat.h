@@ -247,10 +247,11 @@ pat_status pat_apply_AT(pat_op* op, const float* y, float* x, int32_t B,
  * pat_contract (step (ii)): adjoint == 0: out[k][b*nt+n] = sum_l H^[k,l,n] in[k][b*nz+l];
  * adjoint != 0: out[k][b*nz+l] = sum_n conj(H^[k,l,n]) in[k][b*nt+n]; rows of
  * in and out have the strides of B*nz and B*nt slices; no workspace.  B = 1
- * runs on the vector units in float32; B >= 2 on the matrix cores, with the
- * spectra entering as bfloat16 hi + lo pairs (2^-17 relative) and float32
- * library values as three bfloat16 terms (exact), accumulated in float32:
- * an object's result in a batch agrees with its B = 1 result to about 1e-6
+ * runs on the vector units in float32; B >= 2 on the matrix cores, accumulated
+ * in float32: with a float32 library the spectra and library values enter as
+ * pairs of float16 terms under power-of-two scales (2^-22 relative), with a
+ * 16-bit library the spectra as bfloat16 hi + lo pairs (2^-17 relative); an
+ * object's result in a batch agrees with its B = 1 result to about 1e-6
  * relative (l2), not bit for bit. */
 pat_status pat_spectrum(pat_op* op, const float* f, float* spec, int32_t S, void* ws,
                         size_t ws_bytes, void* stream);

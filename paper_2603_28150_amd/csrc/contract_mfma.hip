@@ -616,7 +616,7 @@ pat_status contract_mfma(const MfmaArgs& a, int hdtype, hipStream_t st) {
   if (a.G < 1 || a.G > 8) return fail(PAT_EINVAL, "work items hold 1 to 8 member slots");
   const int npairs = a.G * a.B;
   // column groups of 64 pairs for float32 rows (every group splits the
-  // slab's values into bf16 terms and reads the slab once: half as often as
+  // slab's values into float16 terms and reads the slab once: half as often as
   // with 32-pair groups; measured 8-10 % faster at B = 16), 32 for 16-bit
   // tiles (64 measured 1-3 % slower), 16 when there are no more pairs
   const int MT = npairs <= 16 ? 1 : src == kSrcF32 && npairs >= 64 ? 4 : 2;

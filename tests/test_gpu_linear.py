@@ -109,7 +109,7 @@ def test_linear_batch_equals_single_objects():
     xs = np.stack([inputs.gaussian_random((g.nz, g.ny, g.nx), seed=810 + b) for b in range(3)])
     ys = host(op.apply_A(dev(xs)))
     for b in range(3):
-        # a batch runs on the matrix cores (spectra split to 2^-17 relative)
+        # a batch runs on the matrix cores (float16 terms, 2^-22 relative)
         assert rel(ys[b], host(op.apply_A(dev(xs[b])))) < 1e-5
         assert rel(ys[b], ops.A_linear(Hh2, xs[b])) < 1e-5
 
