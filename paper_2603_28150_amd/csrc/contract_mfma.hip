@@ -144,7 +144,8 @@ __device__ __forceinline__ int a_unit(int ks, int idx) { return idx ^ ((2 * ks +
 // of two, every load of a round (and of its per-depth scales) issued before
 // the first is used: one memory latency per chunk up to 32-pair groups, two
 // for 64-pair groups (whose four items would not fit the registers at once).
-// gmask: bit g set when member slot g of the item holds a frequency.
+// in_off[pl]: offset of pair pl's spectrum row in a.in (float2 units), -1
+// for a pair outside the group or in an empty member slot (staged as zeros).
 // 16-bit libraries: bfloat16 terms, the spectra times the library's
 // per-depth scales when it has them.  Float32 libraries: float16 terms of
 // the spectra times 2^e, e per pair the running minimum over the chunks of
@@ -152,8 +153,8 @@ __device__ __forceinline__ int a_unit(int ks, int idx) { return idx ^ ((2 * ks +
 // magnitude of the pair into [2^14, 2^15); etab[pair] receives e and
 // etab[MT*16 + pair] the change of e from the last chunk (0 or negative).
 template <int MT, int SRC>
-__device__ __forceinline__ void stage_chunk(const MfmaArgs& a, u32x4* lds, int c, unsigned gmask, int p0,
-                                            int gp, int ch, int tid, int* etab, bool first) {
+__device__ __forceinline__ void stage_chunk(const MfmaArgs& a, u32x4* lds, const long long* in_off, int ch,
+                                            int tid, int* etab, bool first) {
   constexpr bool SCALED = SRC != kSrcF32;
   const int k0 = ch * kKC * 16;
   constexpr int items = MT * 16 * kKC * 2;  // pairs x k-octets
@@ -172,11 +173,9 @@ __device__ __forceinline__ void stage_chunk(const MfmaArgs& a, u32x4* lds, int c
 #pragma unroll
       for (int e = 0; e < 4; ++e) q[r][e] = make_float4(0.f, 0.f, 0.f, 0.f);
       if constexpr (SCALED) sq[r][0] = sq[r][1] = make_float4(1.f, 1.f, 1.f, 1.f);
-      if (pl >= gp) continue;
-      const int pair = p0 + pl;
-      const int g = pair / a.B, b = pair % a.B;
-      if (!((gmask >> g) & 1u)) continue;
-      const float2* src = a.in + (size_t)(c * a.G + g) * a.in_rs + (size_t)b * a.K;
+      const long long off = in_off[pl];
+      if (off < 0) continue;
+      const float2* src = a.in + off;
       if (kb + 8 <= a.K) {  // 64 aligned bytes
         const float4* s4 = reinterpret_cast<const float4*>(src + kb);
 #pragma unroll
@@ -271,22 +270,27 @@ __device__ __forceinline__ void stage_chunk(const MfmaArgs& a, u32x4* lds, int c
 }
 
 // LDS: the staged chunk (or the k-part reduction buffer, whichever is
-// larger), then for float32 libraries the exponent table of stage_chunk
+// larger)
 template <int MT>
 constexpr size_t table_offset() {
   constexpr size_t units = (size_t)kTerms * kKC * MT * 64 * 16;
   constexpr size_t red = (size_t)kWaves * 16 * 64 * 4;
   return units > red ? units : red;
 }
+// then the pair offset tables (input rows, output rows: 64-bit, -1 for no
+// pair), then for float32 libraries the exponent table of stage_chunk
 template <int MT>
-constexpr size_t table_bytes() { return (size_t)2 * MT * 16 * sizeof(int); }
+constexpr size_t offs_bytes() { return (size_t)2 * MT * 16 * sizeof(long long); }
+template <int MT>
+constexpr size_t etab_bytes() { return (size_t)2 * MT * 16 * sizeof(int); }
 
 // ALIGNED: K a multiple of 16 and N of 32 (float32 rows read without bounds
 // branches)
 template <int SRC, int MT, bool ALIGNED>
 __global__ __launch_bounds__(kWaves * 64, MT >= 4 ? 2 : kMinBlocks) void k_contract_mfma(MfmaArgs a, int groups) {
   extern __shared__ u32x4 lds[];  // [term][ks][mt][lane] 16-byte units
-  int* etab = reinterpret_cast<int*>(reinterpret_cast<char*>(lds) + table_offset<MT>());
+  long long* offs = reinterpret_cast<long long*>(reinterpret_cast<char*>(lds) + table_offset<MT>());
+  int* etab = reinterpret_cast<int*>(reinterpret_cast<char*>(lds) + table_offset<MT>() + offs_bytes<MT>());
   constexpr int KB = SRC == kSrcF32 ? kKC / 4 : kKC / 2;  // k-steps per batch of B loads
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
@@ -303,9 +307,9 @@ __global__ __launch_bounds__(kWaves * 64, MT >= 4 ? 2 : kMinBlocks) void k_contr
     c = u / groups;
     cg = u - c * groups;
   }
-  // filled member slots of the item, in a register: the loops below test
-  // this mask instead of reading the member table between their stores
-  // (a load after a store waits for that store on the in-order counter)
+  // filled member slots of the item, read once here: the loops below read
+  // the LDS offset tables instead of the member table (a global load after
+  // a store waits for that store on the in-order counter; LDS reads do not)
   unsigned gmask = 0;
 #pragma unroll
   for (int g = 0; g < 8; ++g)
@@ -313,6 +317,21 @@ __global__ __launch_bounds__(kWaves * 64, MT >= 4 ? 2 : kMinBlocks) void k_contr
   const int npairs = a.G * a.B;
   const int p0 = cg * (MT * 16);
   const int gp = min(MT * 16, npairs - p0);  // pairs in this launch group
+  // row offsets of the group's pairs (one division per pair and workgroup,
+  // not one per load and store); read after the first staging barrier
+  if (tid < MT * 16) {
+    long long oi = -1, oo = -1;
+    if (tid < gp) {
+      const int pair = p0 + tid;
+      const int g = pair / a.B, b = pair % a.B;
+      if ((gmask >> g) & 1u) {
+        oi = (long long)(c * a.G + g) * a.in_rs + (long long)b * a.K;
+        oo = (long long)(c * a.G + g) * a.out_rs + (long long)b * a.N;
+      }
+    }
+    offs[tid] = oi;
+    offs[MT * 16 + tid] = oo;
+  }
   // waves -> (N-tile, k-part): a wave owns one N-tile per pass; when there
   // are fewer N-tiles than waves, waves sharing a tile split its k-steps
   int kparts = 1;
@@ -454,7 +473,7 @@ __global__ __launch_bounds__(kWaves * 64, MT >= 4 ? 2 : kMinBlocks) void k_contr
     for (int ch = 0; ch < nchunks; ++ch) {
       if (!(staged && nchunks == 1)) {
         lds_barrier();
-        stage_chunk<MT, SRC>(a, lds, c, gmask, p0, gp, ch, tid, etab, ch == 0);
+        stage_chunk<MT, SRC>(a, lds, offs, ch, tid, etab, ch == 0);
         lds_barrier();
         staged = true;
       }
@@ -541,22 +560,26 @@ __global__ __launch_bounds__(kWaves * 64, MT >= 4 ? 2 : kMinBlocks) void k_contr
     }
 
     // store (re, im) pairs along the output index
+    // (accumulator rows 8 q + 4 h + {0, 1} and {2, 3} of tile m: the re
+    // and im parts of pairs 16 m + 4 q + 2 h and the one after it)
     if (has && kpart == 0 && row < a.N) {
+      typedef float v2f __attribute__((ext_vector_type(2)));
+      typedef long long i64x2 __attribute__((ext_vector_type(2)));
 #pragma unroll
       for (int m = 0; m < MT; ++m) {
+        i64x2 o[4];
 #pragma unroll
-        for (int v = 0; v < 16; v += 2) {
-          const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);  // even: the re part
-          const int pl = (m * 32 + i) >> 1;
-          if (pl >= gp) continue;
-          const int pair = p0 + pl;
-          const int g = pair / a.B, b = pair % a.B;
-          if (!((gmask >> g) & 1u)) continue;
+        for (int q = 0; q < 4; ++q)
+          o[q] = *reinterpret_cast<const i64x2*>(offs + MT * 16 + m * 16 + 4 * q + 2 * (lane >> 5));
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
           // streamed out: not read again by this kernel
-          typedef float v2f __attribute__((ext_vector_type(2)));
-          __builtin_nontemporal_store(v2f{acc[m][v], acc[m][v + 1]},
-                                      reinterpret_cast<v2f*>(a.out + (size_t)(c * a.G + g) * a.out_rs +
-                                                             (size_t)b * a.N + row));
+          if (o[q][0] >= 0)
+            __builtin_nontemporal_store(v2f{acc[m][4 * q], acc[m][4 * q + 1]},
+                                        reinterpret_cast<v2f*>(a.out + o[q][0] + row));
+          if (o[q][1] >= 0)
+            __builtin_nontemporal_store(v2f{acc[m][4 * q + 2], acc[m][4 * q + 3]},
+                                        reinterpret_cast<v2f*>(a.out + o[q][1] + row));
         }
       }
     }
@@ -565,7 +588,7 @@ __global__ __launch_bounds__(kWaves * 64, MT >= 4 ? 2 : kMinBlocks) void k_contr
 
 template <int MT>
 static void launch_mt(const MfmaArgs& a, int src, int groups, hipStream_t st) {
-  const size_t bytes = table_offset<MT>() + (src == kSrcF32 ? table_bytes<MT>() : 0);
+  const size_t bytes = table_offset<MT>() + offs_bytes<MT>() + (src == kSrcF32 ? etab_bytes<MT>() : 0);
   dim3 grid((unsigned)(((long long)a.nitem * groups + 7) / 8 * 8));
   if (src == kSrcF32 && a.K % 16 == 0 && a.N % 32 == 0)
     k_contract_mfma<kSrcF32, MT, true><<<grid, kWaves * 64, bytes, st>>>(a, groups);
@@ -580,14 +603,22 @@ static void launch_mt(const MfmaArgs& a, int src, int groups, hipStream_t st) {
 }
 
 // one wave per row: the row's largest magnitude m, then e = 15 - E with
-// m = f 2^E, 1/2 <= f < 1 (E = 0 when m is zero)
+// m = f 2^E, 1/2 <= f < 1 (E = 0 when m is zero).  Rows start on 16-byte
+// boundaries and their stride is a multiple of 4 floats, so every 4-float
+// load that starts below K stays inside the row's stride.
 __global__ __launch_bounds__(256) void k_row_exp(const float* rows, long long nrows, int K, int srow, int32_t* ex) {
   const long long r = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (r >= nrows) return;  // whole wave
   const int lane = threadIdx.x & 63;
   const float* p = rows + r * srow;
   float mx = 0.f;
-  for (int k = lane; k < K; k += 64) mx = fmaxf(mx, fabsf(p[k]));
+  for (int k = 4 * lane; k < K; k += 256) {
+    const float4 v = *reinterpret_cast<const float4*>(p + k);
+    mx = fmaxf(mx, fabsf(v.x));
+    if (k + 1 < K) mx = fmaxf(mx, fabsf(v.y));
+    if (k + 2 < K) mx = fmaxf(mx, fabsf(v.z));
+    if (k + 3 < K) mx = fmaxf(mx, fabsf(v.w));
+  }
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
   if (lane == 0) {
@@ -599,7 +630,8 @@ __global__ __launch_bounds__(256) void k_row_exp(const float* rows, long long nr
 
 pat_status row_exponents(const float* rows, long long nrows, int K, int srow, int32_t* ex, hipStream_t st) {
   if (nrows == 0) return PAT_OK;
-  if (!rows || !ex || K < 0 || srow < K) return fail(PAT_EINVAL, "row exponents: bad rows");
+  if (!rows || !ex || K < 0 || srow < K || srow % 4 != 0 || (reinterpret_cast<uintptr_t>(rows) & 15u) != 0)
+    return fail(PAT_EINVAL, "row exponents: rows must be 16-byte aligned with a stride of whole 4-float units");
   const long long blocks = (nrows + 3) / 4;
   if (blocks > 0x7fffffffLL) return fail(PAT_EUNSUPPORTED, "row exponents: too many rows");
   k_row_exp<<<dim3((unsigned)blocks), 256, 0, st>>>(rows, nrows, K, srow, ex);
