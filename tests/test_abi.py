@@ -50,9 +50,11 @@ def test_host_only_calls(lib):
     g = _lib.Geometry(32, 32, 16, 64, 1e-4, 1e-4, 1e-4, 2e-8, 1500.0, 0, 0)
     hb, sb = ctypes.c_size_t(), ctypes.c_size_t()
     assert L.pat_H_bytes(ctypes.byref(g), ctypes.byref(hb), ctypes.byref(sb)) == 0
-    # float32 library of a square grid: one slab per distinct m^2 + p^2, two layouts
+    # float32 library of a square grid: one slab per distinct m^2 + p^2, two
+    # layouts, the 16 x 16 Gram block of each slab and one int32 exponent per
+    # row of each layout (for the batched contraction's float16 terms)
     radii = {a * a + b * b for a in range(17) for b in range(a, 17)}
-    assert hb.value >= len(radii) * 16 * 64 * 4 * 2
+    assert hb.value >= len(radii) * (16 * 64 * 4 * 2 + 16 * 16 * 4 + (16 + 64) * 4)
     assert hb.value < (len(radii) + 1) * 16 * 64 * 4 * 2 + (1 << 20)
     # neither a fast transform size nor an even length in [16, 512] (chirp-z)
     for n in (1536, 2048, 8, 14, 201, 514, 1000, 41):
