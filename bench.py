@@ -683,7 +683,7 @@ def serving(args) -> dict:
     def fresh(backend, max_batch, budget=200 << 30):
         srv = Server(backend, hbm_budget=budget, max_batch=max_batch)
         for key, cls in warm.classes.items():   # warm library cache, empty slots
-            cls.cap, cls.pool, cls.ws, cls.active, cls.inflight, cls.bytes_pool = 0, {}, None, [], None, 0
+            cls.cap, cls.pool, cls.ws, cls.active, cls.inflight, cls.bytes_pool = 0, {}, None, [], [], 0
             cls.keep, cls.bytes_keep = [], 0
             srv.classes[key] = cls
         srv.used = sum(c.bytes_lib + c.bytes_ws1 for c in warm.classes.values())

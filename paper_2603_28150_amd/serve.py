@@ -7,7 +7,14 @@ every request carries its own iteration counter and momentum sequence, so
 requests join a class batch at the next iteration boundary after they are
 admitted and leave it the moment their last iteration is done.  Each class
 runs on its own stream, so batches of different classes overlap on the
-device.  The kernel library of every class is built once and cached; a
+device.  A slot's iteration count advances when its iteration is launched,
+so its result is taken (in stream order, right after its last iteration)
+and its row handed on at launch time; a class may therefore have up to
+``depth`` iterations queued, which it does while it is the only class with
+work: the GPU then runs the next iteration while the host handles the last
+one.  With several classes busy their streams keep the device fed, and one
+queued iteration per class lets requests that arrive join the very next
+one.  The kernel library of every class is built once and cached; a
 request is admitted only if the HBM it needs (its slot in the class's state
 pool, plus the library and workspace when the class is new) fits the
 budget, evicting libraries of idle classes when necessary.
@@ -68,13 +75,14 @@ class _Class:
     pool: dict = field(default_factory=dict)   # x, z, d, bad
     ws: object = None
     active: list = field(default_factory=list)  # slot i <-> row i of the pool
-    inflight: object = None                     # (event, n rows stepped)
-    keep: list = field(default_factory=list)    # buffers kept alive until the step ends
+    inflight: list = field(default_factory=list)  # queued iterations: (event, [(request, x, flag)])
+    keep: list = field(default_factory=list)    # (pool, ws, bytes, events): replaced buffers kept
+                                                # alive until the iterations queued before end
     last_used: float = 0.0
     bytes_lib: int = 0
     bytes_ws1: int = 0      # the operator's own one-object workspace (A^T d at admission, step size)
     bytes_pool: int = 0
-    bytes_keep: int = 0     # replaced pools kept alive until the step using them ends
+    bytes_keep: int = 0     # replaced pools kept alive until the iterations using them end
 
 
 class HipBackend:
@@ -91,6 +99,8 @@ class HipBackend:
     def __init__(self, device: int = 0, normal: bool = True):
         self.device = torch.device("cuda", device)
         self.normal = normal
+        self._flags = None   # pinned host ring of the non-finite flags of finished slots
+        self._next_flag = 0
 
     def library_bytes(self, geom, h_dtype) -> int:
         from .op import h_bytes
@@ -162,26 +172,37 @@ class HipBackend:
             else:
                 op.fista_step(pool["d"][:n], pool["x"][:n], pool["z"][:n], betas, taus, lams, nonnegs,
                               nonfinite=pool["bad"][:n], ws=ws)
-            ev = torch.cuda.Event()
-            ev.record(stream)
+
+    def mark(self, stream):
+        ev = torch.cuda.Event()
+        ev.record(stream)
         return ev
 
     def done(self, ev) -> bool:
         return ev.query()
 
     def take_result(self, pool, i, stream):
+        """x_i and its non-finite flag, copied in stream order; the flag lands
+        in pinned host memory and is read only after a later mark() is done
+        (4,096 entries: far more results than can be queued at once)."""
+        if self._flags is None:
+            self._flags = torch.zeros(4096, dtype=torch.int32, pin_memory=True)
+        j = self._next_flag % self._flags.numel()
+        self._next_flag += 1
+        flag = self._flags[j:j + 1]
         with torch.cuda.stream(stream):
             x = pool["x"][i].clone()
-            bad = int(pool["bad"][i].item())
-        return x, bad != 0
+            flag.copy_(pool["bad"][i:i + 1], non_blocking=True)
+        return x, flag
 
 
 class Server:
     def __init__(self, backend=None, hbm_budget: int = 64 << 30, max_batch: int = 16,
-                 clock=time.perf_counter):
+                 clock=time.perf_counter, depth: int = 2):
         self.be = backend if backend is not None else HipBackend()
         self.budget = int(hbm_budget)
         self.max_batch = int(max_batch)
+        self.depth = max(1, int(depth))   # iterations queued per class
         self.clock = clock
         self.classes: dict[tuple, _Class] = {}
         self.pending: list[Request] = []
@@ -210,7 +231,7 @@ class Server:
 
     def _evict_idle(self, need: int, keep_key) -> bool:
         idle = sorted((c for c in self.classes.values()
-                       if c.key != keep_key and not c.active and c.inflight is None
+                       if c.key != keep_key and not c.active and not c.inflight
                        and not any(r.key == c.key for r in self.pending)),
                       key=lambda c: c.last_used)
         for c in idle:
@@ -255,15 +276,15 @@ class Server:
         if new_cap <= cls.cap:
             return False
         need = new_cap * self.be.slot_bytes(cls.op) + self.be.workspace_bytes(cls.op, new_cap)
-        # the old pool stays alive (and charged) until the step that may still
-        # use it has ended, so the new one is charged in full
+        # the old pool stays alive (and charged) until the iterations queued
+        # on it have ended, so the new one is charged in full
         if self.used + need > self.budget and not self._evict_idle(need, cls.key):
             return False
         st = self._stream(cls.key)
         pool, ws = self.be.alloc_pool(cls.op, new_cap, st)
         if cls.cap:
             self.be.copy_rows(cls.pool, pool, len(cls.active), st)
-            cls.keep.append((cls.pool, cls.ws))
+            cls.keep.append((cls.pool, cls.ws, cls.bytes_pool, [ev for ev, _ in cls.inflight]))
         cls.bytes_keep += cls.bytes_pool
         cls.pool, cls.ws, cls.cap = pool, ws, new_cap
         self._charge(need)
@@ -297,60 +318,68 @@ class Server:
         self.pending = still
 
     def _retire(self, cls: _Class):
-        ev, n = cls.inflight
-        if not self.be.done(ev):
-            return
-        cls.inflight = None
-        cls.keep.clear()
-        self._charge(-cls.bytes_keep)
-        cls.bytes_keep = 0
-        st = self._stream(cls.key)
-        finished = []
-        for i in range(n):
-            s = cls.active[i]
-            s.k += 1
-            if s.k >= s.req.niter:
-                finished.append(i)
-        now = self.clock()
-        for i in sorted(finished, reverse=True):
-            s = cls.active[i]
-            x, bad = self.be.take_result(cls.pool, i, st)
-            s.req.x = x
-            s.req.t_done = now
-            s.req.status = "nonfinite" if bad else "done"
-            self.finished.append(s.req)
-            last = len(cls.active) - 1
-            if i != last:
-                self.be.move_row(cls.pool, last, i, st)
-                cls.active[i] = cls.active[last]
-            cls.active.pop()
+        # queued iterations end in order; their finished requests complete
+        now = None
+        while cls.inflight and self.be.done(cls.inflight[0][0]):
+            _, results = cls.inflight.pop(0)
+            now = self.clock() if now is None else now
+            for req, x, flag in results:
+                req.x = x
+                req.t_done = now
+                req.status = "nonfinite" if bool(flag) else "done"
+                self.finished.append(req)
+        still = []
+        for entry in cls.keep:
+            if all(self.be.done(ev) for ev in entry[3]):
+                self._charge(-entry[2])
+                cls.bytes_keep -= entry[2]
+            else:
+                still.append(entry)
+        cls.keep = still
 
-    def _launch(self, cls: _Class):
-        n = len(cls.active)
-        if n == 0 or cls.inflight is not None:
-            return
-        betas, taus, lams, nns = [], [], [], []
-        for s in cls.active:
-            t_next = (1.0 + math.sqrt(1.0 + 4.0 * s.t * s.t)) / 2.0
-            betas.append((s.t - 1.0) / t_next)
-            s.t = t_next
-            taus.append(s.req.tau)
-            lams.append(s.req.lam)
-            nns.append(s.req.nonneg)
-        ev = self.be.step(cls.op, cls.pool, cls.ws, n, betas, taus, lams, nns, self._stream(cls.key))
-        cls.inflight = (ev, n)
-        cls.last_used = self.clock()
-        self.batch_hist[n] = self.batch_hist.get(n, 0) + 1
+    def _launch(self, cls: _Class, depth: int):
+        st = self._stream(cls.key)
+        while cls.active and len(cls.inflight) < depth:
+            n = len(cls.active)
+            betas, taus, lams, nns = [], [], [], []
+            for s in cls.active:
+                t_next = (1.0 + math.sqrt(1.0 + 4.0 * s.t * s.t)) / 2.0
+                betas.append((s.t - 1.0) / t_next)
+                s.t = t_next
+                taus.append(s.req.tau)
+                lams.append(s.req.lam)
+                nns.append(s.req.nonneg)
+            self.be.step(cls.op, cls.pool, cls.ws, n, betas, taus, lams, nns, st)
+            # slots whose last iteration this is: result taken right behind
+            # it on the stream, row handed to the last active slot
+            results = []
+            for i in range(n - 1, -1, -1):
+                s = cls.active[i]
+                s.k += 1
+                if s.k < s.req.niter:
+                    continue
+                x, flag = self.be.take_result(cls.pool, i, st)
+                results.append((s.req, x, flag))
+                last = len(cls.active) - 1
+                if i != last:
+                    self.be.move_row(cls.pool, last, i, st)
+                    cls.active[i] = cls.active[last]
+                cls.active.pop()
+            cls.inflight.append((self.be.mark(st), results))
+            cls.last_used = self.clock()
+            self.batch_hist[n] = self.batch_hist.get(n, 0) + 1
 
     def poll(self) -> bool:
         """One scheduler tick.  Returns True while work remains."""
         for cls in list(self.classes.values()):
-            if cls.inflight is not None:
+            if cls.inflight or cls.keep:
                 self._retire(cls)
         self._admit()
+        working = sum(1 for c in self.classes.values() if c.active or c.inflight)
+        depth = self.depth if working <= 1 else 1
         for cls in self.classes.values():
-            self._launch(cls)
-        busy = any(c.active or c.inflight is not None for c in self.classes.values())
+            self._launch(cls, depth)
+        busy = any(c.active or c.inflight for c in self.classes.values())
         return busy or bool(self.pending)
 
     def run_until_idle(self, sleep: float = 0.0):

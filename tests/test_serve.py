@@ -84,6 +84,9 @@ class CpuBackend:
                 pool["bad"][i] = 1
         return _Ev(self.clock())
 
+    def mark(self, stream):
+        return _Ev(self.clock())
+
     def done(self, ev):
         return True
 
@@ -212,7 +215,7 @@ def test_accounting_charges_workspaces_and_replaced_pools():
     clock = Clock()
     be = WsBackend(clock)
     srv = Server(be, hbm_budget=1 << 40, max_batch=4, clock=clock)
-    reqs = [_req(G1, 30 + i, 3 + i)[0] for i in range(4)]
+    reqs = [_req(G1, 30 + i, 10 + i)[0] for i in range(4)]   # all four overlap: the pool grows to 4
     growth = []
     for r in reqs:
         srv.submit(r)
@@ -241,7 +244,7 @@ def test_class_waiting_for_memory_is_not_rebuilt_every_tick():
     held1 = lib1 + 1500 + slot1 + 1500               # library, own workspace, one slot + its workspace
     budget = held1 + lib2 + 700                       # G2's library fits, with its 1,500-byte workspace not
     srv = Server(be, hbm_budget=budget, max_batch=1, clock=clock)
-    r1, _ = _req(G1, 40, 12)
+    r1, _ = _req(G1, 40, 30)   # still running after the polls below (two iterations queued per poll)
     srv.submit(r1)
     srv.poll()
     r2, _ = _req(G2, 41, 3)
@@ -253,3 +256,51 @@ def test_class_waiting_for_memory_is_not_rebuilt_every_tick():
     srv.run_until_idle()
     assert r1.status == "done" and r2.status == "done"
     assert be.built.count((G2, "f32")) == 2 and srv.peak <= budget
+
+
+class LateBackend(CpuBackend):
+    """CpuBackend whose queued iterations report done only on the second
+    query, so that several stay queued on a class at once."""
+
+    def __init__(self, clock):
+        super().__init__(clock)
+        self.asked = set()
+
+    def done(self, ev):
+        if id(ev) in self.asked:
+            return True
+        self.asked.add(id(ev))
+        return False
+
+
+def test_queued_iterations_respect_the_depth_and_the_results():
+    # a class keeps at most `depth` iterations queued (it queues more than
+    # one only while it is the only class with work); iteration counts advance at
+    # launch, results are taken right after a request's last iteration and
+    # its row handed on, so every result equals the standalone FISTA bit for
+    # bit whatever the depth
+    for depth in (1, 2, 3):
+        clock = Clock()
+        srv = Server(LateBackend(clock), hbm_budget=1 << 40, max_batch=3, clock=clock, depth=depth)
+        reqs = []
+        peak = 0
+
+        def check():
+            nonlocal peak
+            for c in srv.classes.values():
+                assert len(c.inflight) <= depth
+                peak = max(peak, len(c.inflight))
+        for i, (g, n) in enumerate([(G1, 4), (G1, 7), (G2, 5), (G1, 2), (G1, 6)]):
+            r, Hh = _req(g, 300 + 10 * i, n)
+            reqs.append((r, Hh))
+            srv.submit(r)
+            srv.poll()
+            check()
+        while srv.poll():
+            check()
+        assert peak == depth
+        for r, Hh in reqs:
+            assert r.status == "done"
+            assert np.array_equal(r.x, _standalone(Hh, r.d, r.niter, r.tau)), (depth, r.rid)
+        if depth > 1:
+            assert max(srv.batch_hist) > 1
